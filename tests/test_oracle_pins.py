@@ -1,0 +1,292 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+None of these re-derive the oracle's own formulas: they use the paper's
+worked example and its stated uniqueness (Sec. 2.2), counting identities,
+closed-form evolutions, dense matrix exponentials built from Kronecker
+products (scipy), convergence order, and symmetries.
+"""
+import itertools
+
+import numpy as np
+import pytest
+from scipy.linalg import expm
+
+import oracle
+from qaa_inputs import planted_unique_3sat
+
+
+def _satisfies_all(clauses, x):
+    """Proposition P of Sec. 2.2 on assignment x = (x_1..x_n): AND of ORs."""
+    def lit(l):
+        v = abs(l)
+        return x[v - 1] == 1 if l > 0 else x[v - 1] == 0
+    return all(any(lit(l) for l in c) for c in clauses)
+
+
+# --------------------------------------------------------------------------
+# Energy function (Sec. 4.3) and the worked example (Sec. 2.2)
+# --------------------------------------------------------------------------
+
+def test_worked_example_has_exactly_one_solution(worked_example):
+    """The paper states the example formula has only one solution."""
+    n, cl = worked_example["n"], worked_example["clauses"]
+    sols = [x for x in itertools.product((0, 1), repeat=n) if _satisfies_all(cl, x)]
+    assert len(sols) == 1
+    E = oracle.energy(n, cl)
+    zeros = np.nonzero(E == 0)[0]
+    assert zeros.size == 1
+    # x_i is bit (i-1) of z (basis order |q_n ... q_1>)
+    z = int(zeros[0])
+    assert tuple((z >> (i - 1)) & 1 for i in range(1, n + 1)) == sols[0]
+    assert sols[0] == (0, 1, 0, 1, 0, 0) and z == 10
+
+
+def test_worked_example_stated_solution_is_off_by_x1(worked_example):
+    """Reading of the printed solution: it leaves one clause unsatisfied.
+
+    (not x1 or not x2 or not x4) -- the 11th clause -- is false at the
+    printed x = (1,1,0,1,0,0); flipping x1 gives the unique solution.
+    """
+    n, cl = worked_example["n"], worked_example["clauses"]
+    x = worked_example["stated_solution_x1_to_x6"]
+    unsat = [i for i, c in enumerate(cl) if not _satisfies_all([c], x)]
+    assert unsat == [10]
+    z = sum(b << i for i, b in enumerate(x))
+    assert oracle.energy(n, cl)[z] == 1
+
+
+def test_worked_example_has_two_duplicate_clauses(worked_example):
+    """Duplicated clauses are counted once per copy (the example has two)."""
+    cl = [tuple(c) for c in worked_example["clauses"]]
+    dups = len(cl) - len(set(cl))
+    assert dups == 2
+    E = oracle.energy(worked_example["n"], cl)
+    # each copy contributes: sum over z of E is m * 2^{n-3} with m = 27
+    assert int(E.sum()) == 27 * 2 ** (6 - 3) == 216
+
+
+@pytest.mark.parametrize("n,seed", [(6, 1), (9, 2), (12, 3), (14, 4)])
+def test_energy_sum_identity(n, seed):
+    """A clause over 3 distinct variables is false for exactly 2^{n-3} of the
+    2^n assignments, so sum_z E(z) = m 2^{n-3} (and <H_P> of the uniform
+    state is m/8)."""
+    inst = planted_unique_3sat(n, seed)
+    E = oracle.energy(n, inst.clauses)
+    assert int(E.sum()) == inst.m * 2 ** (n - 3)
+    assert E.min() >= 0 and E.max() <= inst.m
+
+
+@pytest.mark.parametrize("n,seed", [(5, 0), (8, 11), (11, 12), (13, 13)])
+def test_planted_solution_is_the_unique_ground_state(n, seed):
+    inst = planted_unique_3sat(n, seed)
+    E = oracle.energy(n, inst.clauses)
+    assert np.count_nonzero(E == 0) == 1
+    assert E[inst.planted] == 0
+
+
+def test_energy_per_clause_indicator():
+    """One clause: E is 1 exactly on the 2^{n-3} assignments falsifying all
+    three literals (enumerated here by building them bit by bit)."""
+    n = 7
+    cl = [[3, -5, 7]]
+    E = oracle.energy(n, cl)
+    falsifying = set()
+    for rest in range(1 << (n - 3)):
+        # place the 4 free bits into positions {0,1,3,5} and fix x3=0, x5=1, x7=0
+        free = [0, 1, 3, 5]
+        z = 0
+        for j, p in enumerate(free):
+            z |= ((rest >> j) & 1) << p
+        z |= 1 << 4          # x5 = 1 makes "-5" false
+        falsifying.add(z)
+    assert set(np.nonzero(E)[0].tolist()) == falsifying
+    assert set(np.unique(E).tolist()) == {0, 1}
+
+
+def test_energy_rejects_out_of_range_literal():
+    with pytest.raises(ValueError):
+        oracle.energy(4, [[1, 2, 5]])
+
+
+# --------------------------------------------------------------------------
+# Evolution pins
+# --------------------------------------------------------------------------
+
+def _basis(n, z0):
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[z0] = 1.0
+    return psi
+
+
+def test_uniform_state_is_stationary_without_clauses():
+    """m = 0: H(s) = (1-s) H_B and the uniform state has H_B eigenvalue 0,
+    so it is left exactly unchanged (the s = 0 ground-state check)."""
+    n = 5
+    psi = oracle.init_uniform(n)
+    ref = psi.copy()
+    oracle.evolve(n, np.zeros((0, 3), np.int32), psi, T=3.7, N=17)
+    assert np.max(np.abs(psi - ref)) < 1e-14
+
+
+@pytest.mark.parametrize("n,z0", [(4, 0), (5, 0b10110), (6, 0b111111)])
+def test_driver_only_closed_form(n, z0):
+    """m = 0 from |z0>: each qubit sees exp(-i Theta (1 - sigma^x)/2) with
+    Theta = sum_k dt (1 - s_k) = T/2, so psi(z) = a^{n-d} b^d, d the Hamming
+    distance to z0, a = (1 + e^{-i Theta})/2, b = (1 - e^{-i Theta})/2."""
+    T, N = 2.9, 23
+    psi = _basis(n, z0)
+    oracle.evolve(n, np.zeros((0, 3), np.int32), psi, T=T, N=N)
+    th = T / 2.0
+    a = (1 + np.exp(-1j * th)) / 2
+    b = (1 - np.exp(-1j * th)) / 2
+    d = np.array([bin(z ^ z0).count("1") for z in range(1 << n)])
+    expect = a ** (n - d) * b ** d
+    assert np.max(np.abs(psi - expect)) < 1e-13
+
+
+@pytest.mark.parametrize("n,seed,k", [(4, 5, 0), (6, 6, 7), (8, 7, 19)])
+def test_one_step_matches_dense_expm(n, seed, k):
+    """Step k equals expm(-i dt/2 s H_P) expm(-i dt (1-s) H_B) expm(-i dt/2 s H_P)
+    with H_B assembled from Kronecker products."""
+    inst = planted_unique_3sat(n, seed)
+    T, N = 10.0, 20
+    rng = np.random.default_rng(seed)
+    psi = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    psi /= np.linalg.norm(psi)
+    U = oracle.dense_strang_step(n, oracle.energy(n, inst.clauses), T, N, k)
+    expect = U @ psi
+    got = psi.copy()
+    oracle.evolve(n, inst.clauses, got, T=T, N=N, k0=k, k1=k + 1)
+    assert np.max(np.abs(got - expect)) < 1e-13
+
+
+def test_dense_h_b_spectrum():
+    """H_B = sum (1 - sigma^x)/2 has eigenvalue j with multiplicity C(n, j)."""
+    n = 5
+    w = np.linalg.eigvalsh(oracle.dense_h_b(n))
+    vals, counts = np.unique(np.round(w).astype(int), return_counts=True)
+    from math import comb
+    assert vals.tolist() == list(range(n + 1))
+    assert counts.tolist() == [comb(n, j) for j in range(n + 1)]
+    assert np.max(np.abs(w - np.round(w))) < 1e-12
+
+
+def test_worked_example_full_evolution_matches_dense_product(worked_example):
+    n, cl = worked_example["n"], worked_example["clauses"]
+    T, N = 10.0, 60
+    E = oracle.energy(n, cl)
+    psi = oracle.init_uniform(n)
+    expect = psi.copy()
+    for k in range(N):
+        expect = oracle.dense_strang_step(n, E, T, N, k) @ expect
+    oracle.evolve(n, cl, psi, T=T, N=N)
+    assert np.max(np.abs(psi - expect)) < 1e-12
+
+
+def _exact_reference(n, E, T, nsub):
+    """Time-ordered propagator from nsub exponential-midpoint substeps."""
+    hb = oracle.dense_h_b(n)
+    hp = np.diag(E.astype(float))
+    psi = np.full(1 << n, 2 ** (-n / 2), dtype=np.complex128)
+    h = T / nsub
+    for j in range(nsub):
+        s = (j + 0.5) / nsub
+        psi = expm(-1j * h * ((1 - s) * hb + s * hp)) @ psi
+    return psi
+
+
+def test_second_order_convergence():
+    """Global error of the Strang steps falls as dt^2: halving dt divides it by ~4."""
+    n = 5
+    inst = planted_unique_3sat(n, 21)
+    E = oracle.energy(n, inst.clauses)
+    T = 4.0
+    ref = _exact_reference(n, E, T, 4096)
+    errs = []
+    for N in (8, 16, 32):
+        psi = oracle.init_uniform(n)
+        oracle.evolve(n, inst.clauses, psi, T=T, N=N)
+        errs.append(np.linalg.norm(psi - ref))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.5 < r1 < 4.6 and 3.5 < r2 < 4.6, (errs, r1, r2)
+
+
+def test_norm_is_conserved():
+    n = 10
+    inst = planted_unique_3sat(n, 3)
+    psi = oracle.init_uniform(n)
+    oracle.evolve(n, inst.clauses, psi, T=10.0, N=1000)
+    obs = oracle.observables(n, inst.clauses, psi)
+    assert abs(obs["norm"] - 1.0) < 1e-12
+
+
+def test_zero_steps_gives_uniform_observables():
+    """No evolution: P_success = degeneracy / 2^n and <H_P> = m/8 exactly."""
+    n = 9
+    inst = planted_unique_3sat(n, 4)
+    psi = oracle.init_uniform(n)
+    oracle.evolve(n, inst.clauses, psi, T=5.0, N=0)
+    obs = oracle.observables(n, inst.clauses, psi)
+    assert obs["degeneracy"] == 1 and obs["e_min"] == 0
+    assert abs(obs["p_success"] - 2.0 ** -n) < 1e-15
+    assert abs(obs["energy"] - inst.m / 8.0) < 1e-12
+
+
+def test_step_ranges_compose():
+    n = 7
+    inst = planted_unique_3sat(n, 8)
+    a = oracle.init_uniform(n)
+    b = oracle.init_uniform(n)
+    oracle.evolve(n, inst.clauses, a, T=6.0, N=40)
+    oracle.evolve(n, inst.clauses, b, T=6.0, N=40, k0=0, k1=13)
+    oracle.evolve(n, inst.clauses, b, T=6.0, N=40, k0=13, k1=40)
+    assert np.array_equal(a, b)
+
+
+def test_gauge_flip_of_one_variable():
+    """Negating variable v in every clause and relabelling z -> z xor 2^{v-1}
+    is a symmetry: H_B is invariant under X_v and the start is uniform."""
+    n, v = 8, 3
+    inst = planted_unique_3sat(n, 9)
+    flipped = inst.clauses.copy()
+    mask = np.abs(flipped) == v
+    flipped[mask] = -flipped[mask]
+    a = oracle.init_uniform(n)
+    b = oracle.init_uniform(n)
+    oracle.evolve(n, inst.clauses, a, T=7.0, N=70)
+    oracle.evolve(n, flipped, b, T=7.0, N=70)
+    z = np.arange(1 << n)
+    assert np.max(np.abs(b - a[z ^ (1 << (v - 1))])) < 1e-13
+    oa = oracle.observables(n, inst.clauses, a)
+    ob = oracle.observables(n, flipped, b)
+    assert abs(oa["p_success"] - ob["p_success"]) < 1e-13
+    assert abs(oa["energy"] - ob["energy"]) < 1e-12
+
+
+def test_variable_relabelling():
+    """Permuting variable labels permutes the bits of z."""
+    n = 7
+    inst = planted_unique_3sat(n, 10)
+    perm = [3, 0, 6, 1, 5, 2, 4]            # old variable i (0-based) -> new perm[i]
+    relab = np.sign(inst.clauses) * (np.array(perm)[np.abs(inst.clauses) - 1] + 1)
+    a = oracle.init_uniform(n)
+    b = oracle.init_uniform(n)
+    oracle.evolve(n, inst.clauses, a, T=5.0, N=50)
+    oracle.evolve(n, relab, b, T=5.0, N=50)
+    z = np.arange(1 << n)
+    znew = np.zeros_like(z)
+    for i, p in enumerate(perm):
+        znew |= ((z >> i) & 1) << p
+    assert np.max(np.abs(b[znew] - a)) < 1e-13
+
+
+def test_slow_sweep_reaches_the_solution(worked_example):
+    """Slow enough evolution ends near the ground state of H_P (Sec. 2.1)."""
+    n, cl = worked_example["n"], worked_example["clauses"]
+    psi = oracle.init_uniform(n)
+    oracle.evolve(n, cl, psi, T=100.0, N=10000)
+    obs = oracle.observables(n, cl, psi)
+    fast = oracle.init_uniform(n)
+    oracle.evolve(n, cl, fast, T=1.0, N=100)
+    assert obs["p_success"] > 0.9
+    assert oracle.observables(n, cl, fast)["p_success"] < obs["p_success"]
