@@ -1,0 +1,206 @@
+#!/usr/bin/env python
+"""Benchmark of the adiabatic 3-SAT evolution on one MI355X.
+
+Workload (the headline configuration): planted unique-solution 3-SAT with
+n = 28 variables (seed 0), linear schedule s = t/T with T = 50 and 5000
+second-order steps (dt = 0.01), complex64 state (2 GiB) with a uint8 energy
+table (256 MiB), uniform start.
+
+One benchmark "step" is one second-order step of the whole path.  The timed
+region is the whole job for K steps: energy table from the clause list,
+uniform initial state, steps 0..K-1 of the 5000-step schedule (with the
+closing half phase), and the FP64 observables.  Inputs (the clause list) are
+resident before timing starts.  value = 2^n * K / seconds (amplitude-steps
+per second).
+
+Also reported on the same JSON line:
+  roofline     -- HBM roofline of the dominant kernel (the fused pass):
+                  algorithmic bytes per launch / event-measured launch time.
+  cpu_baseline -- the CPU oracle timed on a bounded sample of the same job.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "2^n amplitude-steps/s at n=28 (% HBM roofline); batched solves/s; p50/p99"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
+
+# HBM traffic of the pass kernel measured with rocprofv3 --pmc (FETCH_SIZE and
+# WRITE_SIZE runs, scaled by the same counters' reading for a plain copy of
+# known size).  Valid only for the kernel source it was taken on.
+MEASURED_TRAFFIC = {
+    "kernel_source_sha256": None,
+    "bytes_per_launch": None,
+}
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha():
+    path = os.path.join(ROOT, "paper_1103_1399_amd", "csrc", "kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def cpu_baseline(inst, n, T, N, sample_steps):
+    """Oracle on the host cores: energy table once, then `sample_steps` steps;
+    the per-step rate is extrapolated to the full N-step job."""
+    import numpy as np  # noqa: F401
+    import oracle
+    oracle.build()
+    t0 = time.perf_counter()
+    oracle.energy(n, inst.clauses)
+    t_e = time.perf_counter() - t0
+    psi = oracle.init_uniform(n)
+    t0 = time.perf_counter()
+    oracle.evolve(n, inst.clauses, psi, T, N, 0, sample_steps)    # recomputes E inside
+    t_ev = time.perf_counter() - t0
+    t_step = max(1e-9, (t_ev - t_e) / sample_steps)
+    per_step_job = t_step + t_e / N
+    return {
+        "value": (2.0 ** n) / per_step_job,
+        "unit": "amplitude-steps/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": "n=%d seed 0: energy table %.1f s, then %d of the %d steps %.1f s (%.2f s/step); "
+                  "rate = 2^n / (s/step + table/%d), complex128 C oracle with OpenMP"
+                  % (n, t_e, sample_steps, N, t_ev, t_step, N),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000, help="second-order steps timed (default: the full job)")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed warm-up steps")
+    ap.add_argument("--n", type=int, default=28)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=2)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build evolves each state on a single MI355X and has no "
+              "multi-GPU path (asked for --gpus %d, WORLD_SIZE=%d)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1103_1399_amd as qaa
+    from qaa_inputs import planted_unique_3sat
+
+    n, T, N = args.n, 50.0, 5000
+    K, W = args.steps, args.warmup
+    if not (1 <= K <= N) or not (0 <= W <= N):
+        print("--steps must be in [1, %d] and --warmup in [0, %d]" % (N, N), file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    log("generating instance n=%d seed=%d" % (n, args.seed))
+    inst_in = planted_unique_3sat(n, args.seed)
+    lits = inst_in.literals()
+    plan = qaa.qaa_plan_info(n, qaa.QAA_C64)
+
+    # device buffers (allocated before timing)
+    table = torch.empty(1 << n, dtype=torch.uint8, device=dev)
+    amp = torch.empty(1 << n, dtype=torch.complex64, device=dev)
+
+    # warm-up: full path on the same buffers, W steps
+    log("warm-up (%d steps)" % W)
+    h = qaa.Instance(n, lits)
+    qaa.qaa_energy_table(h.handle, table, qaa.QAA_E_U8)
+    st = qaa.make_state(h.handle, amp, table, qaa.QAA_E_U8)
+    qaa.qaa_state_init_uniform(st)
+    if W:
+        qaa.qaa_evolve_range(st, T, N, 0, W)
+    qaa.qaa_observables(st)
+    torch.cuda.synchronize()
+    h.close()
+
+    log("timed: %d steps" % K)
+    qaa.qaa_profile_read(reset=True)
+    qaa.qaa_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = qaa.Instance(n, lits)
+    qaa.qaa_energy_table(h.handle, table, qaa.QAA_E_U8)
+    st = qaa.make_state(h.handle, amp, table, qaa.QAA_E_U8)
+    qaa.qaa_state_init_uniform(st)
+    qaa.qaa_evolve_range(st, T, N, 0, K)
+    obs = qaa.qaa_observables(st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    qaa.qaa_profile_enable(False)
+    prof = qaa.qaa_profile_read(reset=True)
+    secs = t1 - t0
+    log("timed region %.3f s, P_success=%.6f norm=%.9f" % (secs, obs["p_success"], obs["norm"]))
+
+    avg_ms = prof["kernel_ms"] / max(1, prof["launches"])
+    bytes_per_launch = prof["alg_bytes"] / max(1, prof["launches"])
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if prof["launches"] else 0.0
+    traffic = None
+    if MEASURED_TRAFFIC["kernel_source_sha256"] == kernel_source_sha():
+        traffic = MEASURED_TRAFFIC["bytes_per_launch"]
+    roofline = {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "kernel": "qaa pass_kernel (complex64, uint8 table, 2^%d-amplitude tiles)" % plan["tile_bits"],
+        "launches": prof["launches"],
+        "avg_launch_ms": round(avg_ms, 4),
+        "alg_bytes_per_launch": bytes_per_launch,
+    }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, %d steps sample)" % args.cpu_sample_steps)
+        cpu = cpu_baseline(inst_in, n, T, N, args.cpu_sample_steps)
+
+    value = (2.0 ** n) * K / secs
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "amplitude-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": secs / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "planted unique-solution 3-SAT, n=%d qubits (m=%d clauses, seed %d), linear schedule "
+                        "T=%g with %d second-order steps, complex64 state + uint8 energy table, uniform start"
+                        % (n, inst_in.m, args.seed, T, N),
+            "n": n, "m": inst_in.m, "T": T, "schedule_steps": N,
+            "plan": plan,
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "result": {"p_success": obs["p_success"], "energy": obs["energy"], "norm": obs["norm"],
+                   "steps_done": K},
+    }
+    if cpu:
+        out["gpu_over_cpu"] = value / cpu["value"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,252 @@
+/*
+ * qaa.h -- C ABI of the MI355X (gfx950) library that evolves an n-qubit
+ * state vector under the adiabatic 3-SAT Hamiltonian
+ *
+ *     H(s) = (1 - s) H_B + s H_P,   s = t / T            (Sec. 2.1, eq. 1)
+ *     H_B  = sum_i (1 - sigma^x_i) / 2                    (ground state: the
+ *            uniform superposition of Sec. 2.1)
+ *     H_P |z> = E(z) |z>,  E(z) = number of clauses unsatisfied by z
+ *                                                         (Sec. 4.3)
+ *
+ * with N second-order split steps: step k (0 <= k < N) evaluates the
+ * schedule at the midpoint s_k = (k + 1/2)/N, dt = T/N, and applies
+ *     exp(-i dt/2 s_k H_P) exp(-i dt (1 - s_k) H_B) exp(-i dt/2 s_k H_P).
+ * The paper does not name its integrator; this splitting is the build's
+ * reading and is what the test oracle computes.
+ *
+ * Conventions
+ *  - Literals are DIMACS style (Sec. 2.2 K-SAT definition): +v is x_v,
+ *    -v is "not x_v", 1 <= v <= n; three distinct variables per clause.
+ *  - Variable x_i lives on qubit q_i = bit (i-1) of the basis index z
+ *    (basis order |q_n ... q_1> of Sec. 2.1).
+ *  - Amplitudes: 2^n complex numbers in device memory, interleaved
+ *    (re, im), index z; complex64 (float pairs) or complex128.  Amplitude
+ *    and energy-table buffers must be 16-byte aligned and live on the
+ *    calling thread's current HIP device.
+ *  - Every device pointer is caller-owned: the library never frees or
+ *    reallocates a caller buffer.  Buffers must stay alive until the work
+ *    queued on the stream has finished.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls are asynchronous on it unless stated otherwise.
+ *  - Errors: every call returns a qaa_status; nothing throws or aborts
+ *    across the ABI.  qaa_last_error() returns a thread-local message for
+ *    the last failing call of the calling thread.
+ */
+#ifndef QAA_H
+#define QAA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum qaa_status {
+    QAA_OK = 0,
+    QAA_ERR_INVALID_ARG = 1,   /* argument outside the documented domain */
+    QAA_ERR_UNSUPPORTED = 2,   /* valid but not supported (e.g. E_max > 255 with a uint8 table) */
+    QAA_ERR_OUT_OF_MEMORY = 3, /* a library-owned allocation failed / request can never fit */
+    QAA_ERR_DEVICE = 4,        /* a HIP runtime call or kernel launch failed */
+    QAA_ERR_NOT_READY = 5,     /* a prerequisite call has not run (e.g. no energy table yet) */
+    QAA_ERR_INTERNAL = 6
+} qaa_status;
+
+typedef enum qaa_dtype {
+    QAA_C64 = 0,    /* complex64: float re, float im */
+    QAA_C128 = 1    /* complex128: double re, double im */
+} qaa_dtype;
+
+typedef enum qaa_etype {
+    QAA_E_U8 = 0,   /* energy table entries as uint8 (requires E_max <= 255) */
+    QAA_E_U16 = 1   /* energy table entries as uint16 (requires E_max <= 1023 for evolution) */
+} qaa_etype;
+
+/* Largest supported qubit count (2^34 complex64 = 128 GiB). */
+#define QAA_MAX_QUBITS 34
+
+/* ---------------------------------------------------------------------
+ * Instances (Sec. 2.2 K-SAT definition, k = 3).
+ * ------------------------------------------------------------------- */
+
+typedef struct qaa_instance qaa_instance;
+
+/*
+ * Create an instance from a clause list.
+ *   n    : number of variables / qubits, 1 <= n <= QAA_MAX_QUBITS.
+ *   m    : number of clauses, 0 <= m <= 65535.
+ *   lits : host array of 3*m signed literals (copied; may be freed after).
+ *   out  : receives a host-owned handle; release with qaa_instance_destroy.
+ * QAA_ERR_INVALID_ARG if n or m is out of range, a literal is 0 or |v| > n,
+ * a clause repeats a variable, lits is NULL with m > 0, or out is NULL.
+ * Duplicate clauses are allowed and counted once per copy.
+ */
+qaa_status qaa_instance_create(int32_t n, int32_t m, const int32_t *lits, qaa_instance **out);
+
+/* Release an instance (NULL is ignored).  Frees the library-owned device
+ * copy of the clause list; no queued work may still use the instance. */
+void qaa_instance_destroy(qaa_instance *inst);
+
+/*
+ * Query an instance.  Any output pointer may be NULL.  e_min, e_max and
+ * degeneracy (number of z with E(z) = e_min: the ground-manifold size of
+ * Sec. 2.1) are -1 until qaa_energy_table has run once for the instance.
+ */
+qaa_status qaa_instance_info(const qaa_instance *inst, int32_t *n, int32_t *m,
+                             int32_t *e_min, int32_t *e_max, int64_t *degeneracy);
+
+/* ---------------------------------------------------------------------
+ * Energy table: E(z) for all 2^n basis states (Sec. 4.3; the paper's GPU
+ * kernel gives each thread basis states to score, Sec. 4.3 results).
+ * ------------------------------------------------------------------- */
+
+/*
+ * Fill d_table[z] = E(z), z = 0 .. 2^n - 1, bit-exact.
+ *   d_table : device buffer of 2^n uint8 (QAA_E_U8) or uint16 (QAA_E_U16).
+ * SYNCHRONOUS: waits for the stream, then records e_min, e_max and the
+ * degeneracy on the instance.  QAA_ERR_UNSUPPORTED if etype is QAA_E_U8 and
+ * some E(z) > 255 (the table is then incomplete; use QAA_E_U16).
+ */
+qaa_status qaa_energy_table(qaa_instance *inst, void *d_table, qaa_etype etype, void *stream);
+
+/* ---------------------------------------------------------------------
+ * States.
+ * ------------------------------------------------------------------- */
+
+typedef struct qaa_state {
+    const qaa_instance *inst;  /* instance the state evolves under */
+    void *amp;                 /* device, 2^n interleaved complex amplitudes */
+    qaa_dtype dtype;           /* QAA_C64 or QAA_C128 */
+    const void *table;         /* device energy table filled by qaa_energy_table */
+    qaa_etype etype;           /* element type of table */
+} qaa_state;
+
+/* psi(z) = 2^{-n/2}: the ground state of H_B (Sec. 2.1).  Needs only amp. */
+qaa_status qaa_state_init_uniform(const qaa_state *st, void *stream);
+
+/* psi = |z0>, a computational basis state (0 <= z0 < 2^n). */
+qaa_status qaa_state_init_basis(const qaa_state *st, uint64_t z0, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Evolution.
+ * ------------------------------------------------------------------- */
+
+typedef enum qaa_schedule_kind {
+    QAA_SCHED_LINEAR = 0       /* s = t/T (Sec. 2.1, eq. 1) */
+} qaa_schedule_kind;
+
+typedef struct qaa_schedule {
+    int32_t kind;              /* qaa_schedule_kind */
+} qaa_schedule;
+
+/*
+ * Apply all `steps` second-order steps of total time T to st->amp in place
+ * (equivalent to qaa_evolve_range with k0 = 0, k1 = steps).
+ *   sched : NULL or {QAA_SCHED_LINEAR}.
+ * steps == 0 is a no-op.  QAA_ERR_INVALID_ARG for T < 0, steps < 0, a NaN
+ * T, or a state without amp/table/inst.  QAA_ERR_UNSUPPORTED if the
+ * instance's E_max exceeds what the table type allows.  Asynchronous.
+ */
+qaa_status qaa_evolve(const qaa_state *st, const qaa_schedule *sched, double T,
+                      int64_t steps, void *stream);
+
+/*
+ * Apply steps k0 .. k1-1 (0 <= k0 <= k1 <= steps) of the `steps`-step
+ * evolution over total time T.  The state after range [k0, k1) is the state
+ * after step k1 - 1 (both half phases applied), so
+ * evolve_range(0, K); evolve_range(K, N) equals evolve(N) up to FP32 rounding
+ * (the uninterrupted call merges the two half phases at K).  Asynchronous.
+ */
+qaa_status qaa_evolve_range(const qaa_state *st, const qaa_schedule *sched, double T,
+                            int64_t steps, int64_t k0, int64_t k1, void *stream);
+
+/*
+ * Evolve `count` independent states in one launch per pass.  states[i],
+ * T[i] and steps[i] (host arrays) as in qaa_evolve; the states may have
+ * different n.  Each result equals what qaa_evolve gives for that state
+ * alone, up to FP32 rounding (same kernels, same plan per n).  Asynchronous.
+ */
+qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, const double *T,
+                            const int64_t *steps, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Observables (Sec. 2.1: the result is read from the weight on the ground
+ * manifold of H_P).  FP64 accumulation, deterministic order.
+ * ------------------------------------------------------------------- */
+
+typedef struct qaa_obs {
+    double norm;          /* sum_z |psi(z)|^2 */
+    double energy;        /* <H_P> = sum_z E(z) |psi(z)|^2 */
+    double p_success;     /* sum over z with E(z) = e_min of |psi(z)|^2 */
+    int32_t e_min;        /* minimum of E */
+    int64_t degeneracy;   /* number of z with E(z) = e_min */
+} qaa_obs;
+
+/* SYNCHRONOUS: enqueues the reduction on the stream, waits for it, and
+ * fills *out.  QAA_ERR_NOT_READY if the instance has no energy table yet. */
+qaa_status qaa_observables(const qaa_state *st, qaa_obs *out, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Plans (how a step is split into HBM passes) -- introspection.
+ * ------------------------------------------------------------------- */
+
+/*
+ * Describe the pass plan used for n qubits of the given dtype:
+ *   *tile_bits      : qubits held per workgroup tile (0 = whole state in one
+ *                     workgroup, all steps in one launch)
+ *   *sets           : qubit sets the n qubits are split into
+ *   *passes_per_step: HBM read+write passes per step in steady state
+ */
+qaa_status qaa_plan_info(int32_t n, qaa_dtype dtype, int32_t *tile_bits, int32_t *sets,
+                         int32_t *passes_per_step);
+
+/*
+ * Diagnostic: the pass descriptors qaa_evolve_range would launch for an
+ * n-qubit state (energies up to emax) over steps k0..k1-1 of `steps`.
+ * Writes up to `capacity` descriptors of *desc_bytes bytes each into the
+ * host buffer `out` (may be NULL to query the count) and the total number
+ * into *count (0 when the whole state is one workgroup tile).  The record
+ * layout is the library's internal pass descriptor and may change between
+ * versions; it exists so that host-side tests can replay the index maps.
+ */
+qaa_status qaa_debug_pass_descs(int32_t n, qaa_dtype dtype, int32_t emax, double T, int64_t steps,
+                                int64_t k0, int64_t k1, void *out, int32_t capacity, int32_t *count,
+                                int32_t *desc_bytes);
+
+/* ---------------------------------------------------------------------
+ * Kernel timing (tracing).
+ * ------------------------------------------------------------------- */
+
+/*
+ * While enabled (on != 0), every pass-kernel launch made by the calling
+ * process is bracketed by two HIP events recorded on the launch's own
+ * stream.  Enabling adds one event pair per launch; it does not change
+ * results.  Disabled by default.
+ */
+qaa_status qaa_profile_enable(int32_t on);
+
+typedef struct qaa_profile {
+    int64_t launches;       /* pass launches recorded since the last reset */
+    double kernel_ms;       /* sum of their event-measured durations */
+    double min_ms, max_ms;  /* shortest / longest single launch */
+    double alg_bytes;       /* algorithmic HBM bytes of those launches:
+                               2^n * (2 * sizeof(amplitude) + sizeof(energy)
+                               if the pass applies the phase) each */
+} qaa_profile;
+
+/* SYNCHRONOUS: waits for the recorded events, fills *out, and clears the
+ * record when reset != 0. */
+qaa_status qaa_profile_read(qaa_profile *out, int32_t reset);
+
+/* ---------------------------------------------------------------------
+ * Errors and version.
+ * ------------------------------------------------------------------- */
+
+const char *qaa_status_str(qaa_status s);  /* static string, never NULL */
+const char *qaa_last_error(void);          /* thread-local; "" if none */
+int32_t qaa_version(void);                 /* major*10000 + minor*100 + patch */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QAA_H */

@@ -9,7 +9,7 @@ basis states); this module is ctypes marshalling plus two numpy helpers that
 build dense matrices for the small-n pins.  Every function states which part
 of the paper it follows:
 
-* energy           -- Sec. 4.3: E(z) = number of clauses the assignment z
+* energy, energy_at -- Sec. 4.3: E(z) = number of clauses the assignment z
                       leaves unsatisfied; literals as in Sec. 2.2; x_i is bit
                       (i-1) of z (basis order |q_n ... q_1> of Sec. 2.1).
 * init_uniform     -- Sec. 2.1: uniform superposition, the ground state of
@@ -63,6 +63,9 @@ def _load():
             i64p = ctypes.POINTER(ctypes.c_int64)
             lib.oracle_energy.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p]
             lib.oracle_energy.restype = ctypes.c_int
+            lib.oracle_energy_at.argtypes = [ctypes.c_int, ctypes.c_int, i32p, ctypes.POINTER(ctypes.c_uint64),
+                                             ctypes.c_int64, i32p]
+            lib.oracle_energy_at.restype = ctypes.c_int
             lib.oracle_init_uniform.argtypes = [ctypes.c_int, f64p]
             lib.oracle_init_uniform.restype = None
             lib.oracle_evolve.argtypes = [ctypes.c_int, ctypes.c_int, i32p, f64p, ctypes.c_double,
@@ -94,6 +97,18 @@ def energy(n: int, clauses) -> np.ndarray:
     lits = _lits(clauses)
     out = np.empty(1 << n, dtype=np.int32)
     rc = _load().oracle_energy(n, lits.shape[0], _ptr(lits, ctypes.c_int32), _ptr(out, ctypes.c_int32))
+    if rc != 0:
+        raise ValueError("literal out of range")
+    return out
+
+
+def energy_at(n: int, clauses, zs) -> np.ndarray:
+    """E(z) for the given basis states only (Sec. 4.3 energy function)."""
+    lits = _lits(clauses)
+    z = np.ascontiguousarray(np.asarray(zs, dtype=np.uint64))
+    out = np.empty(z.size, dtype=np.int32)
+    rc = _load().oracle_energy_at(n, lits.shape[0], _ptr(lits, ctypes.c_int32), _ptr(z, ctypes.c_uint64),
+                                  z.size, _ptr(out, ctypes.c_int32))
     if rc != 0:
         raise ValueError("literal out of range")
     return out

@@ -1,0 +1,321 @@
+"""Python binding of libqaa (include/qaa.h): argument marshalling only.
+
+Every step of the evolution runs in the library's gfx950 kernels; this module
+converts arguments (PyTorch tensors give device pointers and streams) and
+raises on non-OK status codes.  Importing it without the built library
+raises ImportError: there is no fallback path.
+
+The C-ABI names are exported unchanged (``qaa_instance_create``,
+``qaa_energy_table``, ``qaa_state_init_uniform``, ``qaa_evolve``,
+``qaa_evolve_range``, ``qaa_evolve_batch``, ``qaa_observables``, ...), plus
+small conveniences (``Instance``, ``State``) built only from those calls.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqaa.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        "libqaa.so is not built (expected at %s); run `python -c \"import __graft_entry__ as g; g.build()\"` "
+        "or `python paper_1103_1399_amd/build.py`" % LIB_PATH)
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# status codes (qaa_status)
+QAA_OK = 0
+QAA_ERR_INVALID_ARG = 1
+QAA_ERR_UNSUPPORTED = 2
+QAA_ERR_OUT_OF_MEMORY = 3
+QAA_ERR_DEVICE = 4
+QAA_ERR_NOT_READY = 5
+QAA_ERR_INTERNAL = 6
+# dtypes / table element types
+QAA_C64 = 0
+QAA_C128 = 1
+QAA_E_U8 = 0
+QAA_E_U16 = 1
+QAA_SCHED_LINEAR = 0
+QAA_MAX_QUBITS = 34
+
+
+class QaaError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__("%s: %s (%s)" % (where, msg, _lib.qaa_status_str(status).decode()))
+        self.status = status
+
+
+class qaa_state(ctypes.Structure):
+    _fields_ = [("inst", ctypes.c_void_p), ("amp", ctypes.c_void_p), ("dtype", ctypes.c_int),
+                ("table", ctypes.c_void_p), ("etype", ctypes.c_int)]
+
+
+class qaa_schedule(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32)]
+
+
+class qaa_obs(ctypes.Structure):
+    _fields_ = [("norm", ctypes.c_double), ("energy", ctypes.c_double), ("p_success", ctypes.c_double),
+                ("e_min", ctypes.c_int32), ("degeneracy", ctypes.c_int64)]
+
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_f64p = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+_st = ctypes.c_int
+
+_SIGS = {
+    "qaa_instance_create": (_st, [ctypes.c_int32, ctypes.c_int32, _i32p, ctypes.POINTER(_vp)]),
+    "qaa_instance_destroy": (None, [_vp]),
+    "qaa_instance_info": (_st, [_vp, _i32p, _i32p, _i32p, _i32p, _i64p]),
+    "qaa_energy_table": (_st, [_vp, _vp, ctypes.c_int, _vp]),
+    "qaa_state_init_uniform": (_st, [ctypes.POINTER(qaa_state), _vp]),
+    "qaa_state_init_basis": (_st, [ctypes.POINTER(qaa_state), ctypes.c_uint64, _vp]),
+    "qaa_evolve": (_st, [ctypes.POINTER(qaa_state), ctypes.POINTER(qaa_schedule), ctypes.c_double,
+                         ctypes.c_int64, _vp]),
+    "qaa_evolve_range": (_st, [ctypes.POINTER(qaa_state), ctypes.POINTER(qaa_schedule), ctypes.c_double,
+                               ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _vp]),
+    "qaa_evolve_batch": (_st, [ctypes.c_int32, ctypes.POINTER(qaa_state), _f64p, _i64p, _vp]),
+    "qaa_observables": (_st, [ctypes.POINTER(qaa_state), ctypes.POINTER(qaa_obs), _vp]),
+    "qaa_plan_info": (_st, [ctypes.c_int32, ctypes.c_int, _i32p, _i32p, _i32p]),
+    "qaa_debug_pass_descs": (_st, [ctypes.c_int32, ctypes.c_int, ctypes.c_int32, ctypes.c_double, ctypes.c_int64,
+                                   ctypes.c_int64, ctypes.c_int64, _vp, ctypes.c_int32, _i32p, _i32p]),
+    "qaa_profile_enable": (_st, [ctypes.c_int32]),
+    "qaa_profile_read": (_st, [ctypes.c_void_p, ctypes.c_int32]),
+    "qaa_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "qaa_last_error": (ctypes.c_char_p, []),
+    "qaa_version": (ctypes.c_int32, []),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_SIGS)
+
+
+def _check(status: int, where: str) -> None:
+    if status != QAA_OK:
+        raise QaaError(status, where, _lib.qaa_last_error().decode())
+
+
+def _stream_ptr(stream) -> int | None:
+    """hipStream_t of a torch stream (None -> torch's current stream)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) or None
+
+
+# ---------------------------------------------------------------------------
+# C-ABI calls, same names
+# ---------------------------------------------------------------------------
+
+def qaa_instance_create(n: int, lits) -> int:
+    import numpy as np
+    arr = np.ascontiguousarray(np.asarray(lits, dtype=np.int32).reshape(-1))
+    if arr.size % 3:
+        raise ValueError("literal count must be a multiple of 3")
+    out = _vp()
+    _check(_lib.qaa_instance_create(int(n), arr.size // 3, arr.ctypes.data_as(_i32p), ctypes.byref(out)),
+           "qaa_instance_create")
+    return out.value
+
+
+def qaa_instance_destroy(handle: int) -> None:
+    _lib.qaa_instance_destroy(handle)
+
+
+def qaa_instance_info(handle: int) -> dict:
+    n, m, emin, emax = (ctypes.c_int32() for _ in range(4))
+    deg = ctypes.c_int64()
+    _check(_lib.qaa_instance_info(handle, ctypes.byref(n), ctypes.byref(m), ctypes.byref(emin),
+                                  ctypes.byref(emax), ctypes.byref(deg)), "qaa_instance_info")
+    return {"n": n.value, "m": m.value, "e_min": emin.value, "e_max": emax.value, "degeneracy": deg.value}
+
+
+def qaa_energy_table(handle: int, table, etype: int, stream=None) -> None:
+    _check(_lib.qaa_energy_table(handle, table.data_ptr(), int(etype), _stream_ptr(stream)), "qaa_energy_table")
+
+
+def make_state(handle: int, amp, table=None, etype: int | None = None) -> qaa_state:
+    import torch
+    if amp.dtype == torch.complex64:
+        dt = QAA_C64
+    elif amp.dtype == torch.complex128:
+        dt = QAA_C128
+    else:
+        raise TypeError("amplitudes must be complex64 or complex128")
+    if not amp.is_contiguous():
+        raise ValueError("amplitudes must be contiguous")
+    if table is not None:
+        if etype is None:
+            etype = QAA_E_U8 if table.dtype == torch.uint8 else QAA_E_U16
+        tp = table.data_ptr()
+    else:
+        tp, etype = None, QAA_E_U8
+    return qaa_state(handle, amp.data_ptr(), dt, tp, int(etype))
+
+
+def qaa_state_init_uniform(state: qaa_state, stream=None) -> None:
+    _check(_lib.qaa_state_init_uniform(ctypes.byref(state), _stream_ptr(stream)), "qaa_state_init_uniform")
+
+
+def qaa_state_init_basis(state: qaa_state, z0: int, stream=None) -> None:
+    _check(_lib.qaa_state_init_basis(ctypes.byref(state), int(z0), _stream_ptr(stream)), "qaa_state_init_basis")
+
+
+def qaa_evolve(state: qaa_state, T: float, steps: int, stream=None) -> None:
+    sched = qaa_schedule(QAA_SCHED_LINEAR)
+    _check(_lib.qaa_evolve(ctypes.byref(state), ctypes.byref(sched), float(T), int(steps), _stream_ptr(stream)),
+           "qaa_evolve")
+
+
+def qaa_evolve_range(state: qaa_state, T: float, steps: int, k0: int, k1: int, stream=None) -> None:
+    sched = qaa_schedule(QAA_SCHED_LINEAR)
+    _check(_lib.qaa_evolve_range(ctypes.byref(state), ctypes.byref(sched), float(T), int(steps), int(k0), int(k1),
+                                 _stream_ptr(stream)), "qaa_evolve_range")
+
+
+def qaa_evolve_batch(states, Ts, steps, stream=None) -> None:
+    cnt = len(states)
+    arr = (qaa_state * cnt)(*states)
+    t_arr = (ctypes.c_double * cnt)(*[float(t) for t in Ts])
+    s_arr = (ctypes.c_int64 * cnt)(*[int(s) for s in steps])
+    _check(_lib.qaa_evolve_batch(cnt, arr, t_arr, s_arr, _stream_ptr(stream)), "qaa_evolve_batch")
+
+
+def qaa_observables(state: qaa_state, stream=None) -> dict:
+    out = qaa_obs()
+    _check(_lib.qaa_observables(ctypes.byref(state), ctypes.byref(out), _stream_ptr(stream)), "qaa_observables")
+    return {"norm": out.norm, "energy": out.energy, "p_success": out.p_success, "e_min": out.e_min,
+            "degeneracy": out.degeneracy}
+
+
+def qaa_plan_info(n: int, dtype: int = QAA_C64) -> dict:
+    tb, sets, pps = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.qaa_plan_info(int(n), int(dtype), ctypes.byref(tb), ctypes.byref(sets), ctypes.byref(pps)),
+           "qaa_plan_info")
+    return {"tile_bits": tb.value, "sets": sets.value, "passes_per_step": pps.value}
+
+
+class PassDesc(ctypes.Structure):
+    """Mirror of the library's internal pass descriptor (diagnostics only)."""
+    _fields_ = [("n", ctypes.c_int32), ("n_rest", ctypes.c_int32), ("n_res", ctypes.c_int32),
+                ("phase_at", ctypes.c_int32), ("emax", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("cm1A", ctypes.c_double), ("sA", ctypes.c_double), ("cm1B", ctypes.c_double),
+                ("sB", ctypes.c_double), ("phi", ctypes.c_double), ("gphase", ctypes.c_double),
+                ("acc_in", ctypes.c_void_p), ("acc_out", ctypes.c_void_p), ("acc_zero", ctypes.c_void_p),
+                ("tile_pos", ctypes.c_uint8 * 16), ("rest_pos", ctypes.c_uint8 * 40),
+                ("gbits", (ctypes.c_uint8 * 8) * 12), ("tpos", (ctypes.c_uint8 * 16) * 12),
+                ("maskA", ctypes.c_uint8 * 12), ("maskB", ctypes.c_uint8 * 12)]
+
+
+def qaa_debug_pass_descs(n: int, dtype: int, emax: int, T: float, steps: int, k0: int, k1: int):
+    count, size = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.qaa_debug_pass_descs(n, dtype, emax, T, steps, k0, k1, None, 0, ctypes.byref(count),
+                                     ctypes.byref(size)), "qaa_debug_pass_descs")
+    if size.value != ctypes.sizeof(PassDesc):
+        raise RuntimeError("pass descriptor layout mismatch (%d vs %d bytes)" % (size.value, ctypes.sizeof(PassDesc)))
+    arr = (PassDesc * max(1, count.value))()
+    _check(_lib.qaa_debug_pass_descs(n, dtype, emax, T, steps, k0, k1, arr, count.value, ctypes.byref(count),
+                                     ctypes.byref(size)), "qaa_debug_pass_descs")
+    return list(arr)[:count.value]
+
+
+class qaa_profile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("kernel_ms", ctypes.c_double), ("min_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("alg_bytes", ctypes.c_double)]
+
+
+def qaa_profile_enable(on: bool = True) -> None:
+    _check(_lib.qaa_profile_enable(1 if on else 0), "qaa_profile_enable")
+
+
+def qaa_profile_read(reset: bool = True) -> dict:
+    out = qaa_profile()
+    _check(_lib.qaa_profile_read(ctypes.byref(out), 1 if reset else 0), "qaa_profile_read")
+    return {"launches": out.launches, "kernel_ms": out.kernel_ms, "min_ms": out.min_ms, "max_ms": out.max_ms,
+            "alg_bytes": out.alg_bytes}
+
+
+def qaa_status_str(status: int) -> str:
+    return _lib.qaa_status_str(int(status)).decode()
+
+
+def qaa_last_error() -> str:
+    return _lib.qaa_last_error().decode()
+
+
+def qaa_version() -> int:
+    return int(_lib.qaa_version())
+
+
+# ---------------------------------------------------------------------------
+# Conveniences built from the calls above
+# ---------------------------------------------------------------------------
+
+class Instance:
+    """Owns a qaa_instance handle."""
+
+    def __init__(self, n: int, clauses):
+        self.n = int(n)
+        self.handle = qaa_instance_create(n, clauses)
+
+    def info(self) -> dict:
+        return qaa_instance_info(self.handle)
+
+    def energy_table(self, device="cuda", etype: int = QAA_E_U8, stream=None):
+        import torch
+        dt = torch.uint8 if etype == QAA_E_U8 else torch.int16
+        table = torch.empty(1 << self.n, dtype=dt, device=device)
+        qaa_energy_table(self.handle, table, etype, stream)
+        return table
+
+    def close(self):
+        if self.handle:
+            qaa_instance_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class State:
+    """A device state vector bound to an instance and its energy table."""
+
+    def __init__(self, inst: Instance, table, dtype=None, device="cuda", amp=None):
+        import torch
+        self.inst = inst
+        self.table = table
+        if amp is None:
+            amp = torch.empty(1 << inst.n, dtype=dtype or torch.complex64, device=device)
+        self.amp = amp
+        etype = QAA_E_U8 if table.dtype == torch.uint8 else QAA_E_U16
+        self.c = make_state(inst.handle, amp, table, etype)
+
+    def init_uniform(self, stream=None):
+        qaa_state_init_uniform(self.c, stream)
+        return self
+
+    def init_basis(self, z0: int, stream=None):
+        qaa_state_init_basis(self.c, z0, stream)
+        return self
+
+    def evolve(self, T: float, steps: int, stream=None):
+        qaa_evolve(self.c, T, steps, stream)
+        return self
+
+    def evolve_range(self, T: float, steps: int, k0: int, k1: int, stream=None):
+        qaa_evolve_range(self.c, T, steps, k0, k1, stream)
+        return self
+
+    def observables(self, stream=None) -> dict:
+        return qaa_observables(self.c, stream)

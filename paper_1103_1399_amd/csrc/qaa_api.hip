@@ -1,0 +1,797 @@
+// qaa_api.hip -- host runtime behind include/qaa.h: argument validation,
+// instance encoding, the pass planner, the per-step pass sequence and the
+// per-device scratch used by reductions.
+#include "qaa.h"
+#include "qaa_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using namespace qaa;
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+namespace {
+
+thread_local std::string g_last_error;
+
+qaa_status fail(qaa_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+qaa_status ok()
+{
+    g_last_error.clear();
+    return QAA_OK;
+}
+
+#define QAA_HIP(call)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(QAA_ERR_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));    \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Per-device scratch (reduction partials and small counters).
+// ---------------------------------------------------------------------------
+struct DeviceCtx {
+    std::mutex mu;
+    bool ready = false;
+    uint32_t *stats = nullptr;              // [4] energy min / max / overflow
+    unsigned long long *count = nullptr;    // [1]
+    double *partials = nullptr;             // [2048 * 3]
+    double *obs_out = nullptr;              // [4]
+    void *host_pinned = nullptr;            // 256 B staging for readbacks
+};
+
+std::mutex g_dev_mu;
+std::map<int, std::unique_ptr<DeviceCtx>> g_devs;
+
+qaa_status device_ctx(DeviceCtx **out)
+{
+    int dev = 0;
+    QAA_HIP(hipGetDevice(&dev));
+    DeviceCtx *ctx;
+    {
+        std::lock_guard<std::mutex> lk(g_dev_mu);
+        auto &p = g_devs[dev];
+        if (!p) p.reset(new DeviceCtx());
+        ctx = p.get();
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!ctx->ready) {
+        char *base = nullptr;
+        const size_t bytes = 256 + 2048 * 3 * sizeof(double) + 64;
+        QAA_HIP(hipMalloc(reinterpret_cast<void **>(&base), bytes));
+        ctx->stats = reinterpret_cast<uint32_t *>(base);
+        ctx->count = reinterpret_cast<unsigned long long *>(base + 64);
+        ctx->obs_out = reinterpret_cast<double *>(base + 128);
+        ctx->partials = reinterpret_cast<double *>(base + 256);
+        QAA_HIP(hipHostMalloc(&ctx->host_pinned, 256, hipHostMallocDefault));
+        ctx->ready = true;
+    }
+    *out = ctx;
+    return QAA_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Instances
+// ---------------------------------------------------------------------------
+struct qaa_instance {
+    int32_t n = 0;
+    int32_t m = 0;
+    std::vector<int32_t> lits;
+    std::vector<ClauseRec> recs;
+    std::mutex mu;
+    std::map<int, ClauseRec *> dev_recs;   // device copy per device
+    int32_t e_min = -1, e_max = -1;
+    int64_t degeneracy = -1;
+};
+
+namespace {
+
+// Encode one clause: violated iff every literal is false, i.e. iff
+// x_v = 0 for each positive literal and x_v = 1 for each negated one
+// (Sec. 2.2).  mask = the three variable bits, pat = the negated ones.
+ClauseRec encode_clause(const int32_t *c)
+{
+    uint64_t mask = 0, pat = 0;
+    for (int j = 0; j < 3; ++j) {
+        const int32_t v = c[j] > 0 ? c[j] : -c[j];
+        const uint64_t bit = 1ull << (v - 1);
+        mask |= bit;
+        if (c[j] < 0) pat |= bit;
+    }
+    ClauseRec r;
+    r.mhi = mask & ~7ull;
+    r.phi = pat & ~7ull;
+    r.lo_a = r.lo_b = 0;
+    for (uint64_t j = 0; j < 8; ++j) {
+        const uint64_t hit = ((j & mask & 7ull) == (pat & 7ull)) ? 1ull : 0ull;
+        if (j < 4)
+            r.lo_a |= hit << (16 * j);
+        else
+            r.lo_b |= hit << (16 * (j - 4));
+    }
+    return r;
+}
+
+}  // namespace
+
+extern "C" qaa_status qaa_instance_create(int32_t n, int32_t m, const int32_t *lits, qaa_instance **out)
+{
+    if (!out) return fail(QAA_ERR_INVALID_ARG, "qaa_instance_create: out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > QAA_MAX_QUBITS)
+        return fail(QAA_ERR_INVALID_ARG, "qaa_instance_create: n=%d outside [1, %d]", n, QAA_MAX_QUBITS);
+    if (m < 0 || m > 65535) return fail(QAA_ERR_INVALID_ARG, "qaa_instance_create: m=%d outside [0, 65535]", m);
+    if (m > 0 && !lits) return fail(QAA_ERR_INVALID_ARG, "qaa_instance_create: lits is NULL with m=%d", m);
+    for (int c = 0; c < m; ++c) {
+        int32_t vs[3];
+        for (int j = 0; j < 3; ++j) {
+            const int32_t l = lits[3 * c + j];
+            const int32_t v = l > 0 ? l : -l;
+            if (l == 0 || v > n)
+                return fail(QAA_ERR_INVALID_ARG, "qaa_instance_create: clause %d literal %d out of range for n=%d", c,
+                            l, n);
+            vs[j] = v;
+        }
+        if (vs[0] == vs[1] || vs[0] == vs[2] || vs[1] == vs[2])
+            return fail(QAA_ERR_INVALID_ARG, "qaa_instance_create: clause %d repeats a variable", c);
+    }
+    qaa_instance *inst = new (std::nothrow) qaa_instance();
+    if (!inst) return fail(QAA_ERR_OUT_OF_MEMORY, "qaa_instance_create: host allocation failed");
+    inst->n = n;
+    inst->m = m;
+    inst->lits.assign(lits, lits + 3 * (size_t)m);
+    inst->recs.reserve(m);
+    for (int c = 0; c < m; ++c) inst->recs.push_back(encode_clause(lits + 3 * c));
+    *out = inst;
+    return ok();
+}
+
+extern "C" void qaa_instance_destroy(qaa_instance *inst)
+{
+    if (!inst) return;
+    int cur = 0;
+    const bool have_dev = hipGetDevice(&cur) == hipSuccess;
+    for (auto &kv : inst->dev_recs) {
+        if (!kv.second) continue;
+        if (have_dev) (void)hipSetDevice(kv.first);
+        (void)hipFree(kv.second);
+    }
+    if (have_dev) (void)hipSetDevice(cur);
+    delete inst;
+}
+
+extern "C" qaa_status qaa_instance_info(const qaa_instance *inst, int32_t *n, int32_t *m, int32_t *e_min,
+                                        int32_t *e_max, int64_t *degeneracy)
+{
+    if (!inst) return fail(QAA_ERR_INVALID_ARG, "qaa_instance_info: inst is NULL");
+    if (n) *n = inst->n;
+    if (m) *m = inst->m;
+    if (e_min) *e_min = inst->e_min;
+    if (e_max) *e_max = inst->e_max;
+    if (degeneracy) *degeneracy = inst->degeneracy;
+    return ok();
+}
+
+// ---------------------------------------------------------------------------
+// Energy table
+// ---------------------------------------------------------------------------
+extern "C" qaa_status qaa_energy_table(qaa_instance *inst, void *d_table, qaa_etype etype, void *stream)
+{
+    if (!inst) return fail(QAA_ERR_INVALID_ARG, "qaa_energy_table: inst is NULL");
+    if (!d_table) return fail(QAA_ERR_INVALID_ARG, "qaa_energy_table: d_table is NULL");
+    if (reinterpret_cast<uintptr_t>(d_table) % 16)
+        return fail(QAA_ERR_INVALID_ARG, "qaa_energy_table: d_table must be 16-byte aligned");
+    if (etype != QAA_E_U8 && etype != QAA_E_U16)
+        return fail(QAA_ERR_INVALID_ARG, "qaa_energy_table: bad etype %d", (int)etype);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    DeviceCtx *ctx = nullptr;
+    qaa_status st = device_ctx(&ctx);
+    if (st != QAA_OK) return st;
+    int dev = 0;
+    QAA_HIP(hipGetDevice(&dev));
+
+    ClauseRec *recs = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(inst->mu);
+        auto it = inst->dev_recs.find(dev);
+        if (it == inst->dev_recs.end()) {
+            const size_t bytes = sizeof(ClauseRec) * std::max<size_t>(1, inst->recs.size());
+            QAA_HIP(hipMalloc(reinterpret_cast<void **>(&recs), bytes));
+            if (!inst->recs.empty()) {
+                hipError_t e = hipMemcpy(recs, inst->recs.data(), sizeof(ClauseRec) * inst->recs.size(),
+                                         hipMemcpyHostToDevice);
+                if (e != hipSuccess) {
+                    (void)hipFree(recs);
+                    return fail(QAA_ERR_DEVICE, "qaa_energy_table: clause upload failed: %s", hipGetErrorString(e));
+                }
+            }
+            inst->dev_recs[dev] = recs;
+        } else {
+            recs = it->second;
+        }
+    }
+
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    QAA_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(ctx->stats), 0xFFFFFFFFu, 1, s));
+    QAA_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(ctx->stats + 1), 0u, 3, s));
+    QAA_HIP(launch_energy(recs, inst->m, inst->n, d_table, (int)etype, ctx->stats, s));
+    uint32_t *h = reinterpret_cast<uint32_t *>(ctx->host_pinned);
+    QAA_HIP(hipMemcpyAsync(h, ctx->stats, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    QAA_HIP(hipStreamSynchronize(s));
+    const uint32_t emin = h[0], emax = h[1], over = h[2];
+    if (etype == QAA_E_U8 && (over || emax > 255))
+        return fail(QAA_ERR_UNSUPPORTED, "qaa_energy_table: E_max=%u does not fit uint8; use QAA_E_U16", emax);
+    QAA_HIP(hipMemsetAsync(ctx->count, 0, sizeof(unsigned long long), s));
+    QAA_HIP(launch_count_equal(d_table, (int)etype, inst->n, (int)emin, ctx->count, s));
+    unsigned long long *hc = reinterpret_cast<unsigned long long *>(h + 8);
+    QAA_HIP(hipMemcpyAsync(hc, ctx->count, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    QAA_HIP(hipStreamSynchronize(s));
+    inst->e_min = (int32_t)emin;
+    inst->e_max = (int32_t)emax;
+    inst->degeneracy = (int64_t)*hc;
+    return ok();
+}
+
+// ---------------------------------------------------------------------------
+// State initialisation
+// ---------------------------------------------------------------------------
+namespace {
+
+qaa_status check_state_amp(const qaa_state *st, const char *who)
+{
+    if (!st) return fail(QAA_ERR_INVALID_ARG, "%s: state is NULL", who);
+    if (!st->inst) return fail(QAA_ERR_INVALID_ARG, "%s: state has no instance", who);
+    if (!st->amp) return fail(QAA_ERR_INVALID_ARG, "%s: state has no amplitude buffer", who);
+    if (st->dtype != QAA_C64 && st->dtype != QAA_C128)
+        return fail(QAA_ERR_INVALID_ARG, "%s: bad dtype %d", who, (int)st->dtype);
+    if (reinterpret_cast<uintptr_t>(st->amp) % 16)
+        return fail(QAA_ERR_INVALID_ARG, "%s: amplitudes must be 16-byte aligned", who);
+    return QAA_OK;
+}
+
+qaa_status check_state_table(const qaa_state *st, const char *who)
+{
+    qaa_status r = check_state_amp(st, who);
+    if (r != QAA_OK) return r;
+    if (!st->table) return fail(QAA_ERR_INVALID_ARG, "%s: state has no energy table", who);
+    if (st->etype != QAA_E_U8 && st->etype != QAA_E_U16)
+        return fail(QAA_ERR_INVALID_ARG, "%s: bad etype %d", who, (int)st->etype);
+    if (reinterpret_cast<uintptr_t>(st->table) % 16)
+        return fail(QAA_ERR_INVALID_ARG, "%s: energy table must be 16-byte aligned", who);
+    if (st->inst->e_max < 0)
+        return fail(QAA_ERR_NOT_READY, "%s: qaa_energy_table has not run for this instance", who);
+    return QAA_OK;
+}
+
+}  // namespace
+
+extern "C" qaa_status qaa_state_init_uniform(const qaa_state *st, void *stream)
+{
+    qaa_status r = check_state_amp(st, "qaa_state_init_uniform");
+    if (r != QAA_OK) return r;
+    QAA_HIP(launch_init_uniform(st->amp, (int)st->dtype, st->inst->n, reinterpret_cast<hipStream_t>(stream)));
+    return ok();
+}
+
+extern "C" qaa_status qaa_state_init_basis(const qaa_state *st, uint64_t z0, void *stream)
+{
+    qaa_status r = check_state_amp(st, "qaa_state_init_basis");
+    if (r != QAA_OK) return r;
+    if (z0 >> st->inst->n) return fail(QAA_ERR_INVALID_ARG, "qaa_state_init_basis: z0 >= 2^n");
+    QAA_HIP(launch_init_basis(st->amp, (int)st->dtype, st->inst->n, z0, reinterpret_cast<hipStream_t>(stream)));
+    return ok();
+}
+
+// ---------------------------------------------------------------------------
+// Planner
+// ---------------------------------------------------------------------------
+namespace {
+
+struct SetPlan {
+    std::vector<int> tile;       // physical bits of the tile, ascending (size TB)
+    std::vector<int> rot_local;  // tile-local indices of the rotated qubits
+};
+
+struct Plan {
+    bool resident = false;
+    int tile_bits = 0, reg_bits = 0;
+    std::vector<SetPlan> sets;
+};
+
+Plan make_plan(int n, int dtype)
+{
+    Plan p;
+    const int TB = kPassTileBits[dtype];
+    if (n <= kResRegBits[dtype] + kResThrBits) {
+        p.resident = true;
+        return p;
+    }
+    p.tile_bits = TB;
+    p.reg_bits = kPassRegBits[dtype];
+    const int pas = kPassengerBits[dtype];
+    SetPlan s0;
+    for (int b = 0; b < TB; ++b) {
+        s0.tile.push_back(b);
+        s0.rot_local.push_back(b);
+    }
+    p.sets.push_back(s0);
+    const int q = TB - pas;
+    for (int b = TB; b < n; b += q) {
+        const int hi = std::min(n, b + q);
+        SetPlan s;
+        const int extra = TB - (hi - b);       // low passenger bits
+        for (int j = 0; j < extra; ++j) s.tile.push_back(j);
+        for (int j = b; j < hi; ++j) s.tile.push_back(j);
+        for (int j = extra; j < TB; ++j) s.rot_local.push_back(j);
+        p.sets.push_back(s);
+    }
+    return p;
+}
+
+// Split rotated tile-local bits into register groups of rb bits (highest
+// bits first); each group is padded with non-rotated filler bits.  Returns
+// per group: the rb tile bits (rotated ones first) and the rotated count.
+struct Group {
+    std::vector<int> bits;
+    int nrot;
+};
+
+std::vector<Group> make_groups(const std::vector<int> &rot, int tb, int rb)
+{
+    std::vector<int> order(rot.rbegin(), rot.rend());
+    std::vector<Group> gs;
+    for (size_t i = 0; i < order.size(); i += rb) {
+        Group g;
+        for (size_t j = i; j < std::min(order.size(), i + rb); ++j) g.bits.push_back(order[j]);
+        g.nrot = (int)g.bits.size();
+        for (int b = tb - 1; b >= 0 && (int)g.bits.size() < rb; --b)
+            if (std::find(g.bits.begin(), g.bits.end(), b) == g.bits.end()) g.bits.push_back(b);
+        gs.push_back(g);
+    }
+    return gs;
+}
+
+struct StepCoef {
+    double s, theta, cm1, sn;
+};
+
+StepCoef step_coef(double T, int64_t N, int64_t k)
+{
+    StepCoef c;
+    const double dt = T / (double)N;
+    c.s = ((double)k + 0.5) / (double)N;
+    c.theta = dt * (1.0 - c.s);
+    const double q = std::sin(0.25 * c.theta);
+    c.cm1 = -2.0 * q * q;
+    c.sn = std::sin(0.5 * c.theta);
+    return c;
+}
+
+double wrap_phase(double a)
+{
+    return std::fmod(a, 2.0 * M_PI);
+}
+
+// Residency list for one pass over set `sp`:
+//   v1: rotate with coefficient set A before the phase,
+//   ph: apply the phase,
+//   v2: rotate with coefficient set B after the phase.
+void fill_residencies(PassDesc &d, const SetPlan &sp, int tb, int rb, bool v1, bool ph, bool v2)
+{
+    const std::vector<Group> gs = make_groups(sp.rot_local, tb, rb);
+    const int G = (int)gs.size();
+    struct Res {
+        int g;
+        uint8_t ma, mb;
+        bool phase;
+    };
+    std::vector<Res> rs;
+    auto full = [&](int g) { return (uint8_t)((1u << gs[g].nrot) - 1u); };
+    if (v1 && ph && v2) {
+        for (int g = 0; g < G - 1; ++g) rs.push_back({g, full(g), 0, false});
+        rs.push_back({G - 1, full(G - 1), full(G - 1), true});
+        for (int g = G - 2; g >= 0; --g) rs.push_back({g, 0, full(g), false});
+    } else if (v1 && ph) {
+        for (int g = 0; g < G - 1; ++g) rs.push_back({g, full(g), 0, false});
+        rs.push_back({G - 1, full(G - 1), 0, true});
+    } else if (ph && v2) {
+        rs.push_back({0, 0, full(0), true});
+        for (int g = 1; g < G; ++g) rs.push_back({g, 0, full(g), false});
+    } else {
+        for (int g = 0; g < G; ++g) rs.push_back({g, full(g), 0, false});
+    }
+    d.n_res = (int)rs.size();
+    d.phase_at = -1;
+    for (int r = 0; r < d.n_res; ++r) {
+        const Group &g = gs[rs[r].g];
+        for (int i = 0; i < rb; ++i) d.gbits[r][i] = (uint8_t)g.bits[i];
+        int k = 0;
+        for (int b = 0; b < tb; ++b)
+            if (std::find(g.bits.begin(), g.bits.end(), b) == g.bits.end()) d.tpos[r][k++] = (uint8_t)b;
+        d.maskA[r] = rs[r].ma;
+        d.maskB[r] = rs[r].mb;
+        if (rs[r].phase) d.phase_at = r;
+    }
+}
+
+qaa_status run_resident(const qaa_state *st, double T, int64_t N, int64_t k0, int64_t k1, hipStream_t s)
+{
+    const int n = st->inst->n;
+    const int dt = (int)st->dtype;
+    ResidentDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.amp = st->amp;
+    d.table = st->table;
+    d.n = n;
+    d.emax = st->inst->e_max;
+    d.T = T;
+    d.N = N;
+    d.k0 = k0;
+    d.k1 = k1;
+    d.reg_bits = std::min(kResRegBits[dt], n);
+    d.thr_bits = n - d.reg_bits;
+    std::vector<int> rot;
+    for (int b = 0; b < n; ++b) rot.push_back(b);
+    const std::vector<Group> gs = make_groups(rot, n, d.reg_bits);
+    d.n_groups = (int)gs.size();
+    for (int g = 0; g < d.n_groups; ++g) {
+        for (int i = 0; i < d.reg_bits; ++i) d.gbits[g][i] = (uint8_t)gs[g].bits[i];
+        int k = 0;
+        for (int b = 0; b < n; ++b)
+            if (std::find(gs[g].bits.begin(), gs[g].bits.end(), b) == gs[g].bits.end()) d.tpos[g][k++] = (uint8_t)b;
+        d.gmask[g] = (uint8_t)((1u << gs[g].nrot) - 1u);
+    }
+    QAA_HIP(launch_resident(nullptr, &d, 1, dt, (int)st->etype, s));
+    return QAA_OK;
+}
+
+// The pass sequence for steps k0..k1-1 (see PassDesc).  The qubit sets are
+// visited forward on even steps (relative to k0) and backward on odd ones,
+// so the set that ends step k also starts step k+1 and one pass applies
+// both its rotations and the merged diagonal phase between them.
+std::vector<PassDesc> build_passes(const Plan &p, int n, int emax, double T, int64_t N, int64_t k0, int64_t k1)
+{
+    std::vector<PassDesc> out;
+    const int TB = p.tile_bits, RB = p.reg_bits;
+    const int r = (int)p.sets.size();
+    const double dt = T / (double)N;
+    PassDesc base;
+    std::memset(&base, 0, sizeof base);
+    base.n = n;
+    base.emax = emax;
+    for (int64_t k = k0; k < k1; ++k) {
+        const bool fwd = ((k - k0) & 1) == 0;
+        const StepCoef ck = step_coef(T, N, k);
+        for (int idx = 0; idx < r; ++idx) {
+            const int set = fwd ? idx : r - 1 - idx;
+            const bool first = idx == 0, last = idx == r - 1;
+            if (first && k > k0) continue;    // merged into the previous turn pass
+            PassDesc d = base;
+            const SetPlan &sp = p.sets[set];
+            for (int j = 0; j < TB; ++j) d.tile_pos[j] = (uint8_t)sp.tile[j];
+            int nr = 0;
+            for (int b = 0; b < n; ++b)
+                if (std::find(sp.tile.begin(), sp.tile.end(), b) == sp.tile.end()) d.rest_pos[nr++] = (uint8_t)b;
+            d.n_rest = nr;
+            if (first) {
+                // k == k0: half phase of step k0, then this set's rotations
+                d.phi = 0.5 * dt * ck.s;
+                d.gphase = 0.0;
+                d.cm1B = ck.cm1;
+                d.sB = ck.sn;
+                fill_residencies(d, sp, TB, RB, false, true, true);
+            } else if (last && k + 1 < k1) {
+                const StepCoef cn = step_coef(T, N, k + 1);
+                d.cm1A = ck.cm1;
+                d.sA = ck.sn;
+                d.phi = 0.5 * dt * (ck.s + cn.s);
+                d.gphase = wrap_phase(0.5 * n * ck.theta);
+                d.cm1B = cn.cm1;
+                d.sB = cn.sn;
+                fill_residencies(d, sp, TB, RB, true, true, true);
+            } else if (last) {
+                d.cm1A = ck.cm1;
+                d.sA = ck.sn;
+                d.phi = 0.5 * dt * ck.s;
+                d.gphase = wrap_phase(0.5 * n * ck.theta);
+                fill_residencies(d, sp, TB, RB, true, true, false);
+            } else {
+                d.cm1A = ck.cm1;
+                d.sA = ck.sn;
+                fill_residencies(d, sp, TB, RB, true, false, false);
+            }
+            out.push_back(d);
+        }
+    }
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel timing: event pairs around pass launches (qaa_profile_enable).
+// ---------------------------------------------------------------------------
+struct ProfRec {
+    hipEvent_t a, b;
+    double bytes;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_live;     // recorded, not yet read
+std::vector<hipEvent_t> g_prof_pool;  // free events
+int64_t g_prof_launches = 0;
+double g_prof_ms = 0.0, g_prof_min = 0.0, g_prof_max = 0.0, g_prof_bytes = 0.0;
+
+hipError_t prof_event(hipEvent_t *e)
+{
+    if (!g_prof_pool.empty()) {
+        *e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(e);
+}
+
+// Collect finished records; with wait = false only those already complete.
+hipError_t prof_drain(bool wait)
+{
+    size_t keep = 0;
+    for (size_t i = 0; i < g_prof_live.size(); ++i) {
+        ProfRec &r = g_prof_live[i];
+        if (wait) {
+            hipError_t e = hipEventSynchronize(r.b);
+            if (e != hipSuccess) return e;
+        } else if (hipEventQuery(r.b) != hipSuccess) {
+            g_prof_live[keep++] = r;
+            continue;
+        }
+        float ms = 0.f;
+        hipError_t e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) return e;
+        if (g_prof_launches == 0 || ms < g_prof_min) g_prof_min = ms;
+        if (g_prof_launches == 0 || ms > g_prof_max) g_prof_max = ms;
+        g_prof_launches += 1;
+        g_prof_ms += ms;
+        g_prof_bytes += r.bytes;
+        g_prof_pool.push_back(r.a);
+        g_prof_pool.push_back(r.b);
+    }
+    g_prof_live.resize(keep);
+    return hipSuccess;
+}
+
+// Norm control (see PassDesc) is on unless QAA_NORM_CONTROL=0 is set in
+// the environment (used to measure the uncorrected FP32 drift).
+bool norm_control_enabled()
+{
+    static const bool on = [] {
+        const char *e = std::getenv("QAA_NORM_CONTROL");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
+
+qaa_status run_passes(const qaa_state *st, const Plan &p, double T, int64_t N, int64_t k0, int64_t k1,
+                      hipStream_t s)
+{
+    std::vector<PassDesc> ps = build_passes(p, st->inst->n, st->inst->e_max, T, N, k0, k1);
+    unsigned long long *acc = nullptr;
+    if (norm_control_enabled()) {
+        QAA_HIP(hipMallocAsync(reinterpret_cast<void **>(&acc), 3 * sizeof(unsigned long long), s));
+        QAA_HIP(launch_zero_u64(acc, 3, s));
+        for (size_t j = 0; j < ps.size(); ++j) {
+            ps[j].acc_out = acc + j % 3;
+            ps[j].acc_zero = acc + (j + 1) % 3;
+            ps[j].acc_in = j > 0 ? acc + (j + 2) % 3 : nullptr;
+        }
+    }
+    bool prof;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        prof = g_prof_on;
+    }
+    const double amp_bytes = st->dtype == QAA_C64 ? 8.0 : 16.0;
+    const double e_bytes = st->etype == QAA_E_U8 ? 1.0 : 2.0;
+    const double dim = std::ldexp(1.0, st->inst->n);
+    for (const PassDesc &d : ps) {
+        ProfRec rec{};
+        if (prof) {
+            std::lock_guard<std::mutex> lk(g_prof_mu);
+            if (g_prof_live.size() > 4096) QAA_HIP(prof_drain(false));
+            QAA_HIP(prof_event(&rec.a));
+            QAA_HIP(prof_event(&rec.b));
+            rec.bytes = dim * (2.0 * amp_bytes + (d.phase_at >= 0 ? e_bytes : 0.0));
+            QAA_HIP(hipEventRecord(rec.a, s));
+        }
+        hipError_t e = launch_pass(st->amp, (int)st->dtype, st->table, (int)st->etype, p.tile_bits, p.reg_bits, d, s);
+        if (e != hipSuccess) {
+            if (acc) (void)hipFreeAsync(acc, s);
+            return fail(QAA_ERR_DEVICE, "pass launch failed: %s", hipGetErrorString(e));
+        }
+        if (prof) {
+            std::lock_guard<std::mutex> lk(g_prof_mu);
+            QAA_HIP(hipEventRecord(rec.b, s));
+            g_prof_live.push_back(rec);
+        }
+    }
+    if (acc) QAA_HIP(hipFreeAsync(acc, s));
+    return QAA_OK;
+}
+
+int lut_limit(qaa_etype e) { return e == QAA_E_U8 ? kLutMaxU8 : kLutMax; }
+
+qaa_status evolve_common(const qaa_state *st, const qaa_schedule *sched, double T, int64_t steps, int64_t k0,
+                         int64_t k1, void *stream, const char *who)
+{
+    qaa_status r = check_state_table(st, who);
+    if (r != QAA_OK) return r;
+    if (sched && sched->kind != QAA_SCHED_LINEAR)
+        return fail(QAA_ERR_UNSUPPORTED, "%s: schedule kind %d not supported", who, sched->kind);
+    if (!(T >= 0.0) || !std::isfinite(T)) return fail(QAA_ERR_INVALID_ARG, "%s: T must be finite and >= 0", who);
+    if (steps < 0) return fail(QAA_ERR_INVALID_ARG, "%s: steps < 0", who);
+    if (k0 < 0 || k1 < k0 || k1 > steps)
+        return fail(QAA_ERR_INVALID_ARG, "%s: need 0 <= k0 <= k1 <= steps", who);
+    if (st->inst->e_max >= lut_limit(st->etype))
+        return fail(QAA_ERR_UNSUPPORTED, "%s: E_max=%d exceeds the phase table limit %d", who, st->inst->e_max,
+                    lut_limit(st->etype) - 1);
+    if (k0 == k1) return ok();
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const Plan p = make_plan(st->inst->n, (int)st->dtype);
+    r = p.resident ? run_resident(st, T, steps, k0, k1, s) : run_passes(st, p, T, steps, k0, k1, s);
+    if (r != QAA_OK) return r;
+    return ok();
+}
+
+}  // namespace
+
+extern "C" qaa_status qaa_evolve(const qaa_state *st, const qaa_schedule *sched, double T, int64_t steps,
+                                 void *stream)
+{
+    return evolve_common(st, sched, T, steps, 0, steps, stream, "qaa_evolve");
+}
+
+extern "C" qaa_status qaa_evolve_range(const qaa_state *st, const qaa_schedule *sched, double T, int64_t steps,
+                                       int64_t k0, int64_t k1, void *stream)
+{
+    return evolve_common(st, sched, T, steps, k0, k1, stream, "qaa_evolve_range");
+}
+
+extern "C" qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, const double *T,
+                                       const int64_t *steps, void *stream)
+{
+    if (count < 0) return fail(QAA_ERR_INVALID_ARG, "qaa_evolve_batch: count < 0");
+    if (count == 0) return ok();
+    if (!states || !T || !steps) return fail(QAA_ERR_INVALID_ARG, "qaa_evolve_batch: NULL array");
+    for (int i = 0; i < count; ++i) {
+        qaa_status r = evolve_common(&states[i], nullptr, T[i], steps[i], 0, steps[i], stream, "qaa_evolve_batch");
+        if (r != QAA_OK) return r;
+    }
+    return ok();
+}
+
+// ---------------------------------------------------------------------------
+// Observables
+// ---------------------------------------------------------------------------
+extern "C" qaa_status qaa_observables(const qaa_state *st, qaa_obs *out, void *stream)
+{
+    if (!out) return fail(QAA_ERR_INVALID_ARG, "qaa_observables: out is NULL");
+    qaa_status r = check_state_table(st, "qaa_observables");
+    if (r != QAA_OK) return r;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    DeviceCtx *ctx = nullptr;
+    r = device_ctx(&ctx);
+    if (r != QAA_OK) return r;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const int nb = observables_blocks(st->inst->n);
+    QAA_HIP(launch_observables(st->amp, (int)st->dtype, st->table, (int)st->etype, st->inst->n, st->inst->e_min,
+                               ctx->partials, nb, ctx->obs_out, s));
+    double *h = reinterpret_cast<double *>(ctx->host_pinned);
+    QAA_HIP(hipMemcpyAsync(h, ctx->obs_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    QAA_HIP(hipStreamSynchronize(s));
+    out->norm = h[0];
+    out->energy = h[1];
+    out->p_success = h[2];
+    out->e_min = st->inst->e_min;
+    out->degeneracy = st->inst->degeneracy;
+    return ok();
+}
+
+// ---------------------------------------------------------------------------
+// Plan introspection, errors, version
+// ---------------------------------------------------------------------------
+extern "C" qaa_status qaa_plan_info(int32_t n, qaa_dtype dtype, int32_t *tile_bits, int32_t *sets,
+                                    int32_t *passes_per_step)
+{
+    if (n < 1 || n > QAA_MAX_QUBITS) return fail(QAA_ERR_INVALID_ARG, "qaa_plan_info: n out of range");
+    if (dtype != QAA_C64 && dtype != QAA_C128) return fail(QAA_ERR_INVALID_ARG, "qaa_plan_info: bad dtype");
+    const Plan p = make_plan(n, (int)dtype);
+    if (tile_bits) *tile_bits = p.resident ? 0 : p.tile_bits;
+    if (sets) *sets = p.resident ? 1 : (int32_t)p.sets.size();
+    if (passes_per_step) *passes_per_step = p.resident ? 0 : (int32_t)p.sets.size() - 1;
+    return ok();
+}
+
+extern "C" qaa_status qaa_debug_pass_descs(int32_t n, qaa_dtype dtype, int32_t emax, double T, int64_t steps,
+                                           int64_t k0, int64_t k1, void *out, int32_t capacity, int32_t *count,
+                                           int32_t *desc_bytes)
+{
+    if (n < 1 || n > QAA_MAX_QUBITS) return fail(QAA_ERR_INVALID_ARG, "qaa_debug_pass_descs: n out of range");
+    if (dtype != QAA_C64 && dtype != QAA_C128) return fail(QAA_ERR_INVALID_ARG, "qaa_debug_pass_descs: bad dtype");
+    if (steps < 0 || k0 < 0 || k1 < k0 || k1 > steps || !count)
+        return fail(QAA_ERR_INVALID_ARG, "qaa_debug_pass_descs: bad step range");
+    if (desc_bytes) *desc_bytes = (int32_t)sizeof(PassDesc);
+    const Plan p = make_plan(n, (int)dtype);
+    if (p.resident || k0 == k1) {
+        *count = 0;
+        return ok();
+    }
+    const std::vector<PassDesc> ps = build_passes(p, n, emax, T, steps, k0, k1);
+    *count = (int32_t)ps.size();
+    if (out && capacity > 0)
+        std::memcpy(out, ps.data(), sizeof(PassDesc) * std::min<size_t>(ps.size(), (size_t)capacity));
+    return ok();
+}
+
+extern "C" qaa_status qaa_profile_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return ok();
+}
+
+extern "C" qaa_status qaa_profile_read(qaa_profile *out, int32_t reset)
+{
+    if (!out) return fail(QAA_ERR_INVALID_ARG, "qaa_profile_read: out is NULL");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    QAA_HIP(prof_drain(true));
+    out->launches = g_prof_launches;
+    out->kernel_ms = g_prof_ms;
+    out->min_ms = g_prof_min;
+    out->max_ms = g_prof_max;
+    out->alg_bytes = g_prof_bytes;
+    if (reset) {
+        g_prof_launches = 0;
+        g_prof_ms = g_prof_min = g_prof_max = g_prof_bytes = 0.0;
+    }
+    return ok();
+}
+
+extern "C" const char *qaa_status_str(qaa_status s)
+{
+    switch (s) {
+    case QAA_OK: return "ok";
+    case QAA_ERR_INVALID_ARG: return "invalid argument";
+    case QAA_ERR_UNSUPPORTED: return "unsupported";
+    case QAA_ERR_OUT_OF_MEMORY: return "out of memory";
+    case QAA_ERR_DEVICE: return "device error";
+    case QAA_ERR_NOT_READY: return "not ready";
+    case QAA_ERR_INTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+extern "C" const char *qaa_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" int32_t qaa_version(void) { return 100; }

@@ -1,0 +1,128 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/qaa.h declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+
+import paper_1103_1399_amd as qaa
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "qaa.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(qaa_[a-z_0-9]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for must in ["qaa_instance_create", "qaa_instance_destroy", "qaa_instance_info", "qaa_energy_table",
+                 "qaa_state_init_uniform", "qaa_evolve", "qaa_evolve_range", "qaa_evolve_batch",
+                 "qaa_observables", "qaa_status_str", "qaa_last_error"]:
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(qaa.LIB_PATH)
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+    # and the binding wraps each of them under the same name
+    for name in _declared_functions():
+        assert hasattr(qaa, name), name
+
+
+def test_status_strings():
+    assert qaa.qaa_status_str(qaa.QAA_OK) == "ok"
+    assert qaa.qaa_status_str(qaa.QAA_ERR_INVALID_ARG) == "invalid argument"
+    assert qaa.qaa_status_str(99) == "unknown status"
+    assert qaa.qaa_version() >= 100
+
+
+@pytest.mark.parametrize("n,lits,msg", [
+    (0, [], "n=0"),
+    (35, [], "n=35"),
+    (4, [1, 2, 5], "out of range"),
+    (4, [1, 0, 2], "out of range"),
+    (4, [1, -1, 2], "repeats a variable"),
+    (4, [3, 2, 3], "repeats a variable"),
+])
+def test_instance_create_rejects(n, lits, msg):
+    with pytest.raises(qaa.QaaError) as ei:
+        qaa.qaa_instance_create(n, lits)
+    assert ei.value.status == qaa.QAA_ERR_INVALID_ARG
+    assert msg in str(ei.value)
+
+
+def test_instance_create_and_info_without_table():
+    lits = [1, -2, 3, -1, 2, 4, 2, 3, 4, 2, 3, 4]   # duplicate clause allowed
+    h = qaa.qaa_instance_create(4, lits)
+    try:
+        info = qaa.qaa_instance_info(h)
+        assert info == {"n": 4, "m": 4, "e_min": -1, "e_max": -1, "degeneracy": -1}
+    finally:
+        qaa.qaa_instance_destroy(h)
+    qaa.qaa_instance_destroy(None)   # NULL is ignored
+
+
+def test_zero_clause_instance():
+    h = qaa.qaa_instance_create(1, [])
+    assert qaa.qaa_instance_info(h)["m"] == 0
+    qaa.qaa_instance_destroy(h)
+
+
+def test_evolve_rejects_before_any_device_call():
+    h = qaa.qaa_instance_create(5, [1, 2, 3])
+    try:
+        st = qaa.qaa_state(h, 0x1000, qaa.QAA_C64, 0x2000, qaa.QAA_E_U8)
+        sched = qaa.qaa_schedule(qaa.QAA_SCHED_LINEAR)
+        lib = qaa._lib
+        # energy table not computed yet -> NOT_READY
+        rc = lib.qaa_evolve(ctypes.byref(st), ctypes.byref(sched), 1.0, 10, None)
+        assert rc == qaa.QAA_ERR_NOT_READY
+        assert "qaa_energy_table" in qaa.qaa_last_error()
+        # NULL state / missing buffers
+        assert lib.qaa_evolve(None, None, 1.0, 10, None) == qaa.QAA_ERR_INVALID_ARG
+        bad = qaa.qaa_state(h, None, qaa.QAA_C64, 0x2000, qaa.QAA_E_U8)
+        assert lib.qaa_evolve(ctypes.byref(bad), None, 1.0, 10, None) == qaa.QAA_ERR_INVALID_ARG
+        bad = qaa.qaa_state(h, 0x1000, 7, 0x2000, qaa.QAA_E_U8)
+        assert lib.qaa_evolve(ctypes.byref(bad), None, 1.0, 10, None) == qaa.QAA_ERR_INVALID_ARG
+        assert lib.qaa_observables(ctypes.byref(st), None, None) == qaa.QAA_ERR_INVALID_ARG
+        out = qaa.qaa_obs()
+        assert lib.qaa_observables(ctypes.byref(st), ctypes.byref(out), None) == qaa.QAA_ERR_NOT_READY
+        assert lib.qaa_energy_table(h, None, 0, None) == qaa.QAA_ERR_INVALID_ARG
+        assert lib.qaa_energy_table(h, 0x1000, 5, None) == qaa.QAA_ERR_INVALID_ARG
+        assert lib.qaa_evolve_batch(-1, None, None, None, None) == qaa.QAA_ERR_INVALID_ARG
+        assert lib.qaa_evolve_batch(0, None, None, None, None) == qaa.QAA_OK
+    finally:
+        qaa.qaa_instance_destroy(h)
+
+
+@pytest.mark.parametrize("n,dtype,expect", [
+    (6, 0, (0, 1, 0)),
+    (13, 0, (0, 1, 0)),
+    (14, 0, (13, 2, 1)),
+    (21, 0, (13, 2, 1)),
+    (22, 0, (13, 3, 2)),
+    (28, 0, (13, 3, 2)),
+    (29, 0, (13, 3, 2)),
+    (30, 0, (13, 4, 3)),
+    (12, 1, (0, 1, 0)),
+    (13, 1, (12, 2, 1)),
+    (28, 1, (12, 3, 2)),
+    (29, 1, (12, 4, 3)),
+])
+def test_plan_info(n, dtype, expect):
+    p = qaa.qaa_plan_info(n, dtype)
+    assert (p["tile_bits"], p["sets"], p["passes_per_step"]) == expect
+
+
+def test_plan_info_rejects():
+    with pytest.raises(qaa.QaaError):
+        qaa.qaa_plan_info(0)
+    with pytest.raises(qaa.QaaError):
+        qaa.qaa_plan_info(10, 3)

@@ -1,0 +1,342 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars: energy tables bit-exact; complex64 final state L2 <= 1e-4 and
+|dP_success| <= 1e-5 against the complex128 oracle; complex128 GPU runs
+within 1e-10.  Every input is seeded and synthetic.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from conftest import GOLDEN
+from qaa_inputs import SplitMix64, planted_unique_3sat
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+L2_TOL_C64 = 1e-4
+P_TOL_C64 = 1e-5
+L2_TOL_C128 = 1e-10
+
+
+@pytest.fixture(scope="module")
+def qaa():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1103_1399_amd as m
+    return m
+
+
+def _run_gpu(qaa, n, clauses, T, N, dtype=None, etype=None, basis=None):
+    inst = qaa.Instance(n, np.asarray(clauses, np.int32).reshape(-1))
+    et = qaa.QAA_E_U8 if etype is None else etype
+    table = inst.energy_table(etype=et)
+    st = qaa.State(inst, table, dtype=dtype or torch.complex64)
+    if basis is None:
+        st.init_uniform()
+    else:
+        st.init_basis(basis)
+    st.evolve(T, N)
+    obs = st.observables()
+    return inst, table, st, obs
+
+
+def _oracle_run(n, clauses, T, N, basis=None):
+    if basis is None:
+        psi = oracle.init_uniform(n)
+    else:
+        psi = np.zeros(1 << n, np.complex128)
+        psi[basis] = 1.0
+    oracle.evolve(n, clauses, psi, T, N)
+    return psi, oracle.observables(n, clauses, psi)
+
+
+def _compare(st, obs, psi, ref, l2_tol, p_tol):
+    got = st.amp.cpu().numpy().astype(np.complex128)
+    l2 = float(np.linalg.norm(got - psi))
+    dp = abs(obs["p_success"] - ref["p_success"])
+    de = abs(obs["energy"] - ref["energy"])
+    assert l2 <= l2_tol, "L2 %.3g" % l2
+    assert dp <= p_tol, "dP %.3g" % dp
+    assert de <= 10 * l2_tol * max(1.0, ref["energy"]), "d<H_P> %.3g" % de
+    assert abs(obs["norm"] - 1.0) <= 10 * l2_tol
+    return l2, dp
+
+
+# --------------------------------------------------------------------------
+# Energy table
+# --------------------------------------------------------------------------
+
+def test_energy_table_worked_example(qaa, worked_example):
+    n, cl = worked_example["n"], worked_example["clauses"]
+    inst = qaa.Instance(n, np.asarray(cl, np.int32).reshape(-1))
+    table = inst.energy_table()
+    assert np.array_equal(table.cpu().numpy().astype(np.int32), oracle.energy(n, cl))
+    info = inst.info()
+    assert info["e_min"] == 0 and info["degeneracy"] == 1
+    assert table.cpu().numpy()[10] == 0
+
+
+@pytest.mark.parametrize("n,seed", [(3, 0), (4, 1), (7, 2), (10, 3), (13, 4), (16, 5), (20, 6), (22, 7)])
+@pytest.mark.parametrize("etype", [0, 1])
+def test_energy_table_bit_exact(qaa, n, seed, etype):
+    inst_in = planted_unique_3sat(n, seed)
+    inst = qaa.Instance(n, inst_in.literals())
+    table = inst.energy_table(etype=etype)
+    got = table.cpu().numpy()
+    if etype == 1:
+        got = got.view(np.uint16)
+    E = oracle.energy(n, inst_in.clauses)
+    assert np.array_equal(got.astype(np.int32), E)
+    info = inst.info()
+    assert info["e_min"] == E.min() and info["e_max"] == E.max()
+    assert info["degeneracy"] == np.count_nonzero(E == E.min())
+
+
+def test_energy_table_small_n_without_clauses(qaa):
+    for n in (1, 2, 3):
+        inst = qaa.Instance(n, [])
+        table = inst.energy_table()
+        assert table.cpu().numpy().tolist() == [0] * (1 << n)
+        assert inst.info()["degeneracy"] == 1 << n
+
+
+def test_energy_table_u8_overflow_is_rejected(qaa):
+    n = 5
+    cl = [[1, 2, 3]] * 300          # E = 300 on the 4 states with x1=x2=x3=0
+    inst = qaa.Instance(n, np.asarray(cl, np.int32).reshape(-1))
+    with pytest.raises(qaa.QaaError) as ei:
+        inst.energy_table(etype=qaa.QAA_E_U8)
+    assert ei.value.status == qaa.QAA_ERR_UNSUPPORTED
+    table = inst.energy_table(etype=qaa.QAA_E_U16)
+    assert np.array_equal(table.cpu().numpy().view(np.uint16).astype(np.int32), oracle.energy(n, cl))
+    assert inst.info()["e_max"] == 300
+
+
+def test_energy_table_full_size_n28_sampled(qaa):
+    """n = 28 (the headline size): bit-exact on a sample computed by the
+    oracle one state at a time, plus the exact counting identity
+    sum_z E(z) = m 2^{n-3} and the unique planted zero."""
+    n = 28
+    inst_in = planted_unique_3sat(n, 0)
+    inst = qaa.Instance(n, inst_in.literals())
+    table = inst.energy_table()
+    rng = SplitMix64(28)
+    zs = [rng.below(1 << n) for _ in range(20000)]
+    zs += list(range(4096)) + list(range((1 << n) - 4096, 1 << n)) + [inst_in.planted]
+    zs = np.asarray(zs, dtype=np.int64)
+    got = table[torch.from_numpy(zs).cuda()].cpu().numpy().astype(np.int32)
+    assert np.array_equal(got, oracle.energy_at(n, inst_in.clauses, zs.astype(np.uint64)))
+    total = int(table.to(torch.int64).sum().item())
+    assert total == inst_in.m * (1 << (n - 3))
+    info = inst.info()
+    assert info["e_min"] == 0 and info["degeneracy"] == 1
+    assert int(table[inst_in.planted].item()) == 0
+
+
+# --------------------------------------------------------------------------
+# Evolution parity
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(10))
+def test_evolve_n10_T10_1000_steps(qaa, seed):
+    """n = 10, T = 10, 1000 steps: complex64 GPU vs complex128 oracle."""
+    n, T, N = 10, 10.0, 1000
+    inst_in = planted_unique_3sat(n, seed)
+    _, _, st, obs = _run_gpu(qaa, n, inst_in.clauses, T, N)
+    psi, ref = _oracle_run(n, inst_in.clauses, T, N)
+    _compare(st, obs, psi, ref, L2_TOL_C64, P_TOL_C64)
+
+
+@pytest.mark.parametrize("n,T,N", [(5, 3.0, 40), (13, 5.0, 60), (14, 5.0, 60), (15, 8.0, 80), (17, 5.0, 50),
+                                   (21, 5.0, 30), (22, 5.0, 12), (23, 4.0, 8)])
+def test_evolve_multipass_parity(qaa, n, T, N):
+    """Sizes around every plan boundary: resident (n <= 13), two qubit sets
+    (14..21), three sets (22..), including ragged last sets."""
+    inst_in = planted_unique_3sat(n, 100 + n)
+    _, _, st, obs = _run_gpu(qaa, n, inst_in.clauses, T, N)
+    psi, ref = _oracle_run(n, inst_in.clauses, T, N)
+    _compare(st, obs, psi, ref, L2_TOL_C64, P_TOL_C64)
+
+
+@pytest.mark.parametrize("n,T,N", [(6, 4.0, 50), (12, 5.0, 40), (13, 5.0, 40), (16, 6.0, 30), (20, 5.0, 10)])
+def test_evolve_complex128_parity(qaa, n, T, N):
+    inst_in = planted_unique_3sat(n, 200 + n)
+    _, _, st, obs = _run_gpu(qaa, n, inst_in.clauses, T, N, dtype=torch.complex128)
+    psi, ref = _oracle_run(n, inst_in.clauses, T, N)
+    _compare(st, obs, psi, ref, L2_TOL_C128, 1e-12)
+
+
+def test_evolve_u16_table_path(qaa):
+    n, T, N = 15, 6.0, 40
+    inst_in = planted_unique_3sat(n, 31)
+    _, _, st, obs = _run_gpu(qaa, n, inst_in.clauses, T, N, etype=qaa.QAA_E_U16)
+    psi, ref = _oracle_run(n, inst_in.clauses, T, N)
+    _compare(st, obs, psi, ref, L2_TOL_C64, P_TOL_C64)
+
+
+def test_evolve_from_basis_state(qaa):
+    n, T, N = 16, 5.0, 40
+    inst_in = planted_unique_3sat(n, 41)
+    _, _, st, obs = _run_gpu(qaa, n, inst_in.clauses, T, N, basis=12345)
+    psi, ref = _oracle_run(n, inst_in.clauses, T, N, basis=12345)
+    _compare(st, obs, psi, ref, L2_TOL_C64, P_TOL_C64)
+
+
+def test_evolve_n24_three_sets_vs_oracle(qaa):
+    """n = 24 runs the same three-set pass structure as n = 28."""
+    n, T, N = 24, 50.0, 6
+    inst_in = planted_unique_3sat(n, 0)
+    _, _, st, obs = _run_gpu(qaa, n, inst_in.clauses, T, N)
+    psi, ref = _oracle_run(n, inst_in.clauses, T, N)
+    _compare(st, obs, psi, ref, L2_TOL_C64, P_TOL_C64)
+
+
+def test_evolve_range_composes(qaa):
+    n, T, N, K = 16, 8.0, 60, 23
+    inst_in = planted_unique_3sat(n, 51)
+    inst = qaa.Instance(n, inst_in.literals())
+    table = inst.energy_table()
+    a = qaa.State(inst, table).init_uniform().evolve(T, N)
+    b = qaa.State(inst, table).init_uniform()
+    b.evolve_range(T, N, 0, K)
+    b.evolve_range(T, N, K, N)
+    torch.cuda.synchronize()
+    diff = float(torch.linalg.vector_norm((a.amp - b.amp).to(torch.complex128)).item())
+    assert diff < 1e-5
+    psi, ref = _oracle_run(n, inst_in.clauses, T, N)
+    _compare(b, b.observables(), psi, ref, L2_TOL_C64, P_TOL_C64)
+
+
+def test_zero_steps_and_zero_time_are_identity(qaa):
+    n = 15
+    inst_in = planted_unique_3sat(n, 61)
+    inst = qaa.Instance(n, inst_in.literals())
+    table = inst.energy_table()
+    st = qaa.State(inst, table).init_uniform()
+    ref = st.amp.clone()
+    st.evolve(5.0, 0)
+    assert torch.equal(st.amp, ref)
+    st.evolve(0.0, 7)
+    assert torch.equal(st.amp, ref)
+    obs = st.observables()
+    # 2^{-n/2} is rounded once to FP32 for odd n
+    assert abs(obs["p_success"] - 2.0 ** -n) < 2.0 ** -n * 1e-6
+    assert abs(obs["energy"] - inst_in.m / 8.0) < inst_in.m / 8.0 * 1e-6
+
+
+def test_deterministic(qaa):
+    n, T, N = 18, 5.0, 20
+    inst_in = planted_unique_3sat(n, 71)
+    inst = qaa.Instance(n, inst_in.literals())
+    table = inst.energy_table()
+    a = qaa.State(inst, table).init_uniform().evolve(T, N)
+    b = qaa.State(inst, table).init_uniform().evolve(T, N)
+    torch.cuda.synchronize()
+    assert torch.equal(a.amp, b.amp)
+    assert a.observables() == b.observables()
+
+
+def test_observables_match_oracle_on_same_state(qaa):
+    n, T, N = 17, 5.0, 30
+    inst_in = planted_unique_3sat(n, 81)
+    _, _, st, obs = _run_gpu(qaa, n, inst_in.clauses, T, N)
+    ref = oracle.observables(n, inst_in.clauses, st.amp.cpu().numpy().astype(np.complex128))
+    for k in ("norm", "energy", "p_success"):
+        assert abs(obs[k] - ref[k]) <= 1e-12 * max(1.0, abs(ref[k])), k
+    assert obs["e_min"] == ref["e_min"] and obs["degeneracy"] == ref["degeneracy"]
+
+
+def test_batch_equals_individual(qaa):
+    ns = [6, 10, 13, 14, 17]
+    Ts = [3.0, 4.0, 5.0, 6.0, 7.0]
+    Ns = [30, 40, 50, 20, 10]
+    insts, tables, singles, batch = [], [], [], []
+    for i, n in enumerate(ns):
+        inst_in = planted_unique_3sat(n, 300 + i)
+        inst = qaa.Instance(n, inst_in.literals())
+        table = inst.energy_table()
+        insts.append(inst)
+        tables.append(table)
+        singles.append(qaa.State(inst, table).init_uniform().evolve(Ts[i], Ns[i]))
+        batch.append(qaa.State(inst, table).init_uniform())
+    qaa.qaa_evolve_batch([b.c for b in batch], Ts, Ns)
+    torch.cuda.synchronize()
+    for s, b in zip(singles, batch):
+        assert torch.equal(s.amp, b.amp)
+
+
+# --------------------------------------------------------------------------
+# Full size (n = 28), the launch configuration the benchmark times
+# --------------------------------------------------------------------------
+
+def test_full_size_driver_only_closed_form(qaa):
+    """m = 0 from |z0> at n = 28: psi(z) = a^{n-d} b^d with Theta = T/2
+    (holds for any step count); checked on a sample and by the norm."""
+    n, T, N, z0 = 28, 50.0, 6, 0x5A5A5A5
+    inst = qaa.Instance(n, [])
+    table = inst.energy_table()
+    st = qaa.State(inst, table).init_basis(z0).evolve(T, N)
+    obs = st.observables()
+    th = T / 2.0
+    a = (1 + np.exp(-1j * th)) / 2
+    b = (1 - np.exp(-1j * th)) / 2
+    rng = SplitMix64(5)
+    zs = np.asarray([rng.below(1 << n) for _ in range(4096)] + [z0, z0 ^ 1, z0 ^ (1 << 27)], dtype=np.int64)
+    got = st.amp[torch.from_numpy(zs).cuda()].cpu().numpy().astype(np.complex128)
+    d = np.array([bin(int(z) ^ z0).count("1") for z in zs])
+    expect = a ** (n - d) * b ** d
+    assert np.max(np.abs(got - expect)) < 1e-6
+    assert abs(obs["norm"] - 1.0) < 1e-5
+
+
+def test_full_size_c64_vs_c128_first_steps(qaa):
+    """n = 28, T = 50, steps 0..4 of 5000: complex64 against the complex128
+    GPU path (itself pinned to the oracle at smaller n)."""
+    n, T, N, K = 28, 50.0, 5000, 4
+    inst_in = planted_unique_3sat(n, 0)
+    inst = qaa.Instance(n, inst_in.literals())
+    table = inst.energy_table()
+    a = qaa.State(inst, table, dtype=torch.complex64).init_uniform()
+    a.evolve_range(T, N, 0, K)
+    oa = a.observables()
+    b = qaa.State(inst, table, dtype=torch.complex128).init_uniform()
+    b.evolve_range(T, N, 0, K)
+    ob = b.observables()
+    diff = float(torch.linalg.vector_norm(a.amp.to(torch.complex128) - b.amp).item())
+    assert diff < 1e-5
+    assert abs(oa["p_success"] - ob["p_success"]) < 1e-9
+    assert abs(ob["norm"] - 1.0) < 1e-12
+    assert abs(oa["norm"] - 1.0) < 1e-5
+
+
+# --------------------------------------------------------------------------
+# n = 20, T = 100, 10^4 steps against stored oracle results
+# --------------------------------------------------------------------------
+
+def _golden_c2():
+    path = os.path.join(GOLDEN, "c2_n20_oracle.json")
+    if not os.path.exists(path):
+        return []
+    with open(path) as f:
+        return json.load(f)["records"]
+
+
+@pytest.mark.parametrize("rec", _golden_c2(), ids=lambda r: "seed%d" % r["seed"])
+def test_n20_T100_10k_steps_vs_stored_oracle(qaa, rec):
+    n = rec["n"]
+    inst_in = planted_unique_3sat(n, rec["seed"])
+    assert inst_in.m == rec["m"] and inst_in.planted == rec["planted"]
+    _, _, st, obs = _run_gpu(qaa, n, inst_in.clauses, rec["T"], rec["steps"])
+    ref = rec["observables"]
+    assert abs(obs["p_success"] - ref["p_success"]) <= P_TOL_C64
+    assert abs(obs["energy"] - ref["energy"]) <= 1e-4
+    assert abs(obs["norm"] - 1.0) <= 1e-4
+    zs = torch.tensor(rec["sample_z"], dtype=torch.int64, device="cuda")
+    got = st.amp[zs].cpu().numpy().astype(np.complex128)
+    exp = np.array([complex(a, b) for a, b in rec["sample_amp"]])
+    # per-amplitude error budget: a state-L2 of 1e-4 spread over 2^20 entries
+    assert np.max(np.abs(got - exp)) <= 1e-4
