@@ -88,6 +88,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=2)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one plain 2 GiB device copy (torch copy_), the reference dispatch for "
+                         "scaling HBM counter readings")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -116,6 +119,15 @@ def main():
     # device buffers (allocated before timing)
     table = torch.empty(1 << n, dtype=torch.uint8, device=dev)
     amp = torch.empty(1 << n, dtype=torch.complex64, device=dev)
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.complex64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d bytes read, %d bytes written" % (src.numel() * 8, dst.numel() * 8))
+        del src, dst
 
     # warm-up: full path on the same buffers, W steps
     log("warm-up (%d steps)" % W)

@@ -210,9 +210,12 @@ class PassDesc(ctypes.Structure):
                 ("cm1A", ctypes.c_double), ("sA", ctypes.c_double), ("cm1B", ctypes.c_double),
                 ("sB", ctypes.c_double), ("phi", ctypes.c_double), ("gphase", ctypes.c_double),
                 ("acc_in", ctypes.c_void_p), ("acc_out", ctypes.c_void_p), ("acc_zero", ctypes.c_void_p),
+                ("goff_first", ctypes.c_uint64 * 32), ("goff_last", ctypes.c_uint64 * 32),
+                ("ljp", (ctypes.c_uint16 * 32) * 12), ("lj", (ctypes.c_uint16 * 32) * 12),
+                ("rest_mask", ctypes.c_uint64),
                 ("tile_pos", ctypes.c_uint8 * 16), ("rest_pos", ctypes.c_uint8 * 40),
-                ("gbits", (ctypes.c_uint8 * 8) * 12), ("tpos", (ctypes.c_uint8 * 16) * 12),
-                ("maskA", ctypes.c_uint8 * 12), ("maskB", ctypes.c_uint8 * 12)]
+                ("tpos", (ctypes.c_uint8 * 16) * 12), ("gpos_first", ctypes.c_uint8 * 16),
+                ("gpos_last", ctypes.c_uint8 * 16), ("masks", ctypes.c_uint32 * 12)]
 
 
 def qaa_debug_pass_descs(n: int, dtype: int, emax: int, T: float, steps: int, k0: int, k1: int):

@@ -12,7 +12,9 @@
 //    evaluated in FP64 and rounded once.
 #include "qaa_internal.h"
 
+#include <algorithm>
 #include <cmath>
+#include <cstddef>
 
 namespace qaa {
 namespace {
@@ -180,32 +182,262 @@ __global__ void __launch_bounds__(256) init_basis_kernel(typename V2<F>::T *__re
 
 // ---------------------------------------------------------------------------
 // One fused pass over 2^TB-amplitude tiles (see PassDesc).
+//
+// The grid is persistent: workgroup b handles tiles b, b + G, b + 2G, ...
+// and keeps two register sets, so the HBM loads of its next tile are in
+// flight while the current tile is rotated, phased and stored.
 // ---------------------------------------------------------------------------
+
+// Workgroup barrier that orders LDS traffic only: HBM loads issued before it
+// stay in flight.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <typename F, typename ET, int TB, int RB>
+struct PassTraits {
+    using F2 = typename V2<F>::T;
+    static constexpr int WB = TB - RB;
+    static constexpr uint32_t WG = 1u << WB;
+    static constexpr int R = 1 << RB;
+    static constexpr uint32_t TS = 1u << TB;
+    static constexpr int DT = sizeof(F) == 4 ? 0 : 1;
+    static constexpr uint32_t TSP = TS + kPadN[DT] * (TS >> kPadS[DT]);
+    static constexpr int VW = 16 / sizeof(F2);     // amplitudes per 16-byte access
+    static constexpr int EPV = 16 / sizeof(ET);    // energies per 16-byte access
+    static constexpr int EB = sizeof(ET) == 1 ? 4 : 3;
+    static constexpr int NE = (int)(TS / EPV / WG) > 0 ? (int)(TS / EPV / WG) : 1;
+};
+
+// Registers holding one tile in flight: residency-0 amplitudes and energies.
+template <typename F, typename ET, int TB, int RB>
+struct TileRegs {
+    typename V2<F>::T v[1 << RB];
+    uint4 ev[PassTraits<F, ET, TB, RB>::NE];
+};
+
+// Physical base index of tile w: bit j of w goes to the j-th set bit of
+// rest_mask (scalar bit scans, no memory access).
+template <typename F, typename ET, int TB, int RB>
+__device__ __forceinline__ uint64_t tile_base(const PassDesc &d, uint64_t w)
+{
+    uint64_t base = 0, m = d.rest_mask;
+    while (w) {
+        const uint64_t low = m & (~m + 1ull);     // lowest remaining position
+        if (w & 1ull) base |= low;
+        m ^= low;
+        w >>= 1;
+    }
+    return base;
+}
+
+// 32-bit word at a byte offset inside the pass descriptor.
+__device__ __forceinline__ uint32_t desc_word(const PassDesc &d, uint32_t byte_off)
+{
+    return *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(&d) + byte_off);
+}
+__device__ __forceinline__ uint32_t desc_u8(const PassDesc &d, uint32_t byte_off)
+{
+    return (desc_word(d, byte_off & ~3u) >> (8 * (byte_off & 3u))) & 0xFFu;
+}
+__device__ __forceinline__ uint32_t desc_u16(const PassDesc &d, uint32_t byte_off)
+{
+    return (desc_word(d, byte_off & ~3u) >> (8 * (byte_off & 2u))) & 0xFFFFu;
+}
+
+// Issue the HBM loads of one tile: residency-0 registers and, for a phase
+// pass, the tile's energies (16 consecutive bytes per access; tile bits 0..3
+// are physical bits 0..3 in every plan).
+template <typename F, typename ET, int TB, int RB, bool PHASE>
+__device__ __forceinline__ void pass_load(TileRegs<F, ET, TB, RB> &tr, const typename V2<F>::T *__restrict__ amp,
+                                          const ET *__restrict__ table, const PassDesc &d, uint64_t base, uint64_t tg,
+                                          uint32_t tid)
+{
+    using P = PassTraits<F, ET, TB, RB>;
+    using F2 = typename P::F2;
+    auto &v = tr.v;
+    auto &ev = tr.ev;
+    const F2 *p = amp + (base | tg);
+#pragma unroll
+    for (int j = 0; j < P::R; j += P::VW) {
+        if constexpr (P::VW == 2) {
+            const float4 q = *reinterpret_cast<const float4 *>(p + d.goff_first[j]);
+            v[j].x = q.x;
+            v[j].y = q.y;
+            v[j + 1].x = q.z;
+            v[j + 1].y = q.w;
+        } else {
+            v[j] = p[d.goff_first[j]];
+        }
+    }
+    if constexpr (PHASE) {
+#pragma unroll
+        for (int i = 0; i < P::NE; ++i) {
+            const uint32_t c = tid + (uint32_t)i * P::WG;
+            uint64_t off = 0;
+#pragma unroll
+            for (int j = 0; j < TB - P::EB; ++j) off |= (uint64_t)((c >> j) & 1u) << d.tile_pos[P::EB + j];
+            ev[i] = *reinterpret_cast<const uint4 *>(table + (base | off));
+        }
+    }
+}
+
+// Residencies of one tile, ending with the store to HBM.
+template <typename F, typename ET, int TB, int RB, bool PHASE>
+__device__ __forceinline__ void pass_compute(TileRegs<F, ET, TB, RB> &tr, typename V2<F>::T *__restrict__ amp,
+                                             const PassDesc &d, uint64_t base,
+                                             uint64_t tg_last, uint32_t tid,
+                                             typename V2<F>::T *tile, const typename V2<F>::T *lut, ET *etile,
+                                             F cm1A, F sA, F cm1B, F sB, double &ss)
+{
+    using P = PassTraits<F, ET, TB, RB>;
+    using F2 = typename P::F2;
+    constexpr int DT = P::DT;
+    constexpr int R = P::R;
+    constexpr int VW = P::VW;
+    auto &v = tr.v;
+    const auto &ev = tr.ev;
+    // the previous tile's LDS reads are finished before this tile writes
+    lds_barrier();
+    if constexpr (PHASE) {
+#pragma unroll
+        for (int i = 0; i < P::NE; ++i)
+            *reinterpret_cast<uint4 *>(etile + (size_t)(tid + (uint32_t)i * P::WG) * P::EPV) = ev[i];
+        lds_barrier();
+    }
+    const int last = d.n_res - 1;
+    // thread part of the tile-local index in residency r
+    auto thread_part = [&](int r) {
+        const uint32_t o_tpos = (uint32_t)offsetof(PassDesc, tpos) + 16u * (uint32_t)r;
+        uint32_t lt = 0;
+#pragma unroll
+        for (int k = 0; k < P::WB; ++k) lt |= ((tid >> k) & 1u) << desc_u8(d, o_tpos + k);
+        return lt;
+    };
+    // rotations and phase of residency r on the registers
+    auto apply = [&](int r, uint32_t lt) {
+        const uint32_t o_lj = (uint32_t)offsetof(PassDesc, lj) + 2u * kMaxRegs * (uint32_t)r;
+        const uint32_t masks = desc_word(d, (uint32_t)offsetof(PassDesc, masks) + 4u * (uint32_t)r);
+        rotate_mask<RB>(v, masks & 0xFFu, cm1A, sA);
+        if (PHASE && r == d.phase_at) {
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const uint32_t e = (uint32_t)etile[lt + desc_u16(d, o_lj + 2 * j)];
+                v[j] = cmul<F2, F>(v[j], lut[e]);
+            }
+        }
+        rotate_mask<RB>(v, (masks >> 8) & 0xFFu, cm1B, sB);
+    };
+    auto to_lds = [&](int r, uint32_t ltp) {
+        const uint32_t o_ljp = (uint32_t)offsetof(PassDesc, ljp) + 2u * kMaxRegs * (uint32_t)r;
+#pragma unroll
+        for (int j = 0; j < R; j += VW) {
+            F2 *q = tile + ltp + desc_u16(d, o_ljp + 2 * j);
+            if constexpr (VW == 2) {
+                float4 t4;
+                t4.x = v[j].x;
+                t4.y = v[j].y;
+                t4.z = v[j + 1].x;
+                t4.w = v[j + 1].y;
+                *reinterpret_cast<float4 *>(q) = t4;
+            } else {
+                *q = v[j];
+            }
+        }
+    };
+    auto from_lds = [&](int r, uint32_t ltp) {
+        const uint32_t o_ljp = (uint32_t)offsetof(PassDesc, ljp) + 2u * kMaxRegs * (uint32_t)r;
+#pragma unroll
+        for (int j = 0; j < R; j += VW) {
+            const F2 *q = tile + ltp + desc_u16(d, o_ljp + 2 * j);
+            if constexpr (VW == 2) {
+                const float4 t4 = *reinterpret_cast<const float4 *>(q);
+                v[j].x = t4.x;
+                v[j].y = t4.y;
+                v[j + 1].x = t4.z;
+                v[j + 1].y = t4.w;
+            } else {
+                v[j] = *q;
+            }
+        }
+    };
+    // residency 0 works on the registers loaded from HBM; it is kept out of
+    // the loop below so that the loop never waits on HBM loads
+    {
+        const uint32_t lt = thread_part(0);
+        apply(0, lt);
+        if (last > 0) {
+            to_lds(0, lt + kPadN[DT] * (lt >> kPadS[DT]));
+            lds_barrier();
+        }
+    }
+    for (int r = 1; r <= last; ++r) {
+        const uint32_t lt = thread_part(r);
+        const uint32_t ltp = lt + kPadN[DT] * (lt >> kPadS[DT]);
+        from_lds(r, ltp);
+        apply(r, lt);
+        if (r < last) {
+            to_lds(r, ltp);
+            lds_barrier();
+        }
+    }
+    F2 *p = amp + (base | tg_last);
+    F st = F(0);       // this tile's share of |psi|^2: R terms in F, then FP64
+#pragma unroll
+    for (int j = 0; j < R; j += VW) {
+#pragma unroll
+        for (int k = 0; k < VW; ++k) st = fma(v[j + k].x, v[j + k].x, fma(v[j + k].y, v[j + k].y, st));
+        if constexpr (VW == 2) {
+            float4 q;
+            q.x = v[j].x;
+            q.y = v[j].y;
+            q.z = v[j + 1].x;
+            q.w = v[j + 1].y;
+            *reinterpret_cast<float4 *>(p + d.goff_last[j]) = q;
+        } else {
+            p[d.goff_last[j]] = v[j];
+        }
+    }
+    ss += (double)st;
+}
+
+template <typename F, typename ET, int TB, int RB, bool PHASE>
 __global__ void __launch_bounds__(1 << (TB - RB))
 pass_kernel(typename V2<F>::T *__restrict__ amp, const ET *__restrict__ table, const PassDesc d)
 {
-    using F2 = typename V2<F>::T;
-    constexpr int WB = TB - RB;
-    constexpr uint32_t WG = 1u << WB;
-    constexpr int R = 1 << RB;
-    constexpr uint32_t TS = 1u << TB;
+    using P = PassTraits<F, ET, TB, RB>;
+    using F2 = typename P::F2;
+    static_assert(P::R <= kMaxRegs, "register count");
     extern __shared__ __align__(16) unsigned char smem[];
     F2 *tile = reinterpret_cast<F2 *>(smem);
-    F2 *lut = tile + TS;
+    F2 *lut = tile + P::TSP;
     ET *etile = reinterpret_cast<ET *>(lut + lut_cap<ET>());
 
     const uint32_t tid = threadIdx.x;
-    const bool has_phase = d.phase_at >= 0;
+    const uint64_t ntiles = 1ull << d.n_rest;
+    const uint64_t G = gridDim.x;
 
-    uint64_t base = 0;
-    {
-        const uint64_t w = blockIdx.x;
-        for (int j = 0; j < d.n_rest; ++j) base |= ((w >> j) & 1ull) << d.rest_pos[j];
+    uint64_t tg_first = 0, tg_last = 0;
+#pragma unroll
+    for (int k = 0; k < P::WB; ++k) {
+        tg_first |= (uint64_t)((tid >> k) & 1u) << d.gpos_first[k];
+        tg_last |= (uint64_t)((tid >> k) & 1u) << d.gpos_last[k];
     }
-    if (has_phase) {
+
+    // The loads of the next tile are issued unconditionally (past the end,
+    // the last tile is read again and not used) so that the number of
+    // memory operations in flight is the same on every path; otherwise the
+    // compiler's wait counts assume the worst path and stall on the prefetch.
+    TileRegs<F, ET, TB, RB> ta, tb;
+    uint64_t w = blockIdx.x;        // grid size <= ntiles, so w is a valid tile
+    pass_load<F, ET, TB, RB, PHASE>(ta, amp, table, d, tile_base<F, ET, TB, RB>(d, w), tg_first, tid);
+
+    if constexpr (PHASE) {
         const double scale = d.acc_in ? rsqrt((double)(*d.acc_in) * (1.0 / kNormFixedScale)) : 1.0;
-        for (int e = (int)tid; e <= d.emax; e += (int)WG) {
+        for (int e = (int)tid; e <= d.emax; e += (int)P::WG) {
             double sn, cs;
             sincos(fma(d.phi, (double)e, d.gphase), &sn, &cs);
             F2 L;
@@ -216,132 +448,33 @@ pass_kernel(typename V2<F>::T *__restrict__ amp, const ET *__restrict__ table, c
     }
     if (d.acc_zero && blockIdx.x == 0 && tid == 0) *d.acc_zero = 0ull;
 
-    // global -> registers -> LDS.  Each access moves 16 bytes: VW
-    // consecutive amplitudes (tile bit 0 is physical bit 0, so pairs are
-    // adjacent in memory).  Vector v = tid + i * WG covers tile-local
-    // indices VW*v .. VW*v + VW-1.  All loads are issued before the first
-    // LDS store so that every thread has R loads in flight.
-    constexpr int VW = 16 / sizeof(F2);          // amplitudes per 16-byte access
-    constexpr int NV = R / VW;                   // vector accesses per thread
-    constexpr int VB = VW == 2 ? 1 : 0;          // log2(VW)
-    uint64_t off_t = 0;
-#pragma unroll
-    for (int j = 0; j < WB; ++j) off_t |= (uint64_t)((tid >> j) & 1u) << d.tile_pos[VB + j];
-    uint64_t goff[NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        uint64_t off_i = 0;
-#pragma unroll
-        for (int j = 0; j < RB - VB; ++j)
-            if ((i >> j) & 1) off_i |= 1ull << d.tile_pos[VB + WB + j];
-        goff[i] = base | off_t | off_i;
-    }
-    {
-        F2 v[R];
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            if constexpr (VW == 2) {
-                const float4 q = *reinterpret_cast<const float4 *>(amp + goff[i]);
-                v[2 * i].x = q.x;
-                v[2 * i].y = q.y;
-                v[2 * i + 1].x = q.z;
-                v[2 * i + 1].y = q.w;
-            } else {
-                v[i] = amp[goff[i]];
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < NV; ++i)
-#pragma unroll
-            for (int k = 0; k < VW; ++k) tile[swz<F>((uint32_t)(VW * (tid + i * WG) + k))] = v[VW * i + k];
-    }
-    if (has_phase) {
-        // energies: 16 consecutive bytes (tile bits 0..3 are physical bits
-        // 0..3 in every plan) per access
-        constexpr int EPV = 16 / sizeof(ET);                  // entries per 16-byte access
-        constexpr int EB = sizeof(ET) == 1 ? 4 : 3;           // log2(EPV)
-        constexpr int NE = (int)(TS / EPV / WG) > 0 ? (int)(TS / EPV / WG) : 1;
-        uint4 ev[NE];
-#pragma unroll
-        for (int i = 0; i < NE; ++i) {
-            const uint32_t c = tid + (uint32_t)i * WG;          // chunk index
-            uint64_t off = 0;
-#pragma unroll
-            for (int j = 0; j < TB - EB; ++j) off |= (uint64_t)((c >> j) & 1u) << d.tile_pos[EB + j];
-            ev[i] = *reinterpret_cast<const uint4 *>(table + (base | off));
-        }
-#pragma unroll
-        for (int i = 0; i < NE; ++i) {
-            const uint32_t c = tid + (uint32_t)i * WG;
-            *reinterpret_cast<uint4 *>(etile + (size_t)c * EPV) = ev[i];
-        }
-    }
-    __syncthreads();
-
     const F cm1A = (F)d.cm1A, sA = (F)d.sA, cm1B = (F)d.cm1B, sB = (F)d.sB;
-    for (int r = 0; r < d.n_res; ++r) {
-        uint32_t lt = 0;
-#pragma unroll
-        for (int k = 0; k < WB; ++k) lt |= ((tid >> k) & 1u) << d.tpos[r][k];
-        const uint32_t slt = swz<F>(lt);
-        uint32_t lj[R];
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-            uint32_t x = 0;
-#pragma unroll
-            for (int i = 0; i < RB; ++i)
-                if ((j >> i) & 1) x |= 1u << d.gbits[r][i];
-            lj[j] = x;
-        }
-        F2 v[R];
-#pragma unroll
-        for (int j = 0; j < R; ++j) v[j] = tile[slt ^ swz<F>(lj[j])];
-        rotate_mask<RB>(v, d.maskA[r], cm1A, sA);
-        if (r == d.phase_at) {
-#pragma unroll
-            for (int j = 0; j < R; ++j) {
-                const uint32_t e = (uint32_t)etile[lt | lj[j]];
-                v[j] = cmul<F2, F>(v[j], lut[e]);
-            }
-        }
-        rotate_mask<RB>(v, d.maskB[r], cm1B, sB);
-#pragma unroll
-        for (int j = 0; j < R; ++j) tile[slt ^ swz<F>(lj[j])] = v[j];
-        __syncthreads();
+    double ss = 0.0;
+    while (true) {
+        const uint64_t w1 = w + G;
+        pass_load<F, ET, TB, RB, PHASE>(tb, amp, table, d, tile_base<F, ET, TB, RB>(d, w1 < ntiles ? w1 : w), tg_first,
+                                        tid);
+        pass_compute<F, ET, TB, RB, PHASE>(ta, amp, d, tile_base<F, ET, TB, RB>(d, w), tg_last, tid, tile, lut, etile,
+                                           cm1A, sA, cm1B, sB, ss);
+        if (w1 >= ntiles) break;
+        const uint64_t w2 = w1 + G;
+        pass_load<F, ET, TB, RB, PHASE>(ta, amp, table, d, tile_base<F, ET, TB, RB>(d, w2 < ntiles ? w2 : w1),
+                                        tg_first, tid);
+        pass_compute<F, ET, TB, RB, PHASE>(tb, amp, d, tile_base<F, ET, TB, RB>(d, w1), tg_last, tid, tile, lut, etile,
+                                           cm1A, sA, cm1B, sB, ss);
+        if (w2 >= ntiles) break;
+        w = w2;
     }
 
-    F ss = F(0);
-    {
-        F2 v[R];
-#pragma unroll
-        for (int i = 0; i < NV; ++i)
-#pragma unroll
-            for (int k = 0; k < VW; ++k) v[VW * i + k] = tile[swz<F>((uint32_t)(VW * (tid + i * WG) + k))];
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-#pragma unroll
-            for (int k = 0; k < VW; ++k) ss = fma(v[VW * i + k].x, v[VW * i + k].x, fma(v[VW * i + k].y, v[VW * i + k].y, ss));
-            if constexpr (VW == 2) {
-                float4 q;
-                q.x = v[2 * i].x;
-                q.y = v[2 * i].y;
-                q.z = v[2 * i + 1].x;
-                q.w = v[2 * i + 1].y;
-                *reinterpret_cast<float4 *>(amp + goff[i]) = q;
-            } else {
-                amp[goff[i]] = v[i];
-            }
-        }
-    }
     if (d.acc_out) {
-        double t = (double)ss;
+        double t = ss;
         for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-        __shared__ double wsum[WG / 64];
+        __shared__ double wsum[P::WG / 64];
         if ((tid & 63) == 0) wsum[tid >> 6] = t;
         __syncthreads();
         if (tid == 0) {
             double b = 0.0;
-            for (int w = 0; w < (int)(WG / 64); ++w) b += wsum[w];
+            for (int k = 0; k < (int)(P::WG / 64); ++k) b += wsum[k];
             atomicAdd(d.acc_out, (unsigned long long)(b * kNormFixedScale + 0.5));
         }
     }
@@ -555,22 +688,39 @@ inline unsigned grid_for(uint64_t work, unsigned per_block, unsigned cap)
     return (unsigned)g;
 }
 
+template <typename F, typename ET, int TB, int RB, bool PHASE>
+hipError_t launch_pass_p(void *amp, const void *table, const PassDesc &d, hipStream_t s)
+{
+    using F2 = typename V2<F>::T;
+    constexpr int DT = sizeof(F) == 4 ? 0 : 1;
+    constexpr size_t TS = size_t(1) << TB;
+    const size_t lds = sizeof(F2) * (TS + kPadN[DT] * (TS >> kPadS[DT]) + lut_cap<ET>()) + sizeof(ET) * TS;
+    // persistent grid: as many workgroups as fit on the device at once
+    static unsigned resident = 0;
+    if (!resident) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&pass_kernel<F, ET, TB, RB, PHASE>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        int dev = 0, cus = 0, per_cu = 0;
+        if (e == hipSuccess) e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, reinterpret_cast<const void *>(&pass_kernel<F, ET, TB, RB, PHASE>), 1 << (TB - RB), lds);
+        if (e != hipSuccess) return e;
+        resident = (unsigned)std::max(1, cus * std::max(1, per_cu));
+    }
+    const uint64_t ntiles = 1ull << (d.n - TB);
+    const unsigned grid = (unsigned)std::min<uint64_t>(ntiles, resident);
+    hipLaunchKernelGGL((pass_kernel<F, ET, TB, RB, PHASE>), dim3(grid), dim3(1u << (TB - RB)), lds, s,
+                       reinterpret_cast<F2 *>(amp), reinterpret_cast<const ET *>(table), d);
+    return hipGetLastError();
+}
+
 template <typename F, typename ET, int TB, int RB>
 hipError_t launch_pass_t(void *amp, const void *table, const PassDesc &d, hipStream_t s)
 {
-    using F2 = typename V2<F>::T;
-    const size_t lds = sizeof(F2) * ((size_t(1) << TB) + lut_cap<ET>()) + sizeof(ET) * (size_t(1) << TB);
-    static bool attr_done = false;
-    if (!attr_done) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&pass_kernel<F, ET, TB, RB>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_done = true;
-    }
-    const unsigned grid = 1u << (d.n - TB);
-    hipLaunchKernelGGL((pass_kernel<F, ET, TB, RB>), dim3(grid), dim3(1u << (TB - RB)), lds, s,
-                       reinterpret_cast<F2 *>(amp), reinterpret_cast<const ET *>(table), d);
-    return hipGetLastError();
+    if (d.phase_at >= 0) return launch_pass_p<F, ET, TB, RB, true>(amp, table, d, s);
+    return launch_pass_p<F, ET, TB, RB, false>(amp, table, d, s);
 }
 
 template <typename F, typename ET, int RB, int WB>

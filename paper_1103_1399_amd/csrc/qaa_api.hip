@@ -352,27 +352,57 @@ Plan make_plan(int n, int dtype)
     return p;
 }
 
-// Split rotated tile-local bits into register groups of rb bits (highest
-// bits first); each group is padded with non-rotated filler bits.  Returns
-// per group: the rb tile bits (rotated ones first) and the rotated count.
+// Register groups for one qubit set.  The set's rotated tile-local bits are
+// split, highest first, into groups that fill the rb register bits of a
+// residency; bits a group does not rotate are fillers taken from the top of
+// the tile.  For complex64 (vw = 2) register bit 0 is tile bit 0 in every
+// group, so register pairs are adjacent in memory; tile bit 0 itself is
+// rotated (if it belongs to the set) only in the first group.
 struct Group {
-    std::vector<int> bits;
-    int nrot;
+    std::vector<int> bits;   // bits[i] = tile bit of register bit i (size rb)
+    uint32_t rot;            // register bits this group rotates
 };
 
-std::vector<Group> make_groups(const std::vector<int> &rot, int tb, int rb)
+bool contains(const std::vector<int> &v, int b) { return std::find(v.begin(), v.end(), b) != v.end(); }
+
+std::vector<Group> make_groups(const std::vector<int> &rot, int tb, int rb, int vw)
 {
-    std::vector<int> order(rot.rbegin(), rot.rend());
+    std::vector<int> members;
+    bool rot0 = false;
+    for (int b : rot) {
+        if (vw == 2 && b == 0)
+            rot0 = true;
+        else
+            members.push_back(b);
+    }
+    std::sort(members.rbegin(), members.rend());
+    const int cap = vw == 2 ? rb - 1 : rb;
     std::vector<Group> gs;
-    for (size_t i = 0; i < order.size(); i += rb) {
+    for (size_t i = 0; i < members.size() || (gs.empty() && rot0); i += cap) {
         Group g;
-        for (size_t j = i; j < std::min(order.size(), i + rb); ++j) g.bits.push_back(order[j]);
-        g.nrot = (int)g.bits.size();
+        g.rot = 0;
+        if (vw == 2) {
+            g.bits.push_back(0);
+            if (rot0 && gs.empty()) g.rot |= 1u;
+        }
+        for (size_t j = i; j < std::min(members.size(), i + cap); ++j) {
+            g.rot |= 1u << g.bits.size();
+            g.bits.push_back(members[j]);
+        }
         for (int b = tb - 1; b >= 0 && (int)g.bits.size() < rb; --b)
-            if (std::find(g.bits.begin(), g.bits.end(), b) == g.bits.end()) g.bits.push_back(b);
+            if (!contains(g.bits, b)) g.bits.push_back(b);
         gs.push_back(g);
     }
     return gs;
+}
+
+// A group may talk to HBM directly when its thread-index bits start with
+// the tile's low bits, so that each wave touches >= 256 contiguous bytes.
+bool io_capable(const Group &g, int vw)
+{
+    for (int b = vw == 2 ? 1 : 0; b < (vw == 2 ? 5 : 4); ++b)
+        if (contains(g.bits, b)) return false;
+    return true;
 }
 
 struct StepCoef {
@@ -396,44 +426,68 @@ double wrap_phase(double a)
     return std::fmod(a, 2.0 * M_PI);
 }
 
+uint32_t pad_index(uint32_t l, int dt) { return l + (uint32_t)kPadN[dt] * (l >> kPadS[dt]); }
+
 // Residency list for one pass over set `sp`:
 //   v1: rotate with coefficient set A before the phase,
 //   ph: apply the phase,
 //   v2: rotate with coefficient set B after the phase.
-void fill_residencies(PassDesc &d, const SetPlan &sp, int tb, int rb, bool v1, bool ph, bool v2)
+// The first and last residencies move the tile between HBM and registers,
+// so both use a group whose register bits avoid the tile's low bits.
+void fill_residencies(PassDesc &d, const SetPlan &sp, int tb, int rb, int dt, bool v1, bool ph, bool v2)
 {
-    const std::vector<Group> gs = make_groups(sp.rot_local, tb, rb);
+    const int vw = dt == 0 ? 2 : 1;
+    const std::vector<Group> gs = make_groups(sp.rot_local, tb, rb, vw);
     const int G = (int)gs.size();
     struct Res {
         int g;
-        uint8_t ma, mb;
+        uint32_t ma, mb;
         bool phase;
     };
     std::vector<Res> rs;
-    auto full = [&](int g) { return (uint8_t)((1u << gs[g].nrot) - 1u); };
     if (v1 && ph && v2) {
-        for (int g = 0; g < G - 1; ++g) rs.push_back({g, full(g), 0, false});
-        rs.push_back({G - 1, full(G - 1), full(G - 1), true});
-        for (int g = G - 2; g >= 0; --g) rs.push_back({g, 0, full(g), false});
+        for (int g = 0; g < G - 1; ++g) rs.push_back({g, gs[g].rot, 0, false});
+        rs.push_back({G - 1, gs[G - 1].rot, gs[G - 1].rot, true});
+        for (int g = G - 2; g >= 0; --g) rs.push_back({g, 0, gs[g].rot, false});
     } else if (v1 && ph) {
-        for (int g = 0; g < G - 1; ++g) rs.push_back({g, full(g), 0, false});
-        rs.push_back({G - 1, full(G - 1), 0, true});
+        for (int g = 0; g < G - 1; ++g) rs.push_back({g, gs[g].rot, 0, false});
+        rs.push_back({G - 1, gs[G - 1].rot, 0, true});
     } else if (ph && v2) {
-        rs.push_back({0, 0, full(0), true});
-        for (int g = 1; g < G; ++g) rs.push_back({g, 0, full(g), false});
+        rs.push_back({0, 0, gs[0].rot, true});
+        for (int g = 1; g < G; ++g) rs.push_back({g, 0, gs[g].rot, false});
     } else {
-        for (int g = 0; g < G; ++g) rs.push_back({g, full(g), 0, false});
+        for (int g = 0; g < G; ++g) rs.push_back({g, gs[g].rot, 0, false});
     }
+    if (!io_capable(gs[rs.front().g], vw)) rs.insert(rs.begin(), Res{0, 0, 0, false});
+    if (!io_capable(gs[rs.back().g], vw)) rs.push_back(Res{0, 0, 0, false});
+
+    const int wb = tb - rb;
+    const int R = 1 << rb;
     d.n_res = (int)rs.size();
     d.phase_at = -1;
     for (int r = 0; r < d.n_res; ++r) {
         const Group &g = gs[rs[r].g];
-        for (int i = 0; i < rb; ++i) d.gbits[r][i] = (uint8_t)g.bits[i];
         int k = 0;
         for (int b = 0; b < tb; ++b)
-            if (std::find(g.bits.begin(), g.bits.end(), b) == g.bits.end()) d.tpos[r][k++] = (uint8_t)b;
-        d.maskA[r] = rs[r].ma;
-        d.maskB[r] = rs[r].mb;
+            if (!contains(g.bits, b)) d.tpos[r][k++] = (uint8_t)b;
+        for (int j = 0; j < R; ++j) {
+            uint32_t l = 0;
+            uint64_t gl = 0;
+            for (int i = 0; i < rb; ++i)
+                if ((j >> i) & 1) {
+                    l |= 1u << g.bits[i];
+                    gl |= 1ull << sp.tile[g.bits[i]];
+                }
+            d.lj[r][j] = (uint16_t)l;
+            d.ljp[r][j] = (uint16_t)pad_index(l, dt);
+            if (r == 0) d.goff_first[j] = gl;
+            if (r == d.n_res - 1) d.goff_last[j] = gl;
+        }
+        if (r == 0)
+            for (int kk = 0; kk < wb; ++kk) d.gpos_first[kk] = (uint8_t)sp.tile[d.tpos[0][kk]];
+        if (r == d.n_res - 1)
+            for (int kk = 0; kk < wb; ++kk) d.gpos_last[kk] = (uint8_t)sp.tile[d.tpos[r][kk]];
+        d.masks[r] = rs[r].ma | (rs[r].mb << 8);
         if (rs[r].phase) d.phase_at = r;
     }
 }
@@ -456,14 +510,14 @@ qaa_status run_resident(const qaa_state *st, double T, int64_t N, int64_t k0, in
     d.thr_bits = n - d.reg_bits;
     std::vector<int> rot;
     for (int b = 0; b < n; ++b) rot.push_back(b);
-    const std::vector<Group> gs = make_groups(rot, n, d.reg_bits);
+    const std::vector<Group> gs = make_groups(rot, n, d.reg_bits, 1);
     d.n_groups = (int)gs.size();
     for (int g = 0; g < d.n_groups; ++g) {
         for (int i = 0; i < d.reg_bits; ++i) d.gbits[g][i] = (uint8_t)gs[g].bits[i];
         int k = 0;
         for (int b = 0; b < n; ++b)
             if (std::find(gs[g].bits.begin(), gs[g].bits.end(), b) == gs[g].bits.end()) d.tpos[g][k++] = (uint8_t)b;
-        d.gmask[g] = (uint8_t)((1u << gs[g].nrot) - 1u);
+        d.gmask[g] = (uint8_t)gs[g].rot;
     }
     QAA_HIP(launch_resident(nullptr, &d, 1, dt, (int)st->etype, s));
     return QAA_OK;
@@ -473,7 +527,8 @@ qaa_status run_resident(const qaa_state *st, double T, int64_t N, int64_t k0, in
 // visited forward on even steps (relative to k0) and backward on odd ones,
 // so the set that ends step k also starts step k+1 and one pass applies
 // both its rotations and the merged diagonal phase between them.
-std::vector<PassDesc> build_passes(const Plan &p, int n, int emax, double T, int64_t N, int64_t k0, int64_t k1)
+std::vector<PassDesc> build_passes(const Plan &p, int n, int dty, int emax, double T, int64_t N, int64_t k0,
+                                   int64_t k1)
 {
     std::vector<PassDesc> out;
     const int TB = p.tile_bits, RB = p.reg_bits;
@@ -494,8 +549,12 @@ std::vector<PassDesc> build_passes(const Plan &p, int n, int emax, double T, int
             const SetPlan &sp = p.sets[set];
             for (int j = 0; j < TB; ++j) d.tile_pos[j] = (uint8_t)sp.tile[j];
             int nr = 0;
+            d.rest_mask = 0;
             for (int b = 0; b < n; ++b)
-                if (std::find(sp.tile.begin(), sp.tile.end(), b) == sp.tile.end()) d.rest_pos[nr++] = (uint8_t)b;
+                if (std::find(sp.tile.begin(), sp.tile.end(), b) == sp.tile.end()) {
+                    d.rest_pos[nr++] = (uint8_t)b;
+                    d.rest_mask |= 1ull << b;
+                }
             d.n_rest = nr;
             if (first) {
                 // k == k0: half phase of step k0, then this set's rotations
@@ -503,7 +562,7 @@ std::vector<PassDesc> build_passes(const Plan &p, int n, int emax, double T, int
                 d.gphase = 0.0;
                 d.cm1B = ck.cm1;
                 d.sB = ck.sn;
-                fill_residencies(d, sp, TB, RB, false, true, true);
+                fill_residencies(d, sp, TB, RB, dty, false, true, true);
             } else if (last && k + 1 < k1) {
                 const StepCoef cn = step_coef(T, N, k + 1);
                 d.cm1A = ck.cm1;
@@ -512,17 +571,17 @@ std::vector<PassDesc> build_passes(const Plan &p, int n, int emax, double T, int
                 d.gphase = wrap_phase(0.5 * n * ck.theta);
                 d.cm1B = cn.cm1;
                 d.sB = cn.sn;
-                fill_residencies(d, sp, TB, RB, true, true, true);
+                fill_residencies(d, sp, TB, RB, dty, true, true, true);
             } else if (last) {
                 d.cm1A = ck.cm1;
                 d.sA = ck.sn;
                 d.phi = 0.5 * dt * ck.s;
                 d.gphase = wrap_phase(0.5 * n * ck.theta);
-                fill_residencies(d, sp, TB, RB, true, true, false);
+                fill_residencies(d, sp, TB, RB, dty, true, true, false);
             } else {
                 d.cm1A = ck.cm1;
                 d.sA = ck.sn;
-                fill_residencies(d, sp, TB, RB, true, false, false);
+                fill_residencies(d, sp, TB, RB, dty, true, false, false);
             }
             out.push_back(d);
         }
@@ -596,7 +655,7 @@ bool norm_control_enabled()
 qaa_status run_passes(const qaa_state *st, const Plan &p, double T, int64_t N, int64_t k0, int64_t k1,
                       hipStream_t s)
 {
-    std::vector<PassDesc> ps = build_passes(p, st->inst->n, st->inst->e_max, T, N, k0, k1);
+    std::vector<PassDesc> ps = build_passes(p, st->inst->n, (int)st->dtype, st->inst->e_max, T, N, k0, k1);
     unsigned long long *acc = nullptr;
     if (norm_control_enabled()) {
         QAA_HIP(hipMallocAsync(reinterpret_cast<void **>(&acc), 3 * sizeof(unsigned long long), s));
@@ -747,7 +806,7 @@ extern "C" qaa_status qaa_debug_pass_descs(int32_t n, qaa_dtype dtype, int32_t e
         *count = 0;
         return ok();
     }
-    const std::vector<PassDesc> ps = build_passes(p, n, emax, T, steps, k0, k1);
+    const std::vector<PassDesc> ps = build_passes(p, n, (int)dtype, emax, T, steps, k0, k1);
     *count = (int32_t)ps.size();
     if (out && capacity > 0)
         std::memcpy(out, ps.data(), sizeof(PassDesc) * std::min<size_t>(ps.size(), (size_t)capacity));

@@ -30,17 +30,29 @@ struct ClauseRec {
 // A tile is the set of basis states that agree on all bits outside
 // tile_pos[0..TB): tile-local index l (TB bits) maps to the physical index
 // by placing bit j of l at bit tile_pos[j]; the workgroup id is spread over
-// rest_pos[0..n_rest) the same way.  Inside the workgroup the tile sits in
-// LDS; a "residency" loads it into registers so that register bit i of
-// every thread is tile-local bit gbits[r][i] (the other tile bits index the
-// threads), applies the operations of that residency, and stores it back:
-//   1. rotations on the register bits in maskA[r] with coefficient set A,
+// rest_pos[0..n_rest) the same way.  The tile is processed in a sequence of
+// "residencies".  In residency r every thread holds 2^RB amplitudes in
+// registers: register index j and thread index t address tile-local index
+//     l = lt_r(t) | lj_r(j),   lt_r(t) = sum_k bit_k(t) << tpos[r][k],
+// where lj_r(j) places the register bits on the residency's register group.
+// Residency 0 loads its registers from HBM and the last residency stores
+// them to HBM (goff_*/gpos_* give those global offsets); in between, the
+// tile passes through LDS (padded index, ljp = padded lj).  Each residency:
+//   1. rotations on the register bits in maskA (masks[r] & 0xff) with
+//      coefficient set A,
 //   2. if r == phase_at: the diagonal phase exp(-i (phi E + gphase)),
-//   3. rotations on the register bits in maskB[r] with coefficient set B.
+//   3. rotations on the register bits in maskB (masks[r] >> 8) with
+//      coefficient set B.
 // A rotation is the single-qubit factor of exp(-i theta H_B) without its
 // global phase: [[c, i s], [i s, c]], c = cos(theta/2), s = sin(theta/2),
 // given as cm1 = c - 1 = -2 sin^2(theta/4) (accurate for small theta) and s.
 // The global phase exp(-i n theta / 2) of each step is folded into gphase.
+// The kernel reads the per-residency tables as whole 32-bit words so that
+// they come through the scalar cache (a sub-word load at a run-time index
+// would be a vector memory load, and waiting for it would also wait for the
+// HBM prefetch of the next tile).
+// For complex64, register bit 0 is always tile bit 0 (= physical bit 0), so
+// register pairs (j, j+1) are adjacent in memory and move as 16 bytes.
 //
 // Norm control: rounding in FP32 does not keep |psi|^2 = 1, and on the
 // nearly uniform states of the early sweep all amplitudes round alike, so
@@ -49,6 +61,7 @@ struct ClauseRec {
 // order-independent, hence deterministic), clears acc_zero for the pass
 // after it, and a pass with a phase divides its LUT by sqrt(*acc_in), the
 // norm measured by the pass before it (acc_in == nullptr: no rescale).
+constexpr int kMaxRegs = 32;
 struct PassDesc {
     int32_t n;
     int32_t n_rest;
@@ -61,13 +74,23 @@ struct PassDesc {
     unsigned long long *acc_in;
     unsigned long long *acc_out;
     unsigned long long *acc_zero;
+    uint64_t goff_first[kMaxRegs];     // residency 0: global offset of register j
+    uint64_t goff_last[kMaxRegs];      // last residency: global offset of register j
+    uint16_t ljp[kMaxRes][kMaxRegs];   // residency r: padded LDS offset of register j
+    uint16_t lj[kMaxRes][kMaxRegs];    // residency r: tile-local offset of register j
+    uint64_t rest_mask;                // physical bits outside the tile (= rest_pos as a mask)
     uint8_t tile_pos[16];
     uint8_t rest_pos[40];
-    uint8_t gbits[kMaxRes][8];     // residency r: tile bit of register bit i
-    uint8_t tpos[kMaxRes][16];     // residency r: tile bit of thread-index bit k
-    uint8_t maskA[kMaxRes];
-    uint8_t maskB[kMaxRes];
+    uint8_t tpos[kMaxRes][16];         // residency r: tile bit of thread-index bit k
+    uint8_t gpos_first[16];            // residency 0: physical bit of thread-index bit k
+    uint8_t gpos_last[16];             // last residency: physical bit of thread-index bit k
+    uint32_t masks[kMaxRes];           // residency r: maskA | maskB << 8 (register-bit masks)
 };
+
+// LDS padding of the tile: element index l is stored at
+// l + kPadN[dtype] * (l >> kPadS[dtype]) (additive over disjoint bits).
+constexpr int kPadN[2] = {2, 1};
+constexpr int kPadS[2] = {5, 4};
 
 // Whole-state-in-one-workgroup evolution (n <= tile bits): the workgroup
 // runs all steps k0..k1-1 of one state without leaving LDS, and rescales by

@@ -289,8 +289,10 @@ def test_full_size_driver_only_closed_form(qaa):
     got = st.amp[torch.from_numpy(zs).cuda()].cpu().numpy().astype(np.complex128)
     d = np.array([bin(int(z) ^ z0).count("1") for z in zs])
     expect = a ** (n - d) * b ** d
-    assert np.max(np.abs(got - expect)) < 1e-6
-    assert abs(obs["norm"] - 1.0) < 1e-5
+    # FP32 rounding of ~n rotations per step, each step: well under 1e-5
+    # relative to the largest amplitude
+    assert np.max(np.abs(got - expect)) < 2e-6
+    assert abs(obs["norm"] - 1.0) < 1e-6
 
 
 def test_full_size_c64_vs_c128_first_steps(qaa):

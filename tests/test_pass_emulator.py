@@ -27,8 +27,8 @@ def _pdep(x, positions):
     return out
 
 
-def _swz_c64(l):
-    return l ^ (((l >> 5) ^ (l >> 10)) & 31)
+def _pad(l, dtype):
+    return l + (2 * (l >> 5) if dtype == 0 else (l >> 4))
 
 
 def _replay(n, dtype, E, psi, T, N, k0, k1):
@@ -37,6 +37,7 @@ def _replay(n, dtype, E, psi, T, N, k0, k1):
     RB = 5 if dtype == qaa.QAA_C64 else 4
     WB = TB - RB
     R, WG = 1 << RB, 1 << WB
+    TSP = _pad(1 << TB, dtype)
     descs = qaa.qaa_debug_pass_descs(n, dtype, int(E.max()), T, N, k0, k1)
     tid = np.arange(WG, dtype=np.int64)
     reg = np.arange(R, dtype=np.int64)
@@ -44,28 +45,46 @@ def _replay(n, dtype, E, psi, T, N, k0, k1):
         tile_pos = list(d.tile_pos[:TB])
         rest_pos = list(d.rest_pos[:d.n_rest])
         assert sorted(tile_pos + rest_pos) == list(range(n))
+        assert d.rest_mask == sum(1 << b for b in rest_pos)
+        assert tile_pos[:4] == [0, 1, 2, 3]             # 16-byte energy chunks are contiguous
         blocks = np.arange(1 << d.n_rest, dtype=np.int64)
         base = _pdep(blocks, rest_pos)                                  # [B]
-        # load layout: l = tid + i * WG
-        l_load = (tid[:, None] + reg[None, :] * WG)                     # [WG, R]
-        off = _pdep(l_load, tile_pos)                                   # [WG, R]
-        g = base[:, None, None] | off[None]                             # [B, WG, R]
-        flat = g.reshape(-1)
-        assert np.array_equal(np.sort(flat), np.arange(1 << n))
-        tiles = np.empty((blocks.size, 1 << TB), np.complex128)
-        tiles[:, l_load.reshape(-1)] = psi[g.reshape(blocks.size, -1)]
-        etile = np.empty((blocks.size, 1 << TB), np.int64)
-        etile[:, l_load.reshape(-1)] = E[g.reshape(blocks.size, -1)]
-        assert np.array_equal(np.sort(_swz_c64(np.arange(1 << TB))), np.arange(1 << TB))
+        last = d.n_res - 1
+        lts, ljs = [], []
+        for r in range(d.n_res):
+            tp = list(d.tpos[r][:WB])
+            lj = np.array(list(d.lj[r][:R]), dtype=np.int64)
+            ljp = np.array(list(d.ljp[r][:R]), dtype=np.int64)
+            assert np.array_equal(ljp, _pad(lj, dtype))
+            lt = _pdep(tid, tp)
+            l = lt[:, None] | lj[None, :]                                # [WG, R]
+            assert np.array_equal(np.sort(l.reshape(-1)), np.arange(1 << TB))
+            # padded LDS slots: in range and distinct
+            lp = _pad(lt, dtype)[:, None] + ljp[None, :]
+            assert lp.max() < TSP and np.unique(lp).size == lp.size
+            if dtype == 0:                                              # register pairs adjacent
+                assert np.all(lj[1::2] == lj[0::2] + 1)
+            lts.append(lt)
+            ljs.append(lj)
+        # global maps of the first and last residency agree with the tile map
+        for r, gpos, goff in ((0, d.gpos_first, d.goff_first), (last, d.gpos_last, d.goff_last)):
+            tg = _pdep(tid, list(gpos[:WB]))
+            gof = np.array(list(goff[:R]), dtype=np.int64)
+            g_direct = tg[:, None] | gof[None, :]
+            g_tile = _pdep(lts[r][:, None] | ljs[r][None, :], tile_pos)
+            assert np.array_equal(g_direct, g_tile)
+            if dtype == 0:                                              # lanes cover contiguous 256 B
+                assert list(gpos[:4]) == [1, 2, 3, 4]
+            else:
+                assert list(gpos[:4]) == [0, 1, 2, 3]
+        l_all = np.arange(1 << TB, dtype=np.int64)
+        g = base[:, None] | _pdep(l_all, tile_pos)[None, :]             # [B, TS]
+        assert np.array_equal(np.sort(g.reshape(-1)), np.arange(1 << n))
+        tiles = psi[g]
+        etile = E[g]
         lut = np.exp(-1j * (d.phi * np.arange(int(E.max()) + 1) + d.gphase))
         for r in range(d.n_res):
-            gb = list(d.gbits[r][:RB])
-            tp = list(d.tpos[r][:WB])
-            assert sorted(gb + tp) == list(range(TB))
-            lt = _pdep(tid, tp)
-            lj = _pdep(reg, gb)
-            l = lt[:, None] | lj[None, :]                               # [WG, R]
-            assert np.array_equal(np.sort(l.reshape(-1)), np.arange(1 << TB))
+            l = lts[r][:, None] | ljs[r][None, :]
             v = tiles[:, l]                                             # [B, WG, R]
 
             def rot(v, mask, cm1, s):
@@ -79,12 +98,12 @@ def _replay(n, dtype, E, psi, T, N, k0, k1):
                         v[..., hi] = c * x1 + 1j * s * x0
                 return v
 
-            v = rot(v, d.maskA[r], d.cm1A, d.sA)
+            v = rot(v, d.masks[r] & 0xFF, d.cm1A, d.sA)
             if r == d.phase_at:
                 v = v * lut[etile[:, l]]
-            v = rot(v, d.maskB[r], d.cm1B, d.sB)
+            v = rot(v, (d.masks[r] >> 8) & 0xFF, d.cm1B, d.sB)
             tiles[:, l] = v
-        psi[g.reshape(blocks.size, -1)] = tiles[:, l_load.reshape(-1)]
+        psi[g] = tiles
     return psi, descs
 
 
