@@ -79,6 +79,100 @@ def cpu_baseline(inst, n, T, N, sample_steps):
     }
 
 
+def _percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    i = min(len(xs) - 1, max(0, int(math.ceil(q / 100.0 * len(xs))) - 1))
+    return xs[i]
+
+
+def run_batch(qaa, torch, count, seed, loop_sample):
+    """Batched solves: `count` instances (n ~ U{12..22}, T ~ U[10, 100),
+    steps = round(T/0.01)) evolved together by qaa_evolve_batch; compared
+    with one qaa_evolve call per instance on the first `loop_sample` of them."""
+    from qaa_inputs import batch_workload, planted_unique_3sat
+    wl = batch_workload(count, seed)
+    dev = torch.device("cuda:0")
+    insts, states, keep = [], [], []
+    for n, T, steps, iseed in wl:
+        inst = qaa.Instance(n, planted_unique_3sat(n, iseed).literals())
+        table = inst.energy_table()
+        amp = torch.empty(1 << n, dtype=torch.complex64, device=dev)
+        st = qaa.make_state(inst.handle, amp, table, qaa.QAA_E_U8)
+        insts.append(inst)
+        states.append(st)
+        keep.append((amp, table))
+    Ts = [w[1] for w in wl]
+    Ns = [w[2] for w in wl]
+    amp_steps = sum((1 << w[0]) * w[2] for w in wl)
+    for st in states:
+        qaa.qaa_state_init_uniform(st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    qaa.qaa_evolve_batch(states, Ts, Ns)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    p_batch = [qaa.qaa_observables(st)["p_success"] for st in states[:loop_sample]]
+    # per-instance launches on the same states, same accuracy (same kernels)
+    for st in states[:loop_sample]:
+        qaa.qaa_state_init_uniform(st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for st, T, N in zip(states[:loop_sample], Ts, Ns):
+        qaa.qaa_evolve(st, T, N)
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    p_loop = [qaa.qaa_observables(st)["p_success"] for st in states[:loop_sample]]
+    loop_amp_steps = sum((1 << w[0]) * w[2] for w in wl[:loop_sample])
+    for inst in insts:
+        inst.close()
+    return {
+        "workload": "%d planted 3-SAT instances, n ~ U{12..22}, T ~ U[10,100), dt ~ 0.01 (seed %d)" % (count, seed),
+        "solves_per_s": count / t_batch,
+        "amp_steps_per_s": amp_steps / t_batch,
+        "seconds": t_batch,
+        "amp_steps": amp_steps,
+        "loop": {"instances": loop_sample, "amp_steps_per_s": loop_amp_steps / t_loop, "seconds": t_loop,
+                 "max_abs_dp_vs_batch": max(abs(a - b) for a, b in zip(p_batch, p_loop)) if loop_sample else None},
+    }
+
+
+def run_serving(qaa, count, rates, n_lo, n_hi, t_lo, t_hi, slots, budget):
+    """Open-loop serving: Poisson arrivals at each rate (requests/s), each a
+    planted 3-SAT solve; reports latency percentiles and completed solves/s."""
+    from qaa_inputs import planted_unique_3sat, serving_workload
+    out = []
+    for rate in rates:
+        wl = serving_workload(count, rate, n_lo=n_lo, n_hi=n_hi, t_lo=t_lo, t_hi=t_hi)
+        lits = [planted_unique_3sat(w["n"], w["seed"]).literals() for w in wl]
+        sv = qaa.qaa_server_create(budget, slots)
+        try:
+            t0 = time.perf_counter()
+            tickets = []
+            for w, li in zip(wl, lits):
+                delay = t0 + w["arrival"] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                tickets.append(qaa.qaa_server_submit(sv, w["n"], li, w["T"], w["steps"]))
+            res = [qaa.qaa_server_wait(sv, t) for t in tickets]
+            t_end = time.perf_counter()
+        finally:
+            qaa.qaa_server_destroy(sv)
+        bad = [r for r in res if r["status"] != qaa.QAA_OK]
+        if bad:
+            raise RuntimeError("serving: %d requests failed (status %d)" % (len(bad), bad[0]["status"]))
+        lat = [r["latency_s"] for r in res]
+        out.append({"rate_per_s": rate, "requests": count, "p50_s": _percentile(lat, 50),
+                    "p99_s": _percentile(lat, 99), "mean_queued_s": sum(r["queued_s"] for r in res) / count,
+                    "solves_per_s": count / (t_end - t0),
+                    "amp_steps_per_s": sum((1 << w["n"]) * w["steps"] for w in wl) / (t_end - t0)})
+        log("serving rate %.2f/s: p50 %.3f s p99 %.3f s, %.2f solves/s"
+            % (rate, out[-1]["p50_s"], out[-1]["p99_s"], out[-1]["solves_per_s"]))
+    return {"workload": "Poisson arrivals, n ~ U{%d..%d}, T ~ U[%g,%g), dt ~ 0.01, %d slots, %.1f GiB budget"
+                        % (n_lo, n_hi, t_lo, t_hi, slots, budget / 2.0 ** 30), "points": out}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +185,16 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 2 GiB device copy (torch copy_), the reference dispatch for "
                          "scaling HBM counter readings")
+    ap.add_argument("--batch", type=int, default=0, metavar="COUNT",
+                    help="also run the batched workload with COUNT instances (512 is the full one)")
+    ap.add_argument("--batch-loop-sample", type=int, default=64)
+    ap.add_argument("--serve", type=str, default="", metavar="RATES",
+                    help="also run open-loop serving at these comma-separated arrival rates (requests/s)")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-n", type=str, default="16,24", help="n range lo,hi of served requests")
+    ap.add_argument("--serve-t", type=str, default="10,50", help="T range lo,hi of served requests")
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -183,6 +287,20 @@ def main():
         log("cpu baseline (oracle, %d steps sample)" % args.cpu_sample_steps)
         cpu = cpu_baseline(inst_in, n, T, N, args.cpu_sample_steps)
 
+    extras = {}
+    if args.batch:
+        log("batched workload (%d instances)" % args.batch)
+        extras["batch"] = run_batch(qaa, torch, args.batch, 2024, min(args.batch, args.batch_loop_sample))
+        log("batch: %.2f solves/s, %.3e amp-steps/s (loop %.3e)" % (
+            extras["batch"]["solves_per_s"], extras["batch"]["amp_steps_per_s"],
+            extras["batch"]["loop"]["amp_steps_per_s"]))
+    if args.serve:
+        rates = [float(x) for x in args.serve.split(",") if x]
+        nlo, nhi = (int(x) for x in args.serve_n.split(","))
+        tlo, thi = (float(x) for x in args.serve_t.split(","))
+        extras["serving"] = run_serving(qaa, args.serve_requests, rates, nlo, nhi, tlo, thi, args.serve_slots,
+                                        int(args.serve_budget_gib * 2 ** 30))
+
     value = (2.0 ** n) * K / secs
     out = {
         "metric": METRIC,
@@ -209,6 +327,7 @@ def main():
         "result": {"p_success": obs["p_success"], "energy": obs["energy"], "norm": obs["norm"],
                    "steps_done": K},
     }
+    out.update(extras)
     if cpu:
         out["gpu_over_cpu"] = value / cpu["value"]
     print(json.dumps(out), flush=True)

@@ -160,10 +160,16 @@ qaa_status qaa_evolve_range(const qaa_state *st, const qaa_schedule *sched, doub
                             int64_t steps, int64_t k0, int64_t k1, void *stream);
 
 /*
- * Evolve `count` independent states in one launch per pass.  states[i],
- * T[i] and steps[i] (host arrays) as in qaa_evolve; the states may have
- * different n.  Each result equals what qaa_evolve gives for that state
- * alone, up to FP32 rounding (same kernels, same plan per n).  Asynchronous.
+ * Evolve `count` independent states together.  states[i], T[i] and
+ * steps[i] (host arrays) as in qaa_evolve; the states may have different n.
+ * States whose whole vector fits one workgroup tile (n <= 13 for complex64,
+ * 12 for complex128) run in one launch, one workgroup each; the others run
+ * in lock step, one launch per pass covering every state still running,
+ * with rotation and phase coefficients computed on the device.  Each result
+ * equals what qaa_evolve gives for that state alone up to FP32 rounding
+ * (same pass plan per n).  The call waits for the descriptor uploads (and
+ * so for work already queued on the stream); the evolution itself is
+ * asynchronous on the stream.
  */
 qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, const double *T,
                             const int64_t *steps, void *stream);
@@ -184,6 +190,58 @@ typedef struct qaa_obs {
 /* SYNCHRONOUS: enqueues the reduction on the stream, waits for it, and
  * fills *out.  QAA_ERR_NOT_READY if the instance has no energy table yet. */
 qaa_status qaa_observables(const qaa_state *st, qaa_obs *out, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Serving: a solve-request server.  Requests are admitted in arrival order
+ * when one of `slots` workers is free and their HBM footprint (2^n * 9
+ * bytes: complex64 state plus uint8 energy table) fits the budget beside
+ * the admitted ones; each worker runs its solve (energy table, uniform
+ * start, qaa_evolve, qaa_observables) on its own HIP stream, so solves
+ * admitted while others run overlap on the device.  The server allocates
+ * and frees each request's device buffers on the current device of the
+ * thread that created it.
+ * ------------------------------------------------------------------- */
+
+typedef struct qaa_server qaa_server;
+
+typedef struct qaa_server_config {
+    uint64_t hbm_budget_bytes;  /* admitted requests' footprints never exceed this */
+    int32_t slots;              /* concurrent solves (worker threads / streams), 1..64 */
+    int32_t reserved;           /* set to 0 */
+} qaa_server_config;
+
+typedef struct qaa_server_result {
+    qaa_status status;          /* QAA_OK once done without error */
+    int32_t done;               /* 1 when the solve finished (or failed) */
+    qaa_obs obs;                /* observables of the final state (done == 1) */
+    double queued_s;            /* time from submit to admission (so far, if not admitted) */
+    double latency_s;           /* time from submit to completion (so far, if not done) */
+} qaa_server_result;
+
+/* Start a server (threads and streams).  QAA_ERR_INVALID_ARG for a NULL
+ * argument, slots outside 1..64 or a zero budget. */
+qaa_status qaa_server_create(const qaa_server_config *cfg, qaa_server **out);
+
+/* Queue a solve of the instance (n, m, lits; as qaa_instance_create) for
+ * total time T and `steps` steps; *ticket identifies it.  Copies lits.
+ * QAA_ERR_OUT_OF_MEMORY if its footprint exceeds the whole budget (it could
+ * never be admitted); QAA_ERR_INVALID_ARG for malformed arguments (clause
+ * errors are reported through the result). */
+qaa_status qaa_server_submit(qaa_server *sv, int32_t n, int32_t m, const int32_t *lits, double T,
+                             int64_t steps, int64_t *ticket);
+
+/* Non-blocking status of a ticket. */
+qaa_status qaa_server_poll(qaa_server *sv, int64_t ticket, qaa_server_result *out);
+
+/* Block until the ticket's solve has finished, then fill *out. */
+qaa_status qaa_server_wait(qaa_server *sv, int64_t ticket, qaa_server_result *out);
+
+/* Queue length, running solves and admitted footprint in bytes (any may be NULL). */
+qaa_status qaa_server_stats(qaa_server *sv, int64_t *queued, int64_t *running, uint64_t *bytes_in_use);
+
+/* Stop the server: solves already admitted finish, queued ones are dropped.
+ * No thread may wait on a ticket of a dropped request.  NULL is ignored. */
+void qaa_server_destroy(qaa_server *sv);
 
 /* ---------------------------------------------------------------------
  * Plans (how a step is split into HBM passes) -- introspection.

@@ -23,6 +23,16 @@ if not os.path.exists(LIB_PATH):
         "libqaa.so is not built (expected at %s); run `python -c \"import __graft_entry__ as g; g.build()\"` "
         "or `python paper_1103_1399_amd/build.py`" % LIB_PATH)
 
+# One HIP runtime per process.  PyTorch's ROCm wheels carry their own copies
+# of the HIP and HSA runtimes; when torch is loaded first, libqaa's runtime
+# dependency resolves to the copy already in the process.  Loaded the other
+# way round, the process holds two runtimes and the second one to start
+# finds no usable device.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 # status codes (qaa_status)
@@ -62,6 +72,15 @@ class qaa_obs(ctypes.Structure):
                 ("e_min", ctypes.c_int32), ("degeneracy", ctypes.c_int64)]
 
 
+class qaa_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("slots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class qaa_server_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("done", ctypes.c_int32), ("obs", qaa_obs),
+                ("queued_s", ctypes.c_double), ("latency_s", ctypes.c_double)]
+
+
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _i64p = ctypes.POINTER(ctypes.c_int64)
 _f64p = ctypes.POINTER(ctypes.c_double)
@@ -86,6 +105,13 @@ _SIGS = {
                                    ctypes.c_int64, ctypes.c_int64, _vp, ctypes.c_int32, _i32p, _i32p]),
     "qaa_profile_enable": (_st, [ctypes.c_int32]),
     "qaa_profile_read": (_st, [ctypes.c_void_p, ctypes.c_int32]),
+    "qaa_server_create": (_st, [ctypes.POINTER(qaa_server_config), ctypes.POINTER(_vp)]),
+    "qaa_server_submit": (_st, [_vp, ctypes.c_int32, ctypes.c_int32, _i32p, ctypes.c_double, ctypes.c_int64,
+                                _i64p]),
+    "qaa_server_poll": (_st, [_vp, ctypes.c_int64, ctypes.POINTER(qaa_server_result)]),
+    "qaa_server_wait": (_st, [_vp, ctypes.c_int64, ctypes.POINTER(qaa_server_result)]),
+    "qaa_server_stats": (_st, [_vp, _i64p, _i64p, ctypes.POINTER(ctypes.c_uint64)]),
+    "qaa_server_destroy": (None, [_vp]),
     "qaa_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "qaa_last_error": (ctypes.c_char_p, []),
     "qaa_version": (ctypes.c_int32, []),
@@ -206,9 +232,12 @@ def qaa_plan_info(n: int, dtype: int = QAA_C64) -> dict:
 class PassDesc(ctypes.Structure):
     """Mirror of the library's internal pass descriptor (diagnostics only)."""
     _fields_ = [("n", ctypes.c_int32), ("n_rest", ctypes.c_int32), ("n_res", ctypes.c_int32),
-                ("phase_at", ctypes.c_int32), ("emax", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("phase_at", ctypes.c_int32), ("emax", ctypes.c_int32), ("set_id", ctypes.c_int32),
                 ("cm1A", ctypes.c_double), ("sA", ctypes.c_double), ("cm1B", ctypes.c_double),
-                ("sB", ctypes.c_double), ("phi", ctypes.c_double), ("gphase", ctypes.c_double),
+                ("sB", ctypes.c_double), ("s2A", ctypes.c_double), ("csA", ctypes.c_double),
+                ("s2B", ctypes.c_double), ("csB", ctypes.c_double),
+                ("phi", ctypes.c_double), ("gphase", ctypes.c_double),
+                ("tile_begin", ctypes.c_uint64), ("tile_count", ctypes.c_uint64),
                 ("acc_in", ctypes.c_void_p), ("acc_out", ctypes.c_void_p), ("acc_zero", ctypes.c_void_p),
                 ("goff_first", ctypes.c_uint64 * 32), ("goff_last", ctypes.c_uint64 * 32),
                 ("ljp", (ctypes.c_uint16 * 32) * 12), ("lj", (ctypes.c_uint16 * 32) * 12),
@@ -244,6 +273,51 @@ def qaa_profile_read(reset: bool = True) -> dict:
     _check(_lib.qaa_profile_read(ctypes.byref(out), 1 if reset else 0), "qaa_profile_read")
     return {"launches": out.launches, "kernel_ms": out.kernel_ms, "min_ms": out.min_ms, "max_ms": out.max_ms,
             "alg_bytes": out.alg_bytes}
+
+
+def _result_dict(r: qaa_server_result) -> dict:
+    o = r.obs
+    return {"status": r.status, "done": bool(r.done), "queued_s": r.queued_s, "latency_s": r.latency_s,
+            "norm": o.norm, "energy": o.energy, "p_success": o.p_success, "e_min": o.e_min,
+            "degeneracy": o.degeneracy}
+
+
+def qaa_server_create(hbm_budget_bytes: int, slots: int) -> int:
+    cfg = qaa_server_config(int(hbm_budget_bytes), int(slots), 0)
+    out = _vp()
+    _check(_lib.qaa_server_create(ctypes.byref(cfg), ctypes.byref(out)), "qaa_server_create")
+    return out.value
+
+
+def qaa_server_submit(server: int, n: int, lits, T: float, steps: int) -> int:
+    import numpy as np
+    arr = np.ascontiguousarray(np.asarray(lits, dtype=np.int32).reshape(-1))
+    t = ctypes.c_int64()
+    _check(_lib.qaa_server_submit(server, int(n), arr.size // 3, arr.ctypes.data_as(_i32p), float(T), int(steps),
+                                  ctypes.byref(t)), "qaa_server_submit")
+    return t.value
+
+
+def qaa_server_poll(server: int, ticket: int) -> dict:
+    r = qaa_server_result()
+    _check(_lib.qaa_server_poll(server, int(ticket), ctypes.byref(r)), "qaa_server_poll")
+    return _result_dict(r)
+
+
+def qaa_server_wait(server: int, ticket: int) -> dict:
+    r = qaa_server_result()
+    _check(_lib.qaa_server_wait(server, int(ticket), ctypes.byref(r)), "qaa_server_wait")
+    return _result_dict(r)
+
+
+def qaa_server_stats(server: int) -> dict:
+    q, rn, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_uint64()
+    _check(_lib.qaa_server_stats(server, ctypes.byref(q), ctypes.byref(rn), ctypes.byref(b)), "qaa_server_stats")
+    return {"queued": q.value, "running": rn.value, "bytes_in_use": b.value}
+
+
+def qaa_server_destroy(server: int) -> None:
+    _lib.qaa_server_destroy(server)
 
 
 def qaa_status_str(status: int) -> str:

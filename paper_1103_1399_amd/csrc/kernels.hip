@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstddef>
+#include <cstdlib>
 
 namespace qaa {
 namespace {
@@ -45,29 +46,99 @@ __device__ __forceinline__ F2 cmul(F2 a, F2 b)
     return r;
 }
 
+// Coefficients of one rotation angle theta: cm1 = cos(theta/2) - 1,
+// s = sin(theta/2), s2 = s^2, cs = cos(theta/2) sin(theta/2).
+template <typename F>
+struct Rot {
+    F cm1, s, s2, cs;
+};
+
 // Rotate register bit b of every pair in v: (x0, x1) <- (c x0 + i s x1,
 // c x1 + i s x0) with c = 1 + cm1.
 template <int RB, typename F2, typename F>
-__device__ __forceinline__ void rotate_bit(F2 (&v)[1 << RB], int b, F cm1, F s)
+__device__ __forceinline__ void rotate_bit(F2 (&v)[1 << RB], int b, const Rot<F> &k)
 {
 #pragma unroll
     for (int j = 0; j < (1 << RB); ++j) {
         if (j & (1 << b)) continue;
-        const int k = j | (1 << b);
-        const F2 x0 = v[j], x1 = v[k];
-        v[j].x = fma(-s, x1.y, fma(cm1, x0.x, x0.x));
-        v[j].y = fma(s, x1.x, fma(cm1, x0.y, x0.y));
-        v[k].x = fma(-s, x0.y, fma(cm1, x1.x, x1.x));
-        v[k].y = fma(s, x0.x, fma(cm1, x1.y, x1.y));
+        const int m = j | (1 << b);
+        const F2 x0 = v[j], x1 = v[m];
+        v[j].x = fma(-k.s, x1.y, fma(k.cm1, x0.x, x0.x));
+        v[j].y = fma(k.s, x1.x, fma(k.cm1, x0.y, x0.y));
+        v[m].x = fma(-k.s, x0.y, fma(k.cm1, x1.x, x1.x));
+        v[m].y = fma(k.s, x0.x, fma(k.cm1, x1.y, x1.y));
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
+// Rotate register bits b1 and b2 together.  With R = c + i s X on each bit
+// and c^2 = 1 - s^2, (R x R) maps a quad (x00, x01, x10, x11) to
+//   y00 = x00 - s^2 A + i c s B,   y11 = x11 - s^2 A + i c s B,
+//   y01 = x01 - s^2 B + i c s A,   y10 = x10 - s^2 B + i c s A,
+// with A = x00 + x11 and B = x01 + x10: 5 instructions per amplitude for
+// the two bits instead of 8, and the small corrections are added last.
 template <int RB, typename F2, typename F>
-__device__ __forceinline__ void rotate_mask(F2 (&v)[1 << RB], uint32_t mask, F cm1, F s)
+__device__ __forceinline__ void rotate_pair(F2 (&v)[1 << RB], int b1, int b2, const Rot<F> &k)
 {
 #pragma unroll
-    for (int b = 0; b < RB; ++b)
-        if ((mask >> b) & 1u) rotate_bit<RB>(v, b, cm1, s);
+    for (int j = 0; j < (1 << RB); ++j) {
+        if ((j & (1 << b1)) || (j & (1 << b2))) continue;
+        const int j01 = j | (1 << b1), j10 = j | (1 << b2), j11 = j01 | (1 << b2);
+        const F2 x00 = v[j], x01 = v[j01], x10 = v[j10], x11 = v[j11];
+        F2 A, B;
+        A.x = x00.x + x11.x;
+        A.y = x00.y + x11.y;
+        B.x = x01.x + x10.x;
+        B.y = x01.y + x10.y;
+        v[j].x = fma(-k.s2, A.x, fma(-k.cs, B.y, x00.x));
+        v[j].y = fma(-k.s2, A.y, fma(k.cs, B.x, x00.y));
+        v[j11].x = fma(-k.s2, A.x, fma(-k.cs, B.y, x11.x));
+        v[j11].y = fma(-k.s2, A.y, fma(k.cs, B.x, x11.y));
+        v[j01].x = fma(-k.s2, B.x, fma(-k.cs, A.y, x01.x));
+        v[j01].y = fma(-k.s2, B.y, fma(k.cs, A.x, x01.y));
+        v[j10].x = fma(-k.s2, B.x, fma(-k.cs, A.y, x10.x));
+        v[j10].y = fma(-k.s2, B.y, fma(k.cs, A.x, x10.y));
+        // one quad at a time: enough independent FMAs per quad, and the
+        // temporaries of later quads do not compete for registers
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Rotate every register bit in mask (uniform): neighbouring bits
+// (P0, P0+1), (P0+2, P0+3), ... go through the fused pair update when both
+// are set; the remaining bits one at a time.
+template <int RB, typename F2, typename F, bool FUSE = true>
+__device__ __forceinline__ void rotate_mask(F2 (&v)[1 << RB], uint32_t mask, const Rot<F> &k)
+{
+    if constexpr (!FUSE) {
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+            if ((mask >> b) & 1u) rotate_bit<RB>(v, b, k);
+        return;
+    }
+    constexpr int P0 = RB & 1;      // RB = 5: pairs (1,2), (3,4), single 0; RB = 4: (0,1), (2,3)
+    if (P0 && (mask & 1u)) rotate_bit<RB>(v, 0, k);
+#pragma unroll
+    for (int b = P0; b + 1 < RB; b += 2) {
+        const uint32_t two = (mask >> b) & 3u;
+        if (two == 3u)
+            rotate_pair<RB>(v, b, b + 1, k);
+        else if (two == 1u)
+            rotate_bit<RB>(v, b, k);
+        else if (two == 2u)
+            rotate_bit<RB>(v, b + 1, k);
+    }
+}
+
+template <typename F>
+__host__ __device__ inline Rot<F> make_rot(double cm1, double s, double s2, double cs)
+{
+    Rot<F> k;
+    k.cm1 = (F)cm1;
+    k.s = (F)s;
+    k.s2 = (F)s2;
+    k.cs = (F)cs;
+    return k;
 }
 
 template <typename ET> constexpr int lut_cap() { return sizeof(ET) == 1 ? kLutMaxU8 : kLutMax; }
@@ -188,6 +259,13 @@ __global__ void __launch_bounds__(256) init_basis_kernel(typename V2<F>::T *__re
 // flight while the current tile is rotated, phased and stored.
 // ---------------------------------------------------------------------------
 
+// Add every lane's fixed-point norm share into *acc (one atomic per wave).
+__device__ __forceinline__ void norm_accumulate(unsigned long long *acc, unsigned long long v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(acc, v);
+}
+
 // Workgroup barrier that orders LDS traffic only: HBM loads issued before it
 // stay in flight.
 __device__ __forceinline__ void lds_barrier()
@@ -286,12 +364,12 @@ __device__ __forceinline__ void pass_load(TileRegs<F, ET, TB, RB> &tr, const typ
 }
 
 // Residencies of one tile, ending with the store to HBM.
-template <typename F, typename ET, int TB, int RB, bool PHASE>
+template <typename F, typename ET, int TB, int RB, bool PHASE, bool FUSE>
 __device__ __forceinline__ void pass_compute(TileRegs<F, ET, TB, RB> &tr, typename V2<F>::T *__restrict__ amp,
                                              const PassDesc &d, uint64_t base,
                                              uint64_t tg_last, uint32_t tid,
                                              typename V2<F>::T *tile, const typename V2<F>::T *lut, ET *etile,
-                                             F cm1A, F sA, F cm1B, F sB, double &ss)
+                                             const Rot<F> &kA, const Rot<F> &kB, unsigned long long &ssq)
 {
     using P = PassTraits<F, ET, TB, RB>;
     using F2 = typename P::F2;
@@ -321,15 +399,20 @@ __device__ __forceinline__ void pass_compute(TileRegs<F, ET, TB, RB> &tr, typena
     auto apply = [&](int r, uint32_t lt) {
         const uint32_t o_lj = (uint32_t)offsetof(PassDesc, lj) + 2u * kMaxRegs * (uint32_t)r;
         const uint32_t masks = desc_word(d, (uint32_t)offsetof(PassDesc, masks) + 4u * (uint32_t)r);
-        rotate_mask<RB>(v, masks & 0xFFu, cm1A, sA);
+        rotate_mask<RB, F2, F, FUSE>(v, masks & 0xFFu, kA);
         if (PHASE && r == d.phase_at) {
+            // four amplitudes at a time keeps the table reads' registers few
 #pragma unroll
-            for (int j = 0; j < R; ++j) {
-                const uint32_t e = (uint32_t)etile[lt + desc_u16(d, o_lj + 2 * j)];
-                v[j] = cmul<F2, F>(v[j], lut[e]);
+            for (int j0 = 0; j0 < R; j0 += 4) {
+#pragma unroll
+                for (int j = j0; j < j0 + 4; ++j) {
+                    const uint32_t e = (uint32_t)etile[lt + desc_u16(d, o_lj + 2 * j)];
+                    v[j] = cmul<F2, F>(v[j], lut[e]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
-        rotate_mask<RB>(v, (masks >> 8) & 0xFFu, cm1B, sB);
+        rotate_mask<RB, F2, F, FUSE>(v, (masks >> 8) & 0xFFu, kB);
     };
     auto to_lds = [&](int r, uint32_t ltp) {
         const uint32_t o_ljp = (uint32_t)offsetof(PassDesc, ljp) + 2u * kMaxRegs * (uint32_t)r;
@@ -401,11 +484,17 @@ __device__ __forceinline__ void pass_compute(TileRegs<F, ET, TB, RB> &tr, typena
             p[d.goff_last[j]] = v[j];
         }
     }
-    ss += (double)st;
+    // fixed point per thread and tile: the total does not depend on which
+    // workgroup handled which tile, nor on the order of the additions
+    ssq += (unsigned long long)((double)st * kNormFixedScale + 0.5);
 }
 
-template <typename F, typename ET, int TB, int RB, bool PHASE>
-__global__ void __launch_bounds__(1 << (TB - RB))
+// Two workgroups per CU (LDS-bound) means two waves per SIMD: the register
+// budget is held to that occupancy.
+// FUSE: fused two-qubit rotations; PIPE: persistent grid with the next
+// tile's loads in flight (otherwise one workgroup per tile).
+template <typename F, typename ET, int TB, int RB, bool PHASE, bool FUSE, bool PIPE>
+__global__ void __launch_bounds__(1 << (TB - RB), 2)
 pass_kernel(typename V2<F>::T *__restrict__ amp, const ET *__restrict__ table, const PassDesc d)
 {
     using P = PassTraits<F, ET, TB, RB>;
@@ -417,7 +506,8 @@ pass_kernel(typename V2<F>::T *__restrict__ amp, const ET *__restrict__ table, c
     ET *etile = reinterpret_cast<ET *>(lut + lut_cap<ET>());
 
     const uint32_t tid = threadIdx.x;
-    const uint64_t ntiles = 1ull << d.n_rest;
+    const uint64_t ntiles = d.tile_count;
+    const uint64_t t0 = d.tile_begin;
     const uint64_t G = gridDim.x;
 
     uint64_t tg_first = 0, tg_last = 0;
@@ -433,7 +523,7 @@ pass_kernel(typename V2<F>::T *__restrict__ amp, const ET *__restrict__ table, c
     // compiler's wait counts assume the worst path and stall on the prefetch.
     TileRegs<F, ET, TB, RB> ta, tb;
     uint64_t w = blockIdx.x;        // grid size <= ntiles, so w is a valid tile
-    pass_load<F, ET, TB, RB, PHASE>(ta, amp, table, d, tile_base<F, ET, TB, RB>(d, w), tg_first, tid);
+    pass_load<F, ET, TB, RB, PHASE>(ta, amp, table, d, tile_base<F, ET, TB, RB>(d, t0 + w), tg_first, tid);
 
     if constexpr (PHASE) {
         const double scale = d.acc_in ? rsqrt((double)(*d.acc_in) * (1.0 / kNormFixedScale)) : 1.0;
@@ -448,36 +538,159 @@ pass_kernel(typename V2<F>::T *__restrict__ amp, const ET *__restrict__ table, c
     }
     if (d.acc_zero && blockIdx.x == 0 && tid == 0) *d.acc_zero = 0ull;
 
-    const F cm1A = (F)d.cm1A, sA = (F)d.sA, cm1B = (F)d.cm1B, sB = (F)d.sB;
-    double ss = 0.0;
-    while (true) {
+    const Rot<F> kA = make_rot<F>(d.cm1A, d.sA, d.s2A, d.csA);
+    const Rot<F> kB = make_rot<F>(d.cm1B, d.sB, d.s2B, d.csB);
+    unsigned long long ss = 0ull;
+    if constexpr (!PIPE) {
+        pass_compute<F, ET, TB, RB, PHASE, FUSE>(ta, amp, d, tile_base<F, ET, TB, RB>(d, t0 + w), tg_last, tid, tile,
+                                                 lut, etile, kA, kB, ss);
+    }
+    while (PIPE) {
         const uint64_t w1 = w + G;
-        pass_load<F, ET, TB, RB, PHASE>(tb, amp, table, d, tile_base<F, ET, TB, RB>(d, w1 < ntiles ? w1 : w), tg_first,
-                                        tid);
-        pass_compute<F, ET, TB, RB, PHASE>(ta, amp, d, tile_base<F, ET, TB, RB>(d, w), tg_last, tid, tile, lut, etile,
-                                           cm1A, sA, cm1B, sB, ss);
+        pass_load<F, ET, TB, RB, PHASE>(tb, amp, table, d, tile_base<F, ET, TB, RB>(d, t0 + (w1 < ntiles ? w1 : w)),
+                                        tg_first, tid);
+        pass_compute<F, ET, TB, RB, PHASE, FUSE>(ta, amp, d, tile_base<F, ET, TB, RB>(d, t0 + w), tg_last, tid, tile, lut,
+                                           etile, kA, kB, ss);
         if (w1 >= ntiles) break;
         const uint64_t w2 = w1 + G;
-        pass_load<F, ET, TB, RB, PHASE>(ta, amp, table, d, tile_base<F, ET, TB, RB>(d, w2 < ntiles ? w2 : w1),
+        pass_load<F, ET, TB, RB, PHASE>(ta, amp, table, d, tile_base<F, ET, TB, RB>(d, t0 + (w2 < ntiles ? w2 : w1)),
                                         tg_first, tid);
-        pass_compute<F, ET, TB, RB, PHASE>(tb, amp, d, tile_base<F, ET, TB, RB>(d, w1), tg_last, tid, tile, lut, etile,
-                                           cm1A, sA, cm1B, sB, ss);
+        pass_compute<F, ET, TB, RB, PHASE, FUSE>(tb, amp, d, tile_base<F, ET, TB, RB>(d, t0 + w1), tg_last, tid, tile, lut,
+                                           etile, kA, kB, ss);
         if (w2 >= ntiles) break;
         w = w2;
     }
 
-    if (d.acc_out) {
-        double t = ss;
-        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-        __shared__ double wsum[P::WG / 64];
-        if ((tid & 63) == 0) wsum[tid >> 6] = t;
-        __syncthreads();
-        if (tid == 0) {
-            double b = 0.0;
-            for (int k = 0; k < (int)(P::WG / 64); ++k) b += wsum[k];
-            atomicAdd(d.acc_out, (unsigned long long)(b * kNormFixedScale + 0.5));
+    if (d.acc_out) norm_accumulate(d.acc_out, ss);
+}
+
+// ---------------------------------------------------------------------------
+// Batched passes (see BatchInst).
+// ---------------------------------------------------------------------------
+struct DevCoef {
+    double s, theta, cm1, sn, s2, cs;
+};
+
+// Step k of N over total time T: schedule midpoint s_k = (k + 1/2)/N and the
+// rotation coefficients of theta_k = dt (1 - s_k) (same formulas as the host).
+__device__ __forceinline__ DevCoef dev_step_coef(double T, int64_t N, int64_t k)
+{
+    DevCoef c;
+    const double dt = T / (double)N;
+    c.s = ((double)k + 0.5) / (double)N;
+    c.theta = dt * (1.0 - c.s);
+    const double q = sin(0.25 * c.theta);
+    c.cm1 = -2.0 * q * q;
+    c.sn = sin(0.5 * c.theta);
+    c.s2 = c.sn * c.sn;
+    c.cs = 0.5 * sin(c.theta);
+    return c;
+}
+
+template <typename F, typename ET, int TB, int RB, bool PHASE, bool FUSE>
+__device__ __forceinline__ void batch_tile(const BatchInst &I, const PassDesc &d, uint64_t w, int kind_top,
+                                           const Rot<F> &kA, const Rot<F> &kB, double phi, double gphase,
+                                           unsigned long long *acc_in, unsigned long long *acc_out)
+{
+    using P = PassTraits<F, ET, TB, RB>;
+    using F2 = typename P::F2;
+    extern __shared__ __align__(16) unsigned char smem[];
+    F2 *tile = reinterpret_cast<F2 *>(smem);
+    F2 *lut = tile + P::TSP;
+    ET *etile = reinterpret_cast<ET *>(lut + lut_cap<ET>());
+    F2 *amp = reinterpret_cast<F2 *>(I.amp);
+    const ET *table = reinterpret_cast<const ET *>(I.table);
+    const uint32_t tid = threadIdx.x;
+    uint64_t tg_first = 0, tg_last = 0;
+#pragma unroll
+    for (int k = 0; k < P::WB; ++k) {
+        tg_first |= (uint64_t)((tid >> k) & 1u) << d.gpos_first[k];
+        tg_last |= (uint64_t)((tid >> k) & 1u) << d.gpos_last[k];
+    }
+    const uint64_t base = tile_base<F, ET, TB, RB>(d, w);
+    TileRegs<F, ET, TB, RB> ta;
+    pass_load<F, ET, TB, RB, PHASE>(ta, amp, table, d, base, tg_first, tid);
+    if constexpr (PHASE) {
+        const double scale = acc_in ? rsqrt((double)(*acc_in) * (1.0 / kNormFixedScale)) : 1.0;
+        for (int e = (int)tid; e <= I.emax; e += (int)P::WG) {
+            double sn, cs;
+            sincos(fma(phi, (double)e, gphase), &sn, &cs);
+            F2 L;
+            L.x = (F)(scale * cs);
+            L.y = (F)(-scale * sn);
+            lut[e] = L;
         }
     }
+    unsigned long long ss = 0ull;
+    pass_compute<F, ET, TB, RB, PHASE, FUSE>(ta, amp, d, base, tg_last, tid, tile, lut, etile, kA, kB, ss);
+    if (acc_out) norm_accumulate(acc_out, ss);
+    (void)kind_top;
+}
+
+template <typename F, typename ET, int TB, int RB, bool FUSE>
+__global__ void __launch_bounds__(1 << (TB - RB), 2)
+batch_pass_kernel(const BatchInst *__restrict__ insts, int count, const PassDesc *__restrict__ structs, int64_t s,
+                  int j)
+{
+    // state of this workgroup: the last one whose first tile is <= blockIdx.x
+    const uint64_t g = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (insts[mid].tile_offset <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const BatchInst &I = insts[lo];
+    if (s >= I.N) return;
+    const int r = I.r;
+    const int idx = s == 0 ? j : j + 1;       // position in this step's set order
+    if (idx >= r) return;
+    const bool fwd = (s & 1) == 0;
+    const bool last = idx == r - 1;
+    const int set = fwd ? idx : r - 1 - idx;
+    int kind;
+    if (s == 0 && idx == 0)
+        kind = 0;
+    else if (!last)
+        kind = set;
+    else if (s + 1 < I.N)
+        kind = set == r - 1 ? r - 1 : r;
+    else
+        kind = set == r - 1 ? r + 1 : r + 2;
+    const PassDesc &d = structs[I.struct_base + kind];
+    const uint64_t w = g - I.tile_offset;
+
+    const double dt = I.T / (double)I.N;
+    const DevCoef ck = dev_step_coef(I.T, I.N, s);
+    Rot<F> kA = make_rot<F>(ck.cm1, ck.sn, ck.s2, ck.cs), kB = make_rot<F>(0.0, 0.0, 0.0, 0.0);
+    double phi = 0.0, gph = 0.0;
+    const double twopi = 2.0 * M_PI;
+    if (kind == 0) {
+        kB = kA;
+        phi = 0.5 * dt * ck.s;
+    } else if (kind == r - 1 || kind == r) {
+        const DevCoef cn = dev_step_coef(I.T, I.N, s + 1);
+        kB = make_rot<F>(cn.cm1, cn.sn, cn.s2, cn.cs);
+        phi = 0.5 * dt * (ck.s + cn.s);
+        gph = fmod(0.5 * (double)I.n * ck.theta, twopi);
+    } else if (kind >= r + 1) {
+        phi = 0.5 * dt * ck.s;
+        gph = fmod(0.5 * (double)I.n * ck.theta, twopi);
+    }
+    // norm control rides on the passes over the top set (every other step)
+    unsigned long long *acc_in = nullptr, *acc_out = nullptr;
+    if (I.acc && set == r - 1 && last) {
+        const int64_t gj = s >> 1;
+        acc_out = I.acc + gj % 3;
+        acc_in = gj > 0 ? I.acc + (gj + 2) % 3 : nullptr;
+        if (w == 0 && threadIdx.x == 0) I.acc[(gj + 1) % 3] = 0ull;
+    }
+    if (d.phase_at >= 0)
+        batch_tile<F, ET, TB, RB, true, FUSE>(I, d, w, kind, kA, kB, phi, gph, acc_in, acc_out);
+    else
+        batch_tile<F, ET, TB, RB, false, FUSE>(I, d, w, kind, kA, kB, phi, gph, acc_in, acc_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -539,7 +752,7 @@ __device__ __forceinline__ void resident_body(const ResidentDesc &d)
         }
         __syncthreads();
     };
-    auto residency = [&](int g, bool phase, uint32_t rmask, F cm1, F s, bool meas) {
+    auto residency = [&](int g, bool phase, uint32_t rmask, const Rot<F> &k, bool meas) {
         if (active) {
             uint32_t lt = 0;
             for (int k = 0; k < d.thr_bits; ++k) lt |= ((tid >> k) & 1u) << d.tpos[g][k];
@@ -562,7 +775,7 @@ __device__ __forceinline__ void resident_body(const ResidentDesc &d)
                 for (int j = 0; j < R; ++j)
                     if (((uint32_t)j & ~used) == 0) v[j] = cmul<F2, F>(v[j], lut[(uint32_t)etile[lt | lj[j]]]);
             }
-            rotate_mask<RB>(v, rmask, cm1, s);
+            rotate_mask<RB>(v, rmask, k);
             F ss = F(0);
 #pragma unroll
             for (int j = 0; j < R; ++j)
@@ -590,16 +803,16 @@ __device__ __forceinline__ void resident_body(const ResidentDesc &d)
         const double scale = k == d.k0 ? 1.0 : rsqrt(measure());
         build_lut(phi, gph, scale);
         const double q = sin(0.25 * theta);
-        const F cm1 = (F)(-2.0 * q * q);
-        const F s = (F)sin(0.5 * theta);
-        for (int g = 0; g < d.n_groups; ++g) residency(g, g == 0, d.gmask[g], cm1, s, g == d.n_groups - 1);
+        const double sh = sin(0.5 * theta);
+        const Rot<F> rk = make_rot<F>(-2.0 * q * q, sh, sh * sh, 0.5 * sin(theta));
+        for (int g = 0; g < d.n_groups; ++g) residency(g, g == 0, d.gmask[g], rk, g == d.n_groups - 1);
         theta_prev = theta;
         s_prev = sk;
     }
     if (d.k1 > d.k0) {
         const double scale = rsqrt(measure());
         build_lut(0.5 * dt * s_prev, fmod(0.5 * (double)n * theta_prev, 2.0 * M_PI), scale);
-        residency(0, true, 0u, F(0), F(0), false);
+        residency(0, true, 0u, make_rot<F>(0.0, 0.0, 0.0, 0.0), false);
     }
     for (uint32_t z = tid; z < dim; z += blockDim.x) amp[z] = tile[swz<F>(z)];
 }
@@ -688,39 +901,65 @@ inline unsigned grid_for(uint64_t work, unsigned per_block, unsigned cap)
     return (unsigned)g;
 }
 
-template <typename F, typename ET, int TB, int RB, bool PHASE>
+template <typename F, typename ET, int TB, int RB, bool PHASE, bool FUSE, bool PIPE>
 hipError_t launch_pass_p(void *amp, const void *table, const PassDesc &d, hipStream_t s)
 {
     using F2 = typename V2<F>::T;
     constexpr int DT = sizeof(F) == 4 ? 0 : 1;
     constexpr size_t TS = size_t(1) << TB;
     const size_t lds = sizeof(F2) * (TS + kPadN[DT] * (TS >> kPadS[DT]) + lut_cap<ET>()) + sizeof(ET) * TS;
+    const void *fn = reinterpret_cast<const void *>(&pass_kernel<F, ET, TB, RB, PHASE, FUSE, PIPE>);
     // persistent grid: as many workgroups as fit on the device at once
-    static unsigned resident = 0;
-    if (!resident) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&pass_kernel<F, ET, TB, RB, PHASE>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    // (set up once per instantiation; static initialisation is thread-safe)
+    struct Setup {
+        hipError_t err;
+        unsigned resident;
+    };
+    static const Setup setup = [&] {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         int dev = 0, cus = 0, per_cu = 0;
         if (e == hipSuccess) e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e == hipSuccess)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, reinterpret_cast<const void *>(&pass_kernel<F, ET, TB, RB, PHASE>), 1 << (TB - RB), lds);
-        if (e != hipSuccess) return e;
-        resident = (unsigned)std::max(1, cus * std::max(1, per_cu));
-    }
-    const uint64_t ntiles = 1ull << (d.n - TB);
-    const unsigned grid = (unsigned)std::min<uint64_t>(ntiles, resident);
-    hipLaunchKernelGGL((pass_kernel<F, ET, TB, RB, PHASE>), dim3(grid), dim3(1u << (TB - RB)), lds, s,
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 1 << (TB - RB), lds);
+        return Setup{e, (unsigned)std::max(1, cus * std::max(1, per_cu))};
+    }();
+    if (setup.err != hipSuccess) return setup.err;
+    const unsigned grid = PIPE ? (unsigned)std::min<uint64_t>(d.tile_count, setup.resident) : (unsigned)d.tile_count;
+    hipLaunchKernelGGL((pass_kernel<F, ET, TB, RB, PHASE, FUSE, PIPE>), dim3(grid), dim3(1u << (TB - RB)), lds, s,
                        reinterpret_cast<F2 *>(amp), reinterpret_cast<const ET *>(table), d);
     return hipGetLastError();
+}
+
+// Kernel variant (tuning switch, QAA_PASS_VARIANT): bit 0 fused two-qubit
+// rotations, bit 1 persistent pipelined grid.  Default 2.
+inline int pass_variant()
+{
+    static const int v = [] {
+        const char *e = std::getenv("QAA_PASS_VARIANT");
+        return e ? (std::atoi(e) & 3) : 2;
+    }();
+    return v;
+}
+
+template <typename F, typename ET, int TB, int RB, bool PHASE>
+hipError_t launch_pass_v(void *amp, const void *table, const PassDesc &d, hipStream_t s)
+{
+    if constexpr (sizeof(F) == 4 && sizeof(ET) == 1) {
+        switch (pass_variant()) {
+        case 0: return launch_pass_p<F, ET, TB, RB, PHASE, false, false>(amp, table, d, s);
+        case 1: return launch_pass_p<F, ET, TB, RB, PHASE, true, false>(amp, table, d, s);
+        case 3: return launch_pass_p<F, ET, TB, RB, PHASE, true, true>(amp, table, d, s);
+        default: break;
+        }
+    }
+    return launch_pass_p<F, ET, TB, RB, PHASE, false, true>(amp, table, d, s);
 }
 
 template <typename F, typename ET, int TB, int RB>
 hipError_t launch_pass_t(void *amp, const void *table, const PassDesc &d, hipStream_t s)
 {
-    if (d.phase_at >= 0) return launch_pass_p<F, ET, TB, RB, true>(amp, table, d, s);
-    return launch_pass_p<F, ET, TB, RB, false>(amp, table, d, s);
+    if (d.phase_at >= 0) return launch_pass_v<F, ET, TB, RB, true>(amp, table, d, s);
+    return launch_pass_v<F, ET, TB, RB, false>(amp, table, d, s);
 }
 
 template <typename F, typename ET, int RB, int WB>
@@ -728,16 +967,15 @@ hipError_t launch_resident_t(const ResidentDesc *descs_dev, const ResidentDesc *
 {
     using F2 = typename V2<F>::T;
     const size_t lds = sizeof(F2) * ((size_t(1) << (RB + WB)) + lut_cap<ET>()) + sizeof(ET) * (size_t(1) << (RB + WB));
-    static bool attr_done = false;
-    if (!attr_done) {
+    static const hipError_t attr = [&] {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&resident_one_kernel<F, ET, RB, WB>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&resident_batch_kernel<F, ET, RB, WB>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_done = true;
-    }
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&resident_batch_kernel<F, ET, RB, WB>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        return e;
+    }();
+    if (attr != hipSuccess) return attr;
     if (one)
         hipLaunchKernelGGL((resident_one_kernel<F, ET, RB, WB>), dim3(1), dim3(1u << WB), lds, s, *one);
     else
@@ -760,6 +998,37 @@ hipError_t launch_pass(void *amp, int dtype, const void *table, int etype, int t
     if (dtype == 1 && tile_bits == 12 && reg_bits == 4) {
         if (etype == 0) return launch_pass_t<double, uint8_t, 12, 4>(amp, table, d, s);
         return launch_pass_t<double, uint16_t, 12, 4>(amp, table, d, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename F, typename ET, int TB, int RB>
+hipError_t launch_batch_t(const BatchInst *insts, int count, const PassDesc *structs, int64_t s, int j,
+                          uint64_t grid_tiles, hipStream_t st)
+{
+    using F2 = typename V2<F>::T;
+    constexpr int DT = sizeof(F) == 4 ? 0 : 1;
+    constexpr size_t TS = size_t(1) << TB;
+    const size_t lds = sizeof(F2) * (TS + kPadN[DT] * (TS >> kPadS[DT]) + lut_cap<ET>()) + sizeof(ET) * TS;
+    const void *fn = reinterpret_cast<const void *>(&batch_pass_kernel<F, ET, TB, RB, false>);
+    static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL((batch_pass_kernel<F, ET, TB, RB, false>), dim3((unsigned)grid_tiles), dim3(1u << (TB - RB)),
+                       lds, st, insts, count, structs, s, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_pass(const BatchInst *insts, int count, const PassDesc *structs, int64_t s, int j,
+                             uint64_t grid_tiles, int dtype, int etype, int tile_bits, int reg_bits, hipStream_t st)
+{
+    if (grid_tiles == 0) return hipSuccess;
+    if (dtype == 0 && tile_bits == 13 && reg_bits == 5) {
+        if (etype == 0) return launch_batch_t<float, uint8_t, 13, 5>(insts, count, structs, s, j, grid_tiles, st);
+        return launch_batch_t<float, uint16_t, 13, 5>(insts, count, structs, s, j, grid_tiles, st);
+    }
+    if (dtype == 1 && tile_bits == 12 && reg_bits == 4) {
+        if (etype == 0) return launch_batch_t<double, uint8_t, 12, 4>(insts, count, structs, s, j, grid_tiles, st);
+        return launch_batch_t<double, uint16_t, 12, 4>(insts, count, structs, s, j, grid_tiles, st);
     }
     return hipErrorInvalidValue;
 }

@@ -42,6 +42,20 @@ qaa_status ok()
     return QAA_OK;
 }
 
+}  // namespace
+
+// Shared with the server translation unit (same thread-local message).
+qaa_status qaa::set_error(qaa_status st, const char *msg)
+{
+    if (st == QAA_OK)
+        g_last_error.clear();
+    else
+        g_last_error = msg ? msg : "";
+    return st;
+}
+
+namespace {
+
 #define QAA_HIP(call)                                                                      \
     do {                                                                                   \
         hipError_t e_ = (call);                                                            \
@@ -60,6 +74,8 @@ struct DeviceCtx {
     double *partials = nullptr;             // [2048 * 3]
     double *obs_out = nullptr;              // [4]
     void *host_pinned = nullptr;            // 256 B staging for readbacks
+    hipStream_t side = nullptr;             // second stream for batched small states
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 std::mutex g_dev_mu;
@@ -86,6 +102,9 @@ qaa_status device_ctx(DeviceCtx **out)
         ctx->obs_out = reinterpret_cast<double *>(base + 128);
         ctx->partials = reinterpret_cast<double *>(base + 256);
         QAA_HIP(hipHostMalloc(&ctx->host_pinned, 256, hipHostMallocDefault));
+        QAA_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+        QAA_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+        QAA_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
         ctx->ready = true;
     }
     *out = ctx;
@@ -406,7 +425,7 @@ bool io_capable(const Group &g, int vw)
 }
 
 struct StepCoef {
-    double s, theta, cm1, sn;
+    double s, theta, cm1, sn, s2, cs;
 };
 
 StepCoef step_coef(double T, int64_t N, int64_t k)
@@ -418,6 +437,8 @@ StepCoef step_coef(double T, int64_t N, int64_t k)
     const double q = std::sin(0.25 * c.theta);
     c.cm1 = -2.0 * q * q;
     c.sn = std::sin(0.5 * c.theta);
+    c.s2 = c.sn * c.sn;
+    c.cs = 0.5 * std::sin(c.theta);
     return c;
 }
 
@@ -492,7 +513,7 @@ void fill_residencies(PassDesc &d, const SetPlan &sp, int tb, int rb, int dt, bo
     }
 }
 
-qaa_status run_resident(const qaa_state *st, double T, int64_t N, int64_t k0, int64_t k1, hipStream_t s)
+ResidentDesc make_resident_desc(const qaa_state *st, double T, int64_t N, int64_t k0, int64_t k1)
 {
     const int n = st->inst->n;
     const int dt = (int)st->dtype;
@@ -519,7 +540,13 @@ qaa_status run_resident(const qaa_state *st, double T, int64_t N, int64_t k0, in
             if (std::find(gs[g].bits.begin(), gs[g].bits.end(), b) == gs[g].bits.end()) d.tpos[g][k++] = (uint8_t)b;
         d.gmask[g] = (uint8_t)gs[g].rot;
     }
-    QAA_HIP(launch_resident(nullptr, &d, 1, dt, (int)st->etype, s));
+    return d;
+}
+
+qaa_status run_resident(const qaa_state *st, double T, int64_t N, int64_t k0, int64_t k1, hipStream_t s)
+{
+    const ResidentDesc d = make_resident_desc(st, T, N, k0, k1);
+    QAA_HIP(launch_resident(nullptr, &d, 1, (int)st->dtype, (int)st->etype, s));
     return QAA_OK;
 }
 
@@ -556,35 +583,109 @@ std::vector<PassDesc> build_passes(const Plan &p, int n, int dty, int emax, doub
                     d.rest_mask |= 1ull << b;
                 }
             d.n_rest = nr;
+            d.set_id = set;
+            d.tile_begin = 0;
+            d.tile_count = 1ull << nr;
             if (first) {
                 // k == k0: half phase of step k0, then this set's rotations
                 d.phi = 0.5 * dt * ck.s;
                 d.gphase = 0.0;
                 d.cm1B = ck.cm1;
                 d.sB = ck.sn;
+                d.s2B = ck.s2;
+                d.csB = ck.cs;
                 fill_residencies(d, sp, TB, RB, dty, false, true, true);
             } else if (last && k + 1 < k1) {
                 const StepCoef cn = step_coef(T, N, k + 1);
                 d.cm1A = ck.cm1;
                 d.sA = ck.sn;
+                d.s2A = ck.s2;
+                d.csA = ck.cs;
                 d.phi = 0.5 * dt * (ck.s + cn.s);
                 d.gphase = wrap_phase(0.5 * n * ck.theta);
                 d.cm1B = cn.cm1;
                 d.sB = cn.sn;
+                d.s2B = cn.s2;
+                d.csB = cn.cs;
                 fill_residencies(d, sp, TB, RB, dty, true, true, true);
             } else if (last) {
                 d.cm1A = ck.cm1;
                 d.sA = ck.sn;
+                d.s2A = ck.s2;
+                d.csA = ck.cs;
                 d.phi = 0.5 * dt * ck.s;
                 d.gphase = wrap_phase(0.5 * n * ck.theta);
                 fill_residencies(d, sp, TB, RB, dty, true, true, false);
             } else {
                 d.cm1A = ck.cm1;
                 d.sA = ck.sn;
+                d.s2A = ck.s2;
+                d.csA = ck.cs;
                 fill_residencies(d, sp, TB, RB, dty, true, false, false);
             }
             out.push_back(d);
         }
+    }
+    return out;
+}
+
+// Cache blocking.  Between two passes over the top qubit set, every other
+// pass keeps the top bits of the index fixed inside each tile, so those
+// passes can run group by group: all of them over the tiles whose top
+// `cbits` index bits equal g, then all of them for g + 1, ...  A group of
+// 2^(log2 bytes) bytes stays in the device's last-level caches between those
+// passes, so only the first read and the final write of a group reach HBM.
+// Off by default (measured slower at n = 28: each chunked launch is too
+// short for the persistent pipeline); QAA_CHUNK_LOG2_BYTES = log2 of the
+// group size in bytes turns it on.
+int chunk_log2_bytes()
+{
+    const char *e = std::getenv("QAA_CHUNK_LOG2_BYTES");
+    return e ? std::atoi(e) : 0;
+}
+
+std::vector<PassDesc> schedule_passes(const std::vector<PassDesc> &in, const Plan &p, int n, int amp_log2_bytes)
+{
+    const int top = (int)p.sets.size() - 1;
+    const int lg = chunk_log2_bytes();
+    if (lg <= 0 || top < 2) return in;
+    // the group index is made of the highest index bits, which must all be
+    // rotated by the top set (so that no other pass mixes groups)
+    int top_lo = n;
+    for (size_t j = 0; j < p.sets[top].rot_local.size(); ++j)
+        top_lo = std::min(top_lo, p.sets[top].tile[p.sets[top].rot_local[j]]);
+    const int cbits = std::min(std::max(0, n + amp_log2_bytes - lg), n - top_lo);
+    if (cbits == 0) return in;
+    std::vector<PassDesc> out;
+    size_t i = 0;
+    while (i < in.size()) {
+        if (in[i].set_id == top) {
+            out.push_back(in[i++]);
+            continue;
+        }
+        size_t j = i;
+        while (j < in.size() && in[j].set_id != top) ++j;
+        // passes [i, j) never touch the top set: split them by chunk group,
+        // when the top cbits of every tile-id are the top cbits of the index
+        bool ok = true;
+        for (size_t q = i; q < j && ok; ++q) {
+            const PassDesc &d = in[q];
+            if (d.n_rest < cbits) ok = false;
+            for (int b = 0; b < cbits && ok; ++b)
+                if (d.rest_pos[d.n_rest - cbits + b] != n - cbits + b) ok = false;
+        }
+        if (!ok || j - i < 2) {
+            for (size_t q = i; q < j; ++q) out.push_back(in[q]);
+        } else {
+            for (uint64_t g = 0; g < (1ull << cbits); ++g)
+                for (size_t q = i; q < j; ++q) {
+                    PassDesc d = in[q];
+                    d.tile_count = 1ull << (d.n_rest - cbits);
+                    d.tile_begin = g * d.tile_count;
+                    out.push_back(d);
+                }
+        }
+        i = j;
     }
     return out;
 }
@@ -641,6 +742,12 @@ hipError_t prof_drain(bool wait)
     return hipSuccess;
 }
 
+std::vector<PassDesc> plan_passes(const Plan &p, int n, int dty, int emax, double T, int64_t N, int64_t k0,
+                                  int64_t k1)
+{
+    return schedule_passes(build_passes(p, n, dty, emax, T, N, k0, k1), p, n, dty == 0 ? 3 : 4);
+}
+
 // Norm control (see PassDesc) is on unless QAA_NORM_CONTROL=0 is set in
 // the environment (used to measure the uncorrected FP32 drift).
 bool norm_control_enabled()
@@ -655,16 +762,11 @@ bool norm_control_enabled()
 qaa_status run_passes(const qaa_state *st, const Plan &p, double T, int64_t N, int64_t k0, int64_t k1,
                       hipStream_t s)
 {
-    std::vector<PassDesc> ps = build_passes(p, st->inst->n, (int)st->dtype, st->inst->e_max, T, N, k0, k1);
+    const std::vector<PassDesc> ps = plan_passes(p, st->inst->n, (int)st->dtype, st->inst->e_max, T, N, k0, k1);
     unsigned long long *acc = nullptr;
     if (norm_control_enabled()) {
         QAA_HIP(hipMallocAsync(reinterpret_cast<void **>(&acc), 3 * sizeof(unsigned long long), s));
         QAA_HIP(launch_zero_u64(acc, 3, s));
-        for (size_t j = 0; j < ps.size(); ++j) {
-            ps[j].acc_out = acc + j % 3;
-            ps[j].acc_zero = acc + (j + 1) % 3;
-            ps[j].acc_in = j > 0 ? acc + (j + 2) % 3 : nullptr;
-        }
     }
     bool prof;
     {
@@ -674,14 +776,26 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, double T, int64_t N, i
     const double amp_bytes = st->dtype == QAA_C64 ? 8.0 : 16.0;
     const double e_bytes = st->etype == QAA_E_U8 ? 1.0 : 2.0;
     const double dim = std::ldexp(1.0, st->inst->n);
-    for (const PassDesc &d : ps) {
+    int64_t gj = 0;     // index of the next norm-carrying pass
+    const int top = (int)p.sets.size() - 1;
+    for (PassDesc d : ps) {
+        // Norm control rides on the passes over the top qubit set: each one
+        // measures the norm of its output, and rescales by the norm the
+        // previous one measured (passes over other sets carry no norm work).
+        if (acc && d.set_id == top) {
+            d.acc_out = acc + gj % 3;
+            d.acc_zero = acc + (gj + 1) % 3;
+            d.acc_in = gj > 0 ? acc + (gj + 2) % 3 : nullptr;
+            ++gj;
+        }
         ProfRec rec{};
         if (prof) {
             std::lock_guard<std::mutex> lk(g_prof_mu);
             if (g_prof_live.size() > 4096) QAA_HIP(prof_drain(false));
             QAA_HIP(prof_event(&rec.a));
             QAA_HIP(prof_event(&rec.b));
-            rec.bytes = dim * (2.0 * amp_bytes + (d.phase_at >= 0 ? e_bytes : 0.0));
+            rec.bytes = dim * (double)d.tile_count / std::ldexp(1.0, d.n_rest) *
+                        (2.0 * amp_bytes + (d.phase_at >= 0 ? e_bytes : 0.0));
             QAA_HIP(hipEventRecord(rec.a, s));
         }
         hipError_t e = launch_pass(st->amp, (int)st->dtype, st->table, (int)st->etype, p.tile_bits, p.reg_bits, d, s);
@@ -737,6 +851,125 @@ extern "C" qaa_status qaa_evolve_range(const qaa_state *st, const qaa_schedule *
     return evolve_common(st, sched, T, steps, k0, k1, stream, "qaa_evolve_range");
 }
 
+namespace {
+
+// Pass structures of one qubit count for the batched kernel, in the kind
+// order documented at BatchInst.
+void batch_structs(const Plan &p, int n, int dty, std::vector<PassDesc> &out)
+{
+    const int TB = p.tile_bits, RB = p.reg_bits;
+    const int r = (int)p.sets.size();
+    auto make = [&](int set, bool v1, bool ph, bool v2) {
+        PassDesc d;
+        std::memset(&d, 0, sizeof d);
+        d.n = n;
+        const SetPlan &sp = p.sets[set];
+        for (int j = 0; j < TB; ++j) d.tile_pos[j] = (uint8_t)sp.tile[j];
+        int nr = 0;
+        for (int b = 0; b < n; ++b)
+            if (!contains(sp.tile, b)) {
+                d.rest_pos[nr++] = (uint8_t)b;
+                d.rest_mask |= 1ull << b;
+            }
+        d.n_rest = nr;
+        d.set_id = set;
+        d.tile_count = 1ull << nr;
+        fill_residencies(d, sp, TB, RB, dty, v1, ph, v2);
+        out.push_back(d);
+    };
+    make(0, false, true, true);                          // kind 0: first pass
+    for (int m = 1; m <= r - 2; ++m) make(m, true, false, false);
+    make(r - 1, true, true, true);                       // turn at the top set
+    make(0, true, true, true);                           // turn at set 0
+    make(r - 1, true, true, false);                      // last pass at the top set
+    make(0, true, true, false);                          // last pass at set 0
+}
+
+template <typename T>
+qaa_status upload(const std::vector<T> &host, T **dev, hipStream_t s)
+{
+    const size_t bytes = sizeof(T) * std::max<size_t>(1, host.size());
+    QAA_HIP(hipMallocAsync(reinterpret_cast<void **>(dev), bytes, s));
+    void *pinned = nullptr;
+    QAA_HIP(hipHostMalloc(&pinned, bytes, hipHostMallocDefault));
+    std::memcpy(pinned, host.data(), sizeof(T) * host.size());
+    hipError_t e = hipMemcpyAsync(*dev, pinned, sizeof(T) * host.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipHostFree(pinned);
+    if (e != hipSuccess) return fail(QAA_ERR_DEVICE, "descriptor upload failed: %s", hipGetErrorString(e));
+    return QAA_OK;
+}
+
+// Lock-step batched passes for states of one dtype/etype above the resident size.
+qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states, const double *T,
+                            const int64_t *steps, hipStream_t s)
+{
+    if (idx.empty()) return QAA_OK;
+    const int dty = (int)states[idx[0]].dtype, ety = (int)states[idx[0]].etype;
+    std::vector<int> order(idx);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return steps[a] > steps[b]; });
+    std::vector<PassDesc> structs;
+    std::map<int, int> base_of_n;
+    std::vector<BatchInst> insts;
+    uint64_t tiles = 0;
+    int rmax = 0, TB = 0, RB = 0;
+    std::vector<uint64_t> prefix;       // tiles of the first q states
+    prefix.push_back(0);
+    for (int i : order) {
+        const int n = states[i].inst->n;
+        const Plan p = make_plan(n, dty);
+        if (!base_of_n.count(n)) {
+            base_of_n[n] = (int)structs.size();
+            batch_structs(p, n, dty, structs);
+        }
+        TB = p.tile_bits;
+        RB = p.reg_bits;
+        rmax = std::max(rmax, (int)p.sets.size());
+        BatchInst b;
+        std::memset(&b, 0, sizeof b);
+        b.amp = states[i].amp;
+        b.table = states[i].table;
+        b.T = T[i];
+        b.N = steps[i];
+        b.tile_offset = tiles;
+        b.n = n;
+        b.emax = states[i].inst->e_max;
+        b.r = (int)p.sets.size();
+        b.struct_base = base_of_n[n];
+        tiles += 1ull << (n - TB);
+        prefix.push_back(tiles);
+        insts.push_back(b);
+    }
+    unsigned long long *acc = nullptr;
+    const int cnt = (int)insts.size();
+    if (norm_control_enabled()) {
+        QAA_HIP(hipMallocAsync(reinterpret_cast<void **>(&acc), 3 * sizeof(unsigned long long) * cnt, s));
+        QAA_HIP(launch_zero_u64(acc, 3 * cnt, s));
+        for (int q = 0; q < cnt; ++q) insts[q].acc = acc + 3 * q;
+    }
+    BatchInst *d_insts = nullptr;
+    PassDesc *d_structs = nullptr;
+    qaa_status r = upload(insts, &d_insts, s);
+    if (r == QAA_OK) r = upload(structs, &d_structs, s);
+    if (r != QAA_OK) return r;
+    const int64_t maxN = insts[0].N;
+    int active = cnt;
+    for (int64_t k = 0; k < maxN; ++k) {
+        while (active > 0 && insts[active - 1].N <= k) --active;
+        const int jn = k == 0 ? rmax : rmax - 1;
+        for (int j = 0; j < jn; ++j) {
+            hipError_t e = launch_batch_pass(d_insts, active, d_structs, k, j, prefix[active], dty, ety, TB, RB, s);
+            if (e != hipSuccess) return fail(QAA_ERR_DEVICE, "batched pass launch failed: %s", hipGetErrorString(e));
+        }
+    }
+    QAA_HIP(hipFreeAsync(d_insts, s));
+    QAA_HIP(hipFreeAsync(d_structs, s));
+    if (acc) QAA_HIP(hipFreeAsync(acc, s));
+    return QAA_OK;
+}
+
+}  // namespace
+
 extern "C" qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, const double *T,
                                        const int64_t *steps, void *stream)
 {
@@ -744,9 +977,48 @@ extern "C" qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, c
     if (count == 0) return ok();
     if (!states || !T || !steps) return fail(QAA_ERR_INVALID_ARG, "qaa_evolve_batch: NULL array");
     for (int i = 0; i < count; ++i) {
-        qaa_status r = evolve_common(&states[i], nullptr, T[i], steps[i], 0, steps[i], stream, "qaa_evolve_batch");
+        qaa_status r = check_state_table(&states[i], "qaa_evolve_batch");
         if (r != QAA_OK) return r;
+        if (!(T[i] >= 0.0) || !std::isfinite(T[i]) || steps[i] < 0)
+            return fail(QAA_ERR_INVALID_ARG, "qaa_evolve_batch: state %d has a bad T or step count", i);
+        if (states[i].inst->e_max >= lut_limit(states[i].etype))
+            return fail(QAA_ERR_UNSUPPORTED, "qaa_evolve_batch: state %d E_max exceeds the phase table", i);
     }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    DeviceCtx *ctx = nullptr;
+    qaa_status r = device_ctx(&ctx);
+    if (r != QAA_OK) return r;
+    // small states: one resident launch per dtype/etype on the side stream;
+    // larger ones: lock-step batched passes per dtype/etype on the caller's
+    std::vector<ResidentDesc> small[2][2];
+    std::vector<int> large[2][2];
+    for (int i = 0; i < count; ++i) {
+        if (steps[i] == 0) continue;
+        const int dt = (int)states[i].dtype, et = (int)states[i].etype;
+        if (make_plan(states[i].inst->n, dt).resident)
+            small[dt][et].push_back(make_resident_desc(&states[i], T[i], steps[i], 0, steps[i]));
+        else
+            large[dt][et].push_back(i);
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    QAA_HIP(hipEventRecord(ctx->ev_fork, s));
+    QAA_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+    for (int dt = 0; dt < 2; ++dt)
+        for (int et = 0; et < 2; ++et) {
+            if (small[dt][et].empty()) continue;
+            ResidentDesc *d = nullptr;
+            r = upload(small[dt][et], &d, ctx->side);
+            if (r != QAA_OK) return r;
+            QAA_HIP(launch_resident(d, nullptr, (int)small[dt][et].size(), dt, et, ctx->side));
+            QAA_HIP(hipFreeAsync(d, ctx->side));
+        }
+    for (int dt = 0; dt < 2; ++dt)
+        for (int et = 0; et < 2; ++et) {
+            r = run_batch_passes(large[dt][et], states, T, steps, s);
+            if (r != QAA_OK) return r;
+        }
+    QAA_HIP(hipEventRecord(ctx->ev_join, ctx->side));
+    QAA_HIP(hipStreamWaitEvent(s, ctx->ev_join, 0));
     return ok();
 }
 
@@ -806,7 +1078,7 @@ extern "C" qaa_status qaa_debug_pass_descs(int32_t n, qaa_dtype dtype, int32_t e
         *count = 0;
         return ok();
     }
-    const std::vector<PassDesc> ps = build_passes(p, n, (int)dtype, emax, T, steps, k0, k1);
+    const std::vector<PassDesc> ps = plan_passes(p, n, (int)dtype, emax, T, steps, k0, k1);
     *count = (int32_t)ps.size();
     if (out && capacity > 0)
         std::memcpy(out, ps.data(), sizeof(PassDesc) * std::min<size_t>(ps.size(), (size_t)capacity));

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "qaa.h"
+
 namespace qaa {
 
 // Largest number of register-group residencies in one pass (see PassDesc).
@@ -68,9 +70,12 @@ struct PassDesc {
     int32_t n_res;
     int32_t phase_at;          // -1: no phase in this pass
     int32_t emax;              // largest E value the LUT must cover
-    int32_t pad_;
+    int32_t set_id;            // qubit set of this pass (host bookkeeping)
     double cm1A, sA, cm1B, sB;
+    double s2A, csA, s2B, csB;     // sin^2(theta/2) and sin(theta/2) cos(theta/2) of sets A / B
     double phi, gphase;
+    uint64_t tile_begin;       // this launch handles tiles [tile_begin, tile_begin + tile_count)
+    uint64_t tile_count;
     unsigned long long *acc_in;
     unsigned long long *acc_out;
     unsigned long long *acc_zero;
@@ -113,6 +118,26 @@ struct ResidentDesc {
     uint8_t gmask[8];          // register bits of group g that rotate
 };
 
+// One state of a batched evolution run pass by pass (n above the resident
+// size).  Every launch applies one pass of step s to every state that is
+// still running; a workgroup finds its state from its global tile number.
+// The pass structure comes from structs[struct_base + kind] with
+//   kind 0: first pass (half phase, then set 0),
+//   kind m (1 <= m <= r-2): middle pass over set m,
+//   kind r-1 / r: turn pass over set r-1 / set 0,
+//   kind r+1 / r+2: last pass over set r-1 / set 0,
+// and the rotation and phase coefficients are computed on the device from
+// (T, N, s) exactly as the host computes them for a single state.
+struct BatchInst {
+    void *amp;
+    const void *table;
+    unsigned long long *acc;   // 3 norm-control slots of this state
+    double T;
+    int64_t N;
+    uint64_t tile_offset;      // first global tile of this state
+    int32_t n, emax, r, struct_base;
+};
+
 // Kernel launch helpers (defined in the .hip files).
 hipError_t launch_energy(const ClauseRec *cl, int m, int n, void *table, int etype,
                          uint32_t *stats, hipStream_t s);
@@ -123,6 +148,10 @@ hipError_t launch_init_basis(void *amp, int dtype, int n, uint64_t z0, hipStream
 hipError_t launch_pass(void *amp, int dtype, const void *table, int etype, int tile_bits,
                        int reg_bits, const PassDesc &d, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, int count, hipStream_t s);
+// One lock-step pass (step s, sub-pass j) of a batch; grid = tiles of the
+// states listed (count of them, sorted so that running ones come first).
+hipError_t launch_batch_pass(const BatchInst *insts, int count, const PassDesc *structs, int64_t s, int j,
+                             uint64_t grid_tiles, int dtype, int etype, int tile_bits, int reg_bits, hipStream_t st);
 // Resident evolution: one state (one != nullptr, descriptor by value) or a
 // batch of `count` states whose descriptors are in device memory.
 hipError_t launch_resident(const ResidentDesc *descs_dev, const ResidentDesc *one, int count, int dtype,
@@ -140,5 +169,9 @@ hipError_t launch_observables(const void *amp, int dtype, const void *table, int
                               int emin, double *partials, int nblocks, double *out,
                               hipStream_t s);
 int observables_blocks(int n);
+
+// Sets the calling thread's qaa_last_error() message (cleared for QAA_OK)
+// and returns st.
+qaa_status set_error(qaa_status st, const char *msg);
 
 }  // namespace qaa

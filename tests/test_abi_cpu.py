@@ -126,3 +126,33 @@ def test_plan_info_rejects():
         qaa.qaa_plan_info(0)
     with pytest.raises(qaa.QaaError):
         qaa.qaa_plan_info(10, 3)
+
+
+def test_server_create_rejects_bad_config():
+    lib = qaa._lib
+    out = ctypes.c_void_p()
+    assert lib.qaa_server_create(None, ctypes.byref(out)) == qaa.QAA_ERR_INVALID_ARG
+    for slots, budget in [(0, 1 << 30), (65, 1 << 30), (2, 0)]:
+        cfg = qaa.qaa_server_config(budget, slots, 0)
+        assert lib.qaa_server_create(ctypes.byref(cfg), ctypes.byref(out)) == qaa.QAA_ERR_INVALID_ARG
+        assert out.value is None
+    cfg = qaa.qaa_server_config(1 << 30, 2, 0)
+    assert lib.qaa_server_create(ctypes.byref(cfg), None) == qaa.QAA_ERR_INVALID_ARG
+    # calls on a NULL server are rejected, destroy ignores it
+    t = ctypes.c_int64()
+    lits = (ctypes.c_int32 * 3)(1, 2, 3)
+    assert lib.qaa_server_submit(None, 3, 1, lits, 1.0, 10, ctypes.byref(t)) == qaa.QAA_ERR_INVALID_ARG
+    r = qaa.qaa_server_result()
+    assert lib.qaa_server_poll(None, 1, ctypes.byref(r)) == qaa.QAA_ERR_INVALID_ARG
+    assert lib.qaa_server_wait(None, 1, ctypes.byref(r)) == qaa.QAA_ERR_INVALID_ARG
+    assert lib.qaa_server_stats(None, None, None, None) == qaa.QAA_ERR_INVALID_ARG
+    lib.qaa_server_destroy(None)
+
+
+def test_one_hip_runtime_in_process():
+    # the binding loads torch first, so libqaa shares torch's HIP runtime
+    # instead of mapping a second copy that would compete for the device
+    pytest.importorskip("torch")
+    maps = open("/proc/self/maps").read().splitlines()
+    hip = {line.split()[-1] for line in maps if "libamdhip64" in line}
+    assert len(hip) == 1, hip

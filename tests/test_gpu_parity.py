@@ -251,22 +251,49 @@ def test_observables_match_oracle_on_same_state(qaa):
 
 
 def test_batch_equals_individual(qaa):
-    ns = [6, 10, 13, 14, 17]
-    Ts = [3.0, 4.0, 5.0, 6.0, 7.0]
-    Ns = [30, 40, 50, 20, 10]
-    insts, tables, singles, batch = [], [], [], []
+    """One batched call over uneven n (resident and multi-pass states) gives
+    each state what qaa_evolve gives it alone (same plan; the batched passes
+    compute their coefficients on the device, so agreement is to rounding)."""
+    ns = [6, 10, 13, 14, 15, 17, 21, 22, 14]
+    Ts = [3.0, 4.0, 5.0, 6.0, 7.0, 2.5, 4.5, 3.5, 0.0]
+    Ns = [30, 40, 50, 20, 9, 10, 7, 5, 0]
+    insts, singles, batch = [], [], []
     for i, n in enumerate(ns):
         inst_in = planted_unique_3sat(n, 300 + i)
         inst = qaa.Instance(n, inst_in.literals())
         table = inst.energy_table()
-        insts.append(inst)
-        tables.append(table)
+        insts.append((inst, inst_in))
         singles.append(qaa.State(inst, table).init_uniform().evolve(Ts[i], Ns[i]))
         batch.append(qaa.State(inst, table).init_uniform())
     qaa.qaa_evolve_batch([b.c for b in batch], Ts, Ns)
     torch.cuda.synchronize()
-    for s, b in zip(singles, batch):
-        assert torch.equal(s.amp, b.amp)
+    for (inst, inst_in), n, T, N, sgl, b in zip(insts, ns, Ts, Ns, singles, batch):
+        diff = float(torch.linalg.vector_norm((sgl.amp - b.amp).to(torch.complex128)).item())
+        assert diff < 2e-6, (n, diff)
+        if n <= 17:
+            psi, ref = _oracle_run(n, inst_in.clauses, T, N)
+            _compare(b, b.observables(), psi, ref, L2_TOL_C64, P_TOL_C64)
+
+
+def test_batch_many_uneven_states_vs_oracle(qaa):
+    """A batch drawn like the batched workload (n uniform, T uniform,
+    steps = round(T/dt)), shortened: 40 states, n in 12..17, T in [1, 3)."""
+    from qaa_inputs import batch_workload
+    wl = batch_workload(40, seed=99, n_lo=12, n_hi=17, t_lo=1.0, t_hi=3.0, dt=0.01)
+    states, Ts, Ns, ins = [], [], [], []
+    for n, T, N, iseed in wl:
+        inst_in = planted_unique_3sat(n, iseed)
+        inst = qaa.Instance(n, inst_in.literals())
+        st = qaa.State(inst, inst.energy_table()).init_uniform()
+        states.append(st)
+        Ts.append(T)
+        Ns.append(N)
+        ins.append(inst_in)
+    qaa.qaa_evolve_batch([st.c for st in states], Ts, Ns)
+    torch.cuda.synchronize()
+    for st, inst_in, (n, T, N, _) in list(zip(states, ins, wl))[::5]:
+        psi, ref = _oracle_run(n, inst_in.clauses, T, N)
+        _compare(st, st.observables(), psi, ref, L2_TOL_C64, P_TOL_C64)
 
 
 # --------------------------------------------------------------------------

@@ -1,0 +1,102 @@
+"""GPU tests of the solve-request server (qaa_server_*): every result equals
+the same solve run alone through qaa_evolve, admission never exceeds the HBM
+budget, and oversize or malformed requests are reported."""
+import numpy as np
+import pytest
+
+import oracle
+from qaa_inputs import planted_unique_3sat
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qaa():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1103_1399_amd as m
+    return m
+
+
+def _solo(qaa, n, lits, T, steps):
+    inst = qaa.Instance(n, lits)
+    table = inst.energy_table()
+    st = qaa.State(inst, table)
+    st.init_uniform()
+    st.evolve(T, steps)
+    obs = st.observables()
+    torch.cuda.synchronize()
+    inst.close()
+    return obs
+
+
+def _mix():
+    reqs = []
+    for i, (n, T, steps) in enumerate([(8, 4.0, 40), (11, 5.0, 50), (14, 5.0, 30), (16, 6.0, 30), (9, 3.0, 25),
+                                       (18, 5.0, 12), (13, 6.0, 60), (15, 4.0, 20), (20, 5.0, 6), (12, 2.0, 17)]):
+        inst = planted_unique_3sat(n, 100 + i)
+        reqs.append((n, inst.literals(), T, steps))
+    return reqs
+
+
+def test_server_results_equal_solo_runs(qaa):
+    reqs = _mix()
+    sv = qaa.qaa_server_create(hbm_budget_bytes=1 << 30, slots=4)
+    try:
+        tickets = [qaa.qaa_server_submit(sv, n, lits, T, steps) for n, lits, T, steps in reqs]
+        results = [qaa.qaa_server_wait(sv, t) for t in tickets]
+    finally:
+        qaa.qaa_server_destroy(sv)
+    for (n, lits, T, steps), r in zip(reqs, results):
+        assert r["done"] and r["status"] == qaa.QAA_OK, (n, r)
+        assert 0.0 <= r["queued_s"] <= r["latency_s"]
+        solo = _solo(qaa, n, lits, T, steps)
+        # same kernels, same plan, deterministic reductions: identical numbers
+        for key in ("norm", "energy", "p_success", "e_min", "degeneracy"):
+            assert r[key] == solo[key], (n, key, r[key], solo[key])
+
+
+def test_server_result_matches_oracle(qaa):
+    n, T, steps = 12, 6.0, 80
+    inst = planted_unique_3sat(n, 7)
+    sv = qaa.qaa_server_create(hbm_budget_bytes=1 << 28, slots=1)
+    try:
+        r = qaa.qaa_server_wait(sv, qaa.qaa_server_submit(sv, n, inst.literals(), T, steps))
+    finally:
+        qaa.qaa_server_destroy(sv)
+    psi = oracle.init_uniform(n)
+    oracle.evolve(n, inst.clauses, psi, T, steps)
+    ref = oracle.observables(n, inst.clauses, psi)
+    assert abs(r["p_success"] - ref["p_success"]) <= 1e-5
+    assert abs(r["energy"] - ref["energy"]) <= 1e-4
+    assert abs(r["norm"] - 1.0) <= 1e-5
+
+
+def test_server_admission_respects_budget(qaa):
+    n = 18
+    fp = (1 << n) * 9
+    sv = qaa.qaa_server_create(hbm_budget_bytes=2 * fp, slots=4)
+    try:
+        tickets = [qaa.qaa_server_submit(sv, n, planted_unique_3sat(n, 200 + i).literals(), 5.0, 40)
+                   for i in range(6)]
+        peak = 0
+        while True:
+            s = qaa.qaa_server_stats(sv)
+            peak = max(peak, s["bytes_in_use"])
+            assert s["running"] <= 2 and s["bytes_in_use"] <= 2 * fp
+            if s["queued"] == 0 and s["running"] == 0:
+                break
+        res = [qaa.qaa_server_wait(sv, t) for t in tickets]
+        assert all(r["done"] and r["status"] == qaa.QAA_OK for r in res)
+        assert qaa.qaa_server_stats(sv)["bytes_in_use"] == 0
+        # too large for the whole budget: refused at submit
+        with pytest.raises(qaa.QaaError) as e:
+            qaa.qaa_server_submit(sv, n + 2, planted_unique_3sat(n + 2, 1).literals(), 1.0, 1)
+        assert e.value.status == qaa.QAA_ERR_OUT_OF_MEMORY
+        # malformed clauses: reported through the result
+        t = qaa.qaa_server_submit(sv, 5, [1, 2, 9], 1.0, 1)
+        r = qaa.qaa_server_wait(sv, t)
+        assert r["done"] and r["status"] == qaa.QAA_ERR_INVALID_ARG
+    finally:
+        qaa.qaa_server_destroy(sv)
