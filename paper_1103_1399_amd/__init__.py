@@ -233,9 +233,8 @@ class PassDesc(ctypes.Structure):
     """Mirror of the library's internal pass descriptor (diagnostics only)."""
     _fields_ = [("n", ctypes.c_int32), ("n_rest", ctypes.c_int32), ("n_res", ctypes.c_int32),
                 ("phase_at", ctypes.c_int32), ("emax", ctypes.c_int32), ("set_id", ctypes.c_int32),
-                ("cm1A", ctypes.c_double), ("sA", ctypes.c_double), ("cm1B", ctypes.c_double),
-                ("sB", ctypes.c_double), ("s2A", ctypes.c_double), ("csA", ctypes.c_double),
-                ("s2B", ctypes.c_double), ("csB", ctypes.c_double),
+                ("tA", ctypes.c_double), ("sA", ctypes.c_double), ("tB", ctypes.c_double),
+                ("sB", ctypes.c_double),
                 ("phi", ctypes.c_double), ("gphase", ctypes.c_double),
                 ("tile_begin", ctypes.c_uint64), ("tile_count", ctypes.c_uint64),
                 ("acc_in", ctypes.c_void_p), ("acc_out", ctypes.c_void_p), ("acc_zero", ctypes.c_void_p),

@@ -6,8 +6,10 @@
 //  - A step's driver factor exp(-i theta H_B) is applied qubit by qubit as
 //    [[c, i s], [i s, c]] with c = cos(theta/2), s = sin(theta/2); its global
 //    phase exp(-i n theta/2) is folded into the next diagonal phase.
-//  - c is carried as cm1 = c - 1 so that the update x + cm1 x keeps the
-//    small correction exact to FP32 relative precision ("delta form").
+//  - Each 2x2 block is two real plane rotations by theta/2, applied in place
+//    as three shears with t = tan(theta/4) and s (three FMAs per component
+//    pair; the sheared product stays area-preserving under FP32 rounding of
+//    t and s, so no systematic norm drift comes from the coefficients).
 //  - Diagonal phases exp(-i a E) come from a per-launch lookup table over E
 //    evaluated in FP64 and rounded once.
 #include "qaa_internal.h"
@@ -46,15 +48,20 @@ __device__ __forceinline__ F2 cmul(F2 a, F2 b)
     return r;
 }
 
-// Coefficients of one rotation angle theta: cm1 = cos(theta/2) - 1,
-// s = sin(theta/2), s2 = s^2, cs = cos(theta/2) sin(theta/2).
+// Coefficients of one rotation angle theta: t = tan(theta/4),
+// s = sin(theta/2).
 template <typename F>
 struct Rot {
-    F cm1, s, s2, cs;
+    F t, s;
 };
 
 // Rotate register bit b of every pair in v: (x0, x1) <- (c x0 + i s x1,
-// c x1 + i s x0) with c = 1 + cm1.
+// c x1 + i s x0), c = cos(theta/2), s = sin(theta/2).  In real components
+// this is the plane rotation by theta/2 of (Re x0, Im x1) and of
+// (Re x1, Im x0).  Each is applied in place as three shears,
+// u -= t w; w += s u; u -= t w (t = tan(theta/4)): three FMAs per pair of
+// components, no temporaries, and with FP32-rounded t and s the product
+// stays area-preserving, so rounding adds no systematic norm drift.
 template <int RB, typename F2, typename F>
 __device__ __forceinline__ void rotate_bit(F2 (&v)[1 << RB], int b, const Rot<F> &k)
 {
@@ -62,82 +69,32 @@ __device__ __forceinline__ void rotate_bit(F2 (&v)[1 << RB], int b, const Rot<F>
     for (int j = 0; j < (1 << RB); ++j) {
         if (j & (1 << b)) continue;
         const int m = j | (1 << b);
-        const F2 x0 = v[j], x1 = v[m];
-        v[j].x = fma(-k.s, x1.y, fma(k.cm1, x0.x, x0.x));
-        v[j].y = fma(k.s, x1.x, fma(k.cm1, x0.y, x0.y));
-        v[m].x = fma(-k.s, x0.y, fma(k.cm1, x1.x, x1.x));
-        v[m].y = fma(k.s, x0.x, fma(k.cm1, x1.y, x1.y));
-        __builtin_amdgcn_sched_barrier(0);
+        F &u0 = v[j].x, &w0 = v[m].y;     // (Re x0, Im x1)
+        F &u1 = v[m].x, &w1 = v[j].y;     // (Re x1, Im x0)
+        u0 = fma(-k.t, w0, u0);
+        u1 = fma(-k.t, w1, u1);
+        w0 = fma(k.s, u0, w0);
+        w1 = fma(k.s, u1, w1);
+        u0 = fma(-k.t, w0, u0);
+        u1 = fma(-k.t, w1, u1);
     }
 }
 
-// Rotate register bits b1 and b2 together.  With R = c + i s X on each bit
-// and c^2 = 1 - s^2, (R x R) maps a quad (x00, x01, x10, x11) to
-//   y00 = x00 - s^2 A + i c s B,   y11 = x11 - s^2 A + i c s B,
-//   y01 = x01 - s^2 B + i c s A,   y10 = x10 - s^2 B + i c s A,
-// with A = x00 + x11 and B = x01 + x10: 5 instructions per amplitude for
-// the two bits instead of 8, and the small corrections are added last.
+// Rotate every register bit in mask (uniform over the workgroup).
 template <int RB, typename F2, typename F>
-__device__ __forceinline__ void rotate_pair(F2 (&v)[1 << RB], int b1, int b2, const Rot<F> &k)
-{
-#pragma unroll
-    for (int j = 0; j < (1 << RB); ++j) {
-        if ((j & (1 << b1)) || (j & (1 << b2))) continue;
-        const int j01 = j | (1 << b1), j10 = j | (1 << b2), j11 = j01 | (1 << b2);
-        const F2 x00 = v[j], x01 = v[j01], x10 = v[j10], x11 = v[j11];
-        F2 A, B;
-        A.x = x00.x + x11.x;
-        A.y = x00.y + x11.y;
-        B.x = x01.x + x10.x;
-        B.y = x01.y + x10.y;
-        v[j].x = fma(-k.s2, A.x, fma(-k.cs, B.y, x00.x));
-        v[j].y = fma(-k.s2, A.y, fma(k.cs, B.x, x00.y));
-        v[j11].x = fma(-k.s2, A.x, fma(-k.cs, B.y, x11.x));
-        v[j11].y = fma(-k.s2, A.y, fma(k.cs, B.x, x11.y));
-        v[j01].x = fma(-k.s2, B.x, fma(-k.cs, A.y, x01.x));
-        v[j01].y = fma(-k.s2, B.y, fma(k.cs, A.x, x01.y));
-        v[j10].x = fma(-k.s2, B.x, fma(-k.cs, A.y, x10.x));
-        v[j10].y = fma(-k.s2, B.y, fma(k.cs, A.x, x10.y));
-        // one quad at a time: enough independent FMAs per quad, and the
-        // temporaries of later quads do not compete for registers
-        __builtin_amdgcn_sched_barrier(0);
-    }
-}
-
-// Rotate every register bit in mask (uniform): neighbouring bits
-// (P0, P0+1), (P0+2, P0+3), ... go through the fused pair update when both
-// are set; the remaining bits one at a time.
-template <int RB, typename F2, typename F, bool FUSE = true>
 __device__ __forceinline__ void rotate_mask(F2 (&v)[1 << RB], uint32_t mask, const Rot<F> &k)
 {
-    if constexpr (!FUSE) {
 #pragma unroll
-        for (int b = 0; b < RB; ++b)
-            if ((mask >> b) & 1u) rotate_bit<RB>(v, b, k);
-        return;
-    }
-    constexpr int P0 = RB & 1;      // RB = 5: pairs (1,2), (3,4), single 0; RB = 4: (0,1), (2,3)
-    if (P0 && (mask & 1u)) rotate_bit<RB>(v, 0, k);
-#pragma unroll
-    for (int b = P0; b + 1 < RB; b += 2) {
-        const uint32_t two = (mask >> b) & 3u;
-        if (two == 3u)
-            rotate_pair<RB>(v, b, b + 1, k);
-        else if (two == 1u)
-            rotate_bit<RB>(v, b, k);
-        else if (two == 2u)
-            rotate_bit<RB>(v, b + 1, k);
-    }
+    for (int b = 0; b < RB; ++b)
+        if ((mask >> b) & 1u) rotate_bit<RB>(v, b, k);
 }
 
 template <typename F>
-__host__ __device__ inline Rot<F> make_rot(double cm1, double s, double s2, double cs)
+__host__ __device__ inline Rot<F> make_rot(double t, double s)
 {
     Rot<F> k;
-    k.cm1 = (F)cm1;
+    k.t = (F)t;
     k.s = (F)s;
-    k.s2 = (F)s2;
-    k.cs = (F)cs;
     return k;
 }
 
@@ -364,12 +321,13 @@ __device__ __forceinline__ void pass_load(TileRegs<F, ET, TB, RB> &tr, const typ
 }
 
 // Residencies of one tile, ending with the store to HBM.
-template <typename F, typename ET, int TB, int RB, bool PHASE, bool FUSE>
+template <typename F, typename ET, int TB, int RB, bool PHASE>
 __device__ __forceinline__ void pass_compute(TileRegs<F, ET, TB, RB> &tr, typename V2<F>::T *__restrict__ amp,
                                              const PassDesc &d, uint64_t base,
                                              uint64_t tg_last, uint32_t tid,
                                              typename V2<F>::T *tile, const typename V2<F>::T *lut, ET *etile,
-                                             const Rot<F> &kA, const Rot<F> &kB, unsigned long long &ssq)
+                                             const Rot<F> &kA, const Rot<F> &kB, bool meas,
+                                             unsigned long long &ssq)
 {
     using P = PassTraits<F, ET, TB, RB>;
     using F2 = typename P::F2;
@@ -399,7 +357,7 @@ __device__ __forceinline__ void pass_compute(TileRegs<F, ET, TB, RB> &tr, typena
     auto apply = [&](int r, uint32_t lt) {
         const uint32_t o_lj = (uint32_t)offsetof(PassDesc, lj) + 2u * kMaxRegs * (uint32_t)r;
         const uint32_t masks = desc_word(d, (uint32_t)offsetof(PassDesc, masks) + 4u * (uint32_t)r);
-        rotate_mask<RB, F2, F, FUSE>(v, masks & 0xFFu, kA);
+        rotate_mask<RB, F2, F>(v, masks & 0xFFu, kA);
         if (PHASE && r == d.phase_at) {
             // four amplitudes at a time keeps the table reads' registers few
 #pragma unroll
@@ -412,7 +370,7 @@ __device__ __forceinline__ void pass_compute(TileRegs<F, ET, TB, RB> &tr, typena
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
-        rotate_mask<RB, F2, F, FUSE>(v, (masks >> 8) & 0xFFu, kB);
+        rotate_mask<RB, F2, F>(v, (masks >> 8) & 0xFFu, kB);
     };
     auto to_lds = [&](int r, uint32_t ltp) {
         const uint32_t o_ljp = (uint32_t)offsetof(PassDesc, ljp) + 2u * kMaxRegs * (uint32_t)r;
@@ -468,11 +426,17 @@ __device__ __forceinline__ void pass_compute(TileRegs<F, ET, TB, RB> &tr, typena
         }
     }
     F2 *p = amp + (base | tg_last);
-    F st = F(0);       // this tile's share of |psi|^2: R terms in F, then FP64
+    if (meas) {
+        // this thread's share of |psi|^2 over the tile, as a fixed-point
+        // integer: the total does not depend on which workgroup handled
+        // which tile, nor on the order of the additions
+        F st = F(0);
+#pragma unroll
+        for (int j = 0; j < R; ++j) st = fma(v[j].x, v[j].x, fma(v[j].y, v[j].y, st));
+        ssq += (unsigned long long)((double)st * kNormFixedScale + 0.5);
+    }
 #pragma unroll
     for (int j = 0; j < R; j += VW) {
-#pragma unroll
-        for (int k = 0; k < VW; ++k) st = fma(v[j + k].x, v[j + k].x, fma(v[j + k].y, v[j + k].y, st));
         if constexpr (VW == 2) {
             float4 q;
             q.x = v[j].x;
@@ -484,16 +448,13 @@ __device__ __forceinline__ void pass_compute(TileRegs<F, ET, TB, RB> &tr, typena
             p[d.goff_last[j]] = v[j];
         }
     }
-    // fixed point per thread and tile: the total does not depend on which
-    // workgroup handled which tile, nor on the order of the additions
-    ssq += (unsigned long long)((double)st * kNormFixedScale + 0.5);
 }
 
 // Two workgroups per CU (LDS-bound) means two waves per SIMD: the register
 // budget is held to that occupancy.
-// FUSE: fused two-qubit rotations; PIPE: persistent grid with the next
-// tile's loads in flight (otherwise one workgroup per tile).
-template <typename F, typename ET, int TB, int RB, bool PHASE, bool FUSE, bool PIPE>
+// PIPE: persistent grid with the next tile's loads in flight (otherwise one
+// workgroup per tile).
+template <typename F, typename ET, int TB, int RB, bool PHASE, bool PIPE>
 __global__ void __launch_bounds__(1 << (TB - RB), 2)
 pass_kernel(typename V2<F>::T *__restrict__ amp, const ET *__restrict__ table, const PassDesc d)
 {
@@ -538,25 +499,26 @@ pass_kernel(typename V2<F>::T *__restrict__ amp, const ET *__restrict__ table, c
     }
     if (d.acc_zero && blockIdx.x == 0 && tid == 0) *d.acc_zero = 0ull;
 
-    const Rot<F> kA = make_rot<F>(d.cm1A, d.sA, d.s2A, d.csA);
-    const Rot<F> kB = make_rot<F>(d.cm1B, d.sB, d.s2B, d.csB);
+    const Rot<F> kA = make_rot<F>(d.tA, d.sA);
+    const Rot<F> kB = make_rot<F>(d.tB, d.sB);
+    const bool meas = d.acc_out != nullptr;
     unsigned long long ss = 0ull;
     if constexpr (!PIPE) {
-        pass_compute<F, ET, TB, RB, PHASE, FUSE>(ta, amp, d, tile_base<F, ET, TB, RB>(d, t0 + w), tg_last, tid, tile,
-                                                 lut, etile, kA, kB, ss);
+        pass_compute<F, ET, TB, RB, PHASE>(ta, amp, d, tile_base<F, ET, TB, RB>(d, t0 + w), tg_last, tid, tile,
+                                                 lut, etile, kA, kB, meas, ss);
     }
     while (PIPE) {
         const uint64_t w1 = w + G;
         pass_load<F, ET, TB, RB, PHASE>(tb, amp, table, d, tile_base<F, ET, TB, RB>(d, t0 + (w1 < ntiles ? w1 : w)),
                                         tg_first, tid);
-        pass_compute<F, ET, TB, RB, PHASE, FUSE>(ta, amp, d, tile_base<F, ET, TB, RB>(d, t0 + w), tg_last, tid, tile, lut,
-                                           etile, kA, kB, ss);
+        pass_compute<F, ET, TB, RB, PHASE>(ta, amp, d, tile_base<F, ET, TB, RB>(d, t0 + w), tg_last, tid, tile, lut,
+                                           etile, kA, kB, meas, ss);
         if (w1 >= ntiles) break;
         const uint64_t w2 = w1 + G;
         pass_load<F, ET, TB, RB, PHASE>(ta, amp, table, d, tile_base<F, ET, TB, RB>(d, t0 + (w2 < ntiles ? w2 : w1)),
                                         tg_first, tid);
-        pass_compute<F, ET, TB, RB, PHASE, FUSE>(tb, amp, d, tile_base<F, ET, TB, RB>(d, t0 + w1), tg_last, tid, tile, lut,
-                                           etile, kA, kB, ss);
+        pass_compute<F, ET, TB, RB, PHASE>(tb, amp, d, tile_base<F, ET, TB, RB>(d, t0 + w1), tg_last, tid, tile, lut,
+                                           etile, kA, kB, meas, ss);
         if (w2 >= ntiles) break;
         w = w2;
     }
@@ -568,8 +530,33 @@ pass_kernel(typename V2<F>::T *__restrict__ amp, const ET *__restrict__ table, c
 // Batched passes (see BatchInst).
 // ---------------------------------------------------------------------------
 struct DevCoef {
-    double s, theta, cm1, sn, s2, cs;
+    double s, theta, t, sn;
+    bool flip;
 };
+
+// Shear coefficients of the rotation by phi = theta/2 reduced to
+// [-pi/2, pi/2] (flip: reduced by pi, the block changes sign), and the
+// step's global phase n theta/2 (+ pi for odd n when flipped) mod 2 pi.
+__host__ __device__ inline void rot_params(double theta, double &t, double &sn, bool &flip)
+{
+    double phi = fmod(0.5 * theta, 2.0 * M_PI);
+    if (phi > M_PI) phi -= 2.0 * M_PI;
+    flip = false;
+    if (phi > 0.5 * M_PI) {
+        phi -= M_PI;
+        flip = true;
+    } else if (phi < -0.5 * M_PI) {
+        phi += M_PI;
+        flip = true;
+    }
+    t = tan(0.5 * phi);
+    sn = sin(phi);
+}
+
+__device__ __forceinline__ double step_gphase(int n, double theta, bool flip)
+{
+    return fmod(0.5 * (double)n * theta + (flip ? M_PI * (double)(n & 1) : 0.0), 2.0 * M_PI);
+}
 
 // Step k of N over total time T: schedule midpoint s_k = (k + 1/2)/N and the
 // rotation coefficients of theta_k = dt (1 - s_k) (same formulas as the host).
@@ -579,15 +566,11 @@ __device__ __forceinline__ DevCoef dev_step_coef(double T, int64_t N, int64_t k)
     const double dt = T / (double)N;
     c.s = ((double)k + 0.5) / (double)N;
     c.theta = dt * (1.0 - c.s);
-    const double q = sin(0.25 * c.theta);
-    c.cm1 = -2.0 * q * q;
-    c.sn = sin(0.5 * c.theta);
-    c.s2 = c.sn * c.sn;
-    c.cs = 0.5 * sin(c.theta);
+    rot_params(c.theta, c.t, c.sn, c.flip);
     return c;
 }
 
-template <typename F, typename ET, int TB, int RB, bool PHASE, bool FUSE>
+template <typename F, typename ET, int TB, int RB, bool PHASE>
 __device__ __forceinline__ void batch_tile(const BatchInst &I, const PassDesc &d, uint64_t w, int kind_top,
                                            const Rot<F> &kA, const Rot<F> &kB, double phi, double gphase,
                                            unsigned long long *acc_in, unsigned long long *acc_out)
@@ -622,12 +605,13 @@ __device__ __forceinline__ void batch_tile(const BatchInst &I, const PassDesc &d
         }
     }
     unsigned long long ss = 0ull;
-    pass_compute<F, ET, TB, RB, PHASE, FUSE>(ta, amp, d, base, tg_last, tid, tile, lut, etile, kA, kB, ss);
+    pass_compute<F, ET, TB, RB, PHASE>(ta, amp, d, base, tg_last, tid, tile, lut, etile, kA, kB, acc_out != nullptr,
+                                       ss);
     if (acc_out) norm_accumulate(acc_out, ss);
     (void)kind_top;
 }
 
-template <typename F, typename ET, int TB, int RB, bool FUSE>
+template <typename F, typename ET, int TB, int RB>
 __global__ void __launch_bounds__(1 << (TB - RB), 2)
 batch_pass_kernel(const BatchInst *__restrict__ insts, int count, const PassDesc *__restrict__ structs, int64_t s,
                   int j)
@@ -664,20 +648,19 @@ batch_pass_kernel(const BatchInst *__restrict__ insts, int count, const PassDesc
 
     const double dt = I.T / (double)I.N;
     const DevCoef ck = dev_step_coef(I.T, I.N, s);
-    Rot<F> kA = make_rot<F>(ck.cm1, ck.sn, ck.s2, ck.cs), kB = make_rot<F>(0.0, 0.0, 0.0, 0.0);
+    Rot<F> kA = make_rot<F>(ck.t, ck.sn), kB = make_rot<F>(0.0, 0.0);
     double phi = 0.0, gph = 0.0;
-    const double twopi = 2.0 * M_PI;
     if (kind == 0) {
         kB = kA;
         phi = 0.5 * dt * ck.s;
     } else if (kind == r - 1 || kind == r) {
         const DevCoef cn = dev_step_coef(I.T, I.N, s + 1);
-        kB = make_rot<F>(cn.cm1, cn.sn, cn.s2, cn.cs);
+        kB = make_rot<F>(cn.t, cn.sn);
         phi = 0.5 * dt * (ck.s + cn.s);
-        gph = fmod(0.5 * (double)I.n * ck.theta, twopi);
+        gph = step_gphase(I.n, ck.theta, ck.flip);
     } else if (kind >= r + 1) {
         phi = 0.5 * dt * ck.s;
-        gph = fmod(0.5 * (double)I.n * ck.theta, twopi);
+        gph = step_gphase(I.n, ck.theta, ck.flip);
     }
     // norm control rides on the passes over the top set (every other step)
     unsigned long long *acc_in = nullptr, *acc_out = nullptr;
@@ -688,9 +671,9 @@ batch_pass_kernel(const BatchInst *__restrict__ insts, int count, const PassDesc
         if (w == 0 && threadIdx.x == 0) I.acc[(gj + 1) % 3] = 0ull;
     }
     if (d.phase_at >= 0)
-        batch_tile<F, ET, TB, RB, true, FUSE>(I, d, w, kind, kA, kB, phi, gph, acc_in, acc_out);
+        batch_tile<F, ET, TB, RB, true>(I, d, w, kind, kA, kB, phi, gph, acc_in, acc_out);
     else
-        batch_tile<F, ET, TB, RB, false, FUSE>(I, d, w, kind, kA, kB, phi, gph, acc_in, acc_out);
+        batch_tile<F, ET, TB, RB, false>(I, d, w, kind, kA, kB, phi, gph, acc_in, acc_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -789,6 +772,7 @@ __device__ __forceinline__ void resident_body(const ResidentDesc &d)
     };
 
     double theta_prev = 0.0, s_prev = 0.0;
+    bool flip_prev = false;
     for (int64_t k = d.k0; k < d.k1; ++k) {
         const double sk = ((double)k + 0.5) / Nd;
         const double theta = dt * (1.0 - sk);
@@ -798,21 +782,21 @@ __device__ __forceinline__ void resident_body(const ResidentDesc &d)
             gph = 0.0;
         } else {
             phi = 0.5 * dt * (s_prev + sk);
-            gph = fmod(0.5 * (double)n * theta_prev, 2.0 * M_PI);
+            gph = step_gphase(n, theta_prev, flip_prev);
         }
         const double scale = k == d.k0 ? 1.0 : rsqrt(measure());
         build_lut(phi, gph, scale);
-        const double q = sin(0.25 * theta);
-        const double sh = sin(0.5 * theta);
-        const Rot<F> rk = make_rot<F>(-2.0 * q * q, sh, sh * sh, 0.5 * sin(theta));
+        double rt, rs;
+        rot_params(theta, rt, rs, flip_prev);
+        const Rot<F> rk = make_rot<F>(rt, rs);
         for (int g = 0; g < d.n_groups; ++g) residency(g, g == 0, d.gmask[g], rk, g == d.n_groups - 1);
         theta_prev = theta;
         s_prev = sk;
     }
     if (d.k1 > d.k0) {
         const double scale = rsqrt(measure());
-        build_lut(0.5 * dt * s_prev, fmod(0.5 * (double)n * theta_prev, 2.0 * M_PI), scale);
-        residency(0, true, 0u, make_rot<F>(0.0, 0.0, 0.0, 0.0), false);
+        build_lut(0.5 * dt * s_prev, step_gphase(n, theta_prev, flip_prev), scale);
+        residency(0, true, 0u, make_rot<F>(0.0, 0.0), false);
     }
     for (uint32_t z = tid; z < dim; z += blockDim.x) amp[z] = tile[swz<F>(z)];
 }
@@ -901,14 +885,14 @@ inline unsigned grid_for(uint64_t work, unsigned per_block, unsigned cap)
     return (unsigned)g;
 }
 
-template <typename F, typename ET, int TB, int RB, bool PHASE, bool FUSE, bool PIPE>
+template <typename F, typename ET, int TB, int RB, bool PHASE, bool PIPE>
 hipError_t launch_pass_p(void *amp, const void *table, const PassDesc &d, hipStream_t s)
 {
     using F2 = typename V2<F>::T;
     constexpr int DT = sizeof(F) == 4 ? 0 : 1;
     constexpr size_t TS = size_t(1) << TB;
     const size_t lds = sizeof(F2) * (TS + kPadN[DT] * (TS >> kPadS[DT]) + lut_cap<ET>()) + sizeof(ET) * TS;
-    const void *fn = reinterpret_cast<const void *>(&pass_kernel<F, ET, TB, RB, PHASE, FUSE, PIPE>);
+    const void *fn = reinterpret_cast<const void *>(&pass_kernel<F, ET, TB, RB, PHASE, PIPE>);
     // persistent grid: as many workgroups as fit on the device at once
     // (set up once per instantiation; static initialisation is thread-safe)
     struct Setup {
@@ -925,18 +909,18 @@ hipError_t launch_pass_p(void *amp, const void *table, const PassDesc &d, hipStr
     }();
     if (setup.err != hipSuccess) return setup.err;
     const unsigned grid = PIPE ? (unsigned)std::min<uint64_t>(d.tile_count, setup.resident) : (unsigned)d.tile_count;
-    hipLaunchKernelGGL((pass_kernel<F, ET, TB, RB, PHASE, FUSE, PIPE>), dim3(grid), dim3(1u << (TB - RB)), lds, s,
+    hipLaunchKernelGGL((pass_kernel<F, ET, TB, RB, PHASE, PIPE>), dim3(grid), dim3(1u << (TB - RB)), lds, s,
                        reinterpret_cast<F2 *>(amp), reinterpret_cast<const ET *>(table), d);
     return hipGetLastError();
 }
 
-// Kernel variant (tuning switch, QAA_PASS_VARIANT): bit 0 fused two-qubit
-// rotations, bit 1 persistent pipelined grid.  Default 2.
+// Kernel variant (tuning switch, QAA_PASS_VARIANT): 2 (default) persistent
+// grid with the next tile's loads in flight, 0 one workgroup per tile.
 inline int pass_variant()
 {
     static const int v = [] {
         const char *e = std::getenv("QAA_PASS_VARIANT");
-        return e ? (std::atoi(e) & 3) : 2;
+        return e ? (std::atoi(e) & 2) : 2;
     }();
     return v;
 }
@@ -944,15 +928,8 @@ inline int pass_variant()
 template <typename F, typename ET, int TB, int RB, bool PHASE>
 hipError_t launch_pass_v(void *amp, const void *table, const PassDesc &d, hipStream_t s)
 {
-    if constexpr (sizeof(F) == 4 && sizeof(ET) == 1) {
-        switch (pass_variant()) {
-        case 0: return launch_pass_p<F, ET, TB, RB, PHASE, false, false>(amp, table, d, s);
-        case 1: return launch_pass_p<F, ET, TB, RB, PHASE, true, false>(amp, table, d, s);
-        case 3: return launch_pass_p<F, ET, TB, RB, PHASE, true, true>(amp, table, d, s);
-        default: break;
-        }
-    }
-    return launch_pass_p<F, ET, TB, RB, PHASE, false, true>(amp, table, d, s);
+    if (pass_variant() == 0) return launch_pass_p<F, ET, TB, RB, PHASE, false>(amp, table, d, s);
+    return launch_pass_p<F, ET, TB, RB, PHASE, true>(amp, table, d, s);
 }
 
 template <typename F, typename ET, int TB, int RB>
@@ -1010,10 +987,10 @@ hipError_t launch_batch_t(const BatchInst *insts, int count, const PassDesc *str
     constexpr int DT = sizeof(F) == 4 ? 0 : 1;
     constexpr size_t TS = size_t(1) << TB;
     const size_t lds = sizeof(F2) * (TS + kPadN[DT] * (TS >> kPadS[DT]) + lut_cap<ET>()) + sizeof(ET) * TS;
-    const void *fn = reinterpret_cast<const void *>(&batch_pass_kernel<F, ET, TB, RB, false>);
+    const void *fn = reinterpret_cast<const void *>(&batch_pass_kernel<F, ET, TB, RB>);
     static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((batch_pass_kernel<F, ET, TB, RB, false>), dim3((unsigned)grid_tiles), dim3(1u << (TB - RB)),
+    hipLaunchKernelGGL((batch_pass_kernel<F, ET, TB, RB>), dim3((unsigned)grid_tiles), dim3(1u << (TB - RB)),
                        lds, st, insts, count, structs, s, j);
     return hipGetLastError();
 }

@@ -424,8 +424,15 @@ bool io_capable(const Group &g, int vw)
     return true;
 }
 
+// Step k: schedule midpoint s, driver angle theta, and the shear
+// coefficients of the per-qubit rotation by phi = theta/2.  phi is reduced to
+// [-pi/2, pi/2] first (a 2 pi shift changes nothing; M(phi) = -M(phi - pi)
+// for the 2x2 block M), so |t| = |tan(phi/2)| <= 1 and the shears stay well
+// conditioned; a reduction by pi flips the sign of every qubit's block,
+// which the step's global phase absorbs (flip).
 struct StepCoef {
-    double s, theta, cm1, sn, s2, cs;
+    double s, theta, t, sn;
+    bool flip;
 };
 
 StepCoef step_coef(double T, int64_t N, int64_t k)
@@ -434,12 +441,28 @@ StepCoef step_coef(double T, int64_t N, int64_t k)
     const double dt = T / (double)N;
     c.s = ((double)k + 0.5) / (double)N;
     c.theta = dt * (1.0 - c.s);
-    const double q = std::sin(0.25 * c.theta);
-    c.cm1 = -2.0 * q * q;
-    c.sn = std::sin(0.5 * c.theta);
-    c.s2 = c.sn * c.sn;
-    c.cs = 0.5 * std::sin(c.theta);
+    double phi = std::fmod(0.5 * c.theta, 2.0 * M_PI);
+    if (phi > M_PI) phi -= 2.0 * M_PI;
+    c.flip = false;
+    if (phi > 0.5 * M_PI) {
+        phi -= M_PI;
+        c.flip = true;
+    } else if (phi < -0.5 * M_PI) {
+        phi += M_PI;
+        c.flip = true;
+    }
+    c.t = std::tan(0.5 * phi);
+    c.sn = std::sin(phi);
     return c;
+}
+
+double wrap_phase(double a);
+
+// Global phase of step k's driver factor on n qubits: exp(-i n theta / 2),
+// times (-1)^n when the rotation angle was reduced by pi.
+double step_gphase(int n, const StepCoef &c)
+{
+    return wrap_phase(0.5 * n * c.theta + (c.flip ? M_PI * (n & 1) : 0.0));
 }
 
 double wrap_phase(double a)
@@ -590,37 +613,27 @@ std::vector<PassDesc> build_passes(const Plan &p, int n, int dty, int emax, doub
                 // k == k0: half phase of step k0, then this set's rotations
                 d.phi = 0.5 * dt * ck.s;
                 d.gphase = 0.0;
-                d.cm1B = ck.cm1;
+                d.tB = ck.t;
                 d.sB = ck.sn;
-                d.s2B = ck.s2;
-                d.csB = ck.cs;
                 fill_residencies(d, sp, TB, RB, dty, false, true, true);
             } else if (last && k + 1 < k1) {
                 const StepCoef cn = step_coef(T, N, k + 1);
-                d.cm1A = ck.cm1;
+                d.tA = ck.t;
                 d.sA = ck.sn;
-                d.s2A = ck.s2;
-                d.csA = ck.cs;
                 d.phi = 0.5 * dt * (ck.s + cn.s);
-                d.gphase = wrap_phase(0.5 * n * ck.theta);
-                d.cm1B = cn.cm1;
+                d.gphase = step_gphase(n, ck);
+                d.tB = cn.t;
                 d.sB = cn.sn;
-                d.s2B = cn.s2;
-                d.csB = cn.cs;
                 fill_residencies(d, sp, TB, RB, dty, true, true, true);
             } else if (last) {
-                d.cm1A = ck.cm1;
+                d.tA = ck.t;
                 d.sA = ck.sn;
-                d.s2A = ck.s2;
-                d.csA = ck.cs;
                 d.phi = 0.5 * dt * ck.s;
-                d.gphase = wrap_phase(0.5 * n * ck.theta);
+                d.gphase = step_gphase(n, ck);
                 fill_residencies(d, sp, TB, RB, dty, true, true, false);
             } else {
-                d.cm1A = ck.cm1;
+                d.tA = ck.t;
                 d.sA = ck.sn;
-                d.s2A = ck.s2;
-                d.csA = ck.cs;
                 fill_residencies(d, sp, TB, RB, dty, true, false, false);
             }
             out.push_back(d);

@@ -71,8 +71,7 @@ struct PassDesc {
     int32_t phase_at;          // -1: no phase in this pass
     int32_t emax;              // largest E value the LUT must cover
     int32_t set_id;            // qubit set of this pass (host bookkeeping)
-    double cm1A, sA, cm1B, sB;
-    double s2A, csA, s2B, csB;     // sin^2(theta/2) and sin(theta/2) cos(theta/2) of sets A / B
+    double tA, sA, tB, sB;     // tan(theta/4), sin(theta/2) of the rotations before (A) / after (B) the phase
     double phi, gphase;
     uint64_t tile_begin;       // this launch handles tiles [tile_begin, tile_begin + tile_count)
     uint64_t tile_count;

@@ -83,37 +83,42 @@ def _replay(n, dtype, E, psi, T, N, k0, k1):
         assert np.unique(g).size == g.size
         tiles = psi[g]
         etile = E[g]
-        for cm1, sn, s2, cs, m in ((d.cm1A, d.sA, d.s2A, d.csA, d.masks[0] & 0xFF), (d.cm1B, d.sB, d.s2B, d.csB, 1)):
-            if cm1 or sn:
-                c = 1.0 + cm1
-                assert abs(c * c + sn * sn - 1.0) < 1e-15 and abs(s2 - sn * sn) < 1e-18 and abs(cs - c * sn) < 1e-15
+        for t, sn in ((d.tA, d.sA), (d.tB, d.sB)):
+            if t or sn:
+                # three shears by (t, s, t) compose to the rotation with
+                # cos = 1 - t s: t = tan(theta/4) and s = sin(theta/2)
+                c = 1.0 - t * sn
+                assert abs(c * c + sn * sn - 1.0) < 1e-15
+                assert abs(2.0 * t / (1.0 + t * t) - sn) < 1e-15
         lut = np.exp(-1j * (d.phi * np.arange(int(E.max()) + 1) + d.gphase))
         for r in range(d.n_res):
             l = lts[r][:, None] | ljs[r][None, :]
             v = tiles[:, l]                                             # [B, WG, R]
 
-            def rot(v, mask, cm1, s):
+            def rot(v, mask, t, s):
                 for b in range(RB):
                     if (mask >> b) & 1:
                         lo = [j for j in range(R) if not (j >> b) & 1]
                         hi = [j | (1 << b) for j in lo]
                         x0, x1 = v[..., lo].copy(), v[..., hi].copy()
-                        c = 1.0 + cm1
+                        c = 1.0 - t * s
                         v[..., lo] = c * x0 + 1j * s * x1
                         v[..., hi] = c * x1 + 1j * s * x0
                 return v
 
-            v = rot(v, d.masks[r] & 0xFF, d.cm1A, d.sA)
+            v = rot(v, d.masks[r] & 0xFF, d.tA, d.sA)
             if r == d.phase_at:
                 v = v * lut[etile[:, l]]
-            v = rot(v, (d.masks[r] >> 8) & 0xFF, d.cm1B, d.sB)
+            v = rot(v, (d.masks[r] >> 8) & 0xFF, d.tB, d.sB)
             tiles[:, l] = v
         psi[g] = tiles
     return psi, descs
 
 
 @pytest.mark.parametrize("n,dtype,T,N", [(14, 0, 5.0, 4), (16, 0, 6.0, 3), (21, 0, 5.0, 2), (22, 0, 5.0, 2),
-                                         (13, 1, 5.0, 4), (17, 1, 5.0, 3)])
+                                         (13, 1, 5.0, 4), (17, 1, 5.0, 3),
+                                         # large steps: rotation angles reduced by pi (odd and even n)
+                                         (15, 0, 50.0, 5), (14, 0, 40.0, 3)])
 def test_pass_plan_replays_the_oracle(n, dtype, T, N):
     inst = planted_unique_3sat(n, 500 + n)
     E = oracle.energy(n, inst.clauses).astype(np.int64)
