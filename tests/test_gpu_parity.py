@@ -342,6 +342,54 @@ def test_full_size_c64_vs_c128_first_steps(qaa):
     assert abs(oa["norm"] - 1.0) < 1e-5
 
 
+@pytest.mark.parametrize("n", [29, 30, 31])
+def test_large_n_driver_only_closed_form(qaa, n):
+    """n = 29 (3 sets), 30 and 31 (4 sets, 3 passes per step; 8 and 16 GiB
+    states): the m = 0 closed form from a basis state, sampled."""
+    T, N, z0 = 20.0, 5, (0x2B6D5A93 & ((1 << n) - 1))
+    assert qaa.qaa_plan_info(n)["sets"] == (3 if n == 29 else 4)
+    inst = qaa.Instance(n, [])
+    table = inst.energy_table()
+    st = qaa.State(inst, table).init_basis(z0).evolve(T, N)
+    obs = st.observables()
+    th = T / 2.0
+    a = (1 + np.exp(-1j * th)) / 2
+    b = (1 - np.exp(-1j * th)) / 2
+    rng = SplitMix64(n)
+    zs = np.asarray([rng.below(1 << n) for _ in range(4096)] + [z0, z0 ^ 1, z0 ^ (1 << (n - 1))], dtype=np.int64)
+    got = st.amp[torch.from_numpy(zs).cuda()].cpu().numpy().astype(np.complex128)
+    d = np.array([bin(int(z) ^ z0).count("1") for z in zs])
+    expect = a ** (n - d) * b ** d
+    assert np.max(np.abs(got - expect)) < 2e-6
+    assert abs(obs["norm"] - 1.0) < 1e-6
+    del st, table
+    torch.cuda.empty_cache()
+
+
+def test_n30_c64_vs_c128_first_steps(qaa):
+    """A planted instance at n = 30 (4 qubit sets): complex64 against the
+    complex128 GPU path over the first steps of a T = 50, 5000-step run."""
+    n, T, N, K = 30, 50.0, 5000, 3
+    inst_in = planted_unique_3sat(n, 0)
+    inst = qaa.Instance(n, inst_in.literals())
+    table = inst.energy_table()
+    info = inst.info()
+    assert info["e_min"] == 0 and info["degeneracy"] == 1
+    a = qaa.State(inst, table, dtype=torch.complex64).init_uniform()
+    a.evolve_range(T, N, 0, K)
+    oa = a.observables()
+    b = qaa.State(inst, table, dtype=torch.complex128).init_uniform()
+    b.evolve_range(T, N, 0, K)
+    ob = b.observables()
+    diff = float(torch.linalg.vector_norm(a.amp.to(torch.complex128) - b.amp).item())
+    assert diff < 1e-5
+    assert abs(oa["p_success"] - ob["p_success"]) < 1e-10
+    assert abs(oa["energy"] - ob["energy"]) < 1e-5 * ob["energy"]
+    assert abs(ob["norm"] - 1.0) < 1e-12
+    del a, b, table
+    torch.cuda.empty_cache()
+
+
 # --------------------------------------------------------------------------
 # n = 20, T = 100, 10^4 steps against stored oracle results
 # --------------------------------------------------------------------------
