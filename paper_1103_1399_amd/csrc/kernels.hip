@@ -450,13 +450,18 @@ __device__ __forceinline__ void pass_compute(TileRegs<F, ET, TB, RB> &tr, typena
     }
 }
 
-// Two workgroups per CU (LDS-bound) means two waves per SIMD: the register
-// budget is held to that occupancy.
-// PIPE: persistent grid with the next tile's loads in flight (otherwise one
-// workgroup per tile).
+// The tiles first, first + stride, ... (< end) of one pass, pipelined: the
+// HBM loads of the next tile are in flight while the current one is
+// computed (PIPE), else only tile `first`.  The phase table (a pass with a
+// phase) is built in LDS from phi, gphase and the norm correction *acc_in.
+// Returns this thread's fixed-point share of sum |psi|^2 when meas is set.
 template <typename F, typename ET, int TB, int RB, bool PHASE, bool PIPE>
-__global__ void __launch_bounds__(1 << (TB - RB), 2)
-pass_kernel(typename V2<F>::T *__restrict__ amp, const ET *__restrict__ table, const PassDesc d)
+__device__ __forceinline__ unsigned long long tile_loop(typename V2<F>::T *__restrict__ amp,
+                                                        const ET *__restrict__ table, const PassDesc &d,
+                                                        uint64_t first, uint64_t stride, uint64_t end, double phi,
+                                                        double gphase, int emax,
+                                                        const unsigned long long *acc_in, const Rot<F> &kA,
+                                                        const Rot<F> &kB, bool meas)
 {
     using P = PassTraits<F, ET, TB, RB>;
     using F2 = typename P::F2;
@@ -467,10 +472,6 @@ pass_kernel(typename V2<F>::T *__restrict__ amp, const ET *__restrict__ table, c
     ET *etile = reinterpret_cast<ET *>(lut + lut_cap<ET>());
 
     const uint32_t tid = threadIdx.x;
-    const uint64_t ntiles = d.tile_count;
-    const uint64_t t0 = d.tile_begin;
-    const uint64_t G = gridDim.x;
-
     uint64_t tg_first = 0, tg_last = 0;
 #pragma unroll
     for (int k = 0; k < P::WB; ++k) {
@@ -483,46 +484,57 @@ pass_kernel(typename V2<F>::T *__restrict__ amp, const ET *__restrict__ table, c
     // memory operations in flight is the same on every path; otherwise the
     // compiler's wait counts assume the worst path and stall on the prefetch.
     TileRegs<F, ET, TB, RB> ta, tb;
-    uint64_t w = blockIdx.x;        // grid size <= ntiles, so w is a valid tile
-    pass_load<F, ET, TB, RB, PHASE>(ta, amp, table, d, tile_base<F, ET, TB, RB>(d, t0 + w), tg_first, tid);
+    uint64_t w = first;             // callers pass first < end
+    pass_load<F, ET, TB, RB, PHASE>(ta, amp, table, d, tile_base<F, ET, TB, RB>(d, w), tg_first, tid);
 
     if constexpr (PHASE) {
-        const double scale = d.acc_in ? rsqrt((double)(*d.acc_in) * (1.0 / kNormFixedScale)) : 1.0;
-        for (int e = (int)tid; e <= d.emax; e += (int)P::WG) {
+        const double scale = acc_in ? rsqrt((double)(*acc_in) * (1.0 / kNormFixedScale)) : 1.0;
+        for (int e = (int)tid; e <= emax; e += (int)P::WG) {
             double sn, cs;
-            sincos(fma(d.phi, (double)e, d.gphase), &sn, &cs);
+            sincos(fma(phi, (double)e, gphase), &sn, &cs);
             F2 L;
             L.x = (F)(scale * cs);
             L.y = (F)(-scale * sn);
             lut[e] = L;
         }
     }
-    if (d.acc_zero && blockIdx.x == 0 && tid == 0) *d.acc_zero = 0ull;
 
-    const Rot<F> kA = make_rot<F>(d.tA, d.sA);
-    const Rot<F> kB = make_rot<F>(d.tB, d.sB);
-    const bool meas = d.acc_out != nullptr;
     unsigned long long ss = 0ull;
     if constexpr (!PIPE) {
-        pass_compute<F, ET, TB, RB, PHASE>(ta, amp, d, tile_base<F, ET, TB, RB>(d, t0 + w), tg_last, tid, tile,
-                                                 lut, etile, kA, kB, meas, ss);
+        pass_compute<F, ET, TB, RB, PHASE>(ta, amp, d, tile_base<F, ET, TB, RB>(d, w), tg_last, tid, tile, lut, etile,
+                                           kA, kB, meas, ss);
     }
     while (PIPE) {
-        const uint64_t w1 = w + G;
-        pass_load<F, ET, TB, RB, PHASE>(tb, amp, table, d, tile_base<F, ET, TB, RB>(d, t0 + (w1 < ntiles ? w1 : w)),
-                                        tg_first, tid);
-        pass_compute<F, ET, TB, RB, PHASE>(ta, amp, d, tile_base<F, ET, TB, RB>(d, t0 + w), tg_last, tid, tile, lut,
+        const uint64_t w1 = w + stride;
+        pass_load<F, ET, TB, RB, PHASE>(tb, amp, table, d, tile_base<F, ET, TB, RB>(d, w1 < end ? w1 : w), tg_first,
+                                        tid);
+        pass_compute<F, ET, TB, RB, PHASE>(ta, amp, d, tile_base<F, ET, TB, RB>(d, w), tg_last, tid, tile, lut, etile,
+                                           kA, kB, meas, ss);
+        if (w1 >= end) break;
+        const uint64_t w2 = w1 + stride;
+        pass_load<F, ET, TB, RB, PHASE>(ta, amp, table, d, tile_base<F, ET, TB, RB>(d, w2 < end ? w2 : w1), tg_first,
+                                        tid);
+        pass_compute<F, ET, TB, RB, PHASE>(tb, amp, d, tile_base<F, ET, TB, RB>(d, w1), tg_last, tid, tile, lut,
                                            etile, kA, kB, meas, ss);
-        if (w1 >= ntiles) break;
-        const uint64_t w2 = w1 + G;
-        pass_load<F, ET, TB, RB, PHASE>(ta, amp, table, d, tile_base<F, ET, TB, RB>(d, t0 + (w2 < ntiles ? w2 : w1)),
-                                        tg_first, tid);
-        pass_compute<F, ET, TB, RB, PHASE>(tb, amp, d, tile_base<F, ET, TB, RB>(d, t0 + w1), tg_last, tid, tile, lut,
-                                           etile, kA, kB, meas, ss);
-        if (w2 >= ntiles) break;
+        if (w2 >= end) break;
         w = w2;
     }
+    return ss;
+}
 
+// Two workgroups per CU (LDS-bound) means two waves per SIMD: the register
+// budget is held to that occupancy.
+// PIPE: persistent grid (workgroup b takes tiles b, b + grid, ...) with the
+// next tile's loads in flight; otherwise one workgroup per tile.
+template <typename F, typename ET, int TB, int RB, bool PHASE, bool PIPE>
+__global__ void __launch_bounds__(1 << (TB - RB), 2)
+pass_kernel(typename V2<F>::T *__restrict__ amp, const ET *__restrict__ table, const PassDesc d)
+{
+    if (d.acc_zero && blockIdx.x == 0 && threadIdx.x == 0) *d.acc_zero = 0ull;
+    const uint64_t first = d.tile_begin + blockIdx.x;     // grid size <= tile_count
+    const unsigned long long ss = tile_loop<F, ET, TB, RB, PHASE, PIPE>(
+        amp, table, d, first, gridDim.x, d.tile_begin + d.tile_count, d.phi, d.gphase, d.emax, d.acc_in,
+        make_rot<F>(d.tA, d.sA), make_rot<F>(d.tB, d.sB), d.acc_out != nullptr);
     if (d.acc_out) norm_accumulate(d.acc_out, ss);
 }
 
@@ -570,63 +582,17 @@ __device__ __forceinline__ DevCoef dev_step_coef(double T, int64_t N, int64_t k)
     return c;
 }
 
-template <typename F, typename ET, int TB, int RB, bool PHASE>
-__device__ __forceinline__ void batch_tile(const BatchInst &I, const PassDesc &d, uint64_t w, int kind_top,
-                                           const Rot<F> &kA, const Rot<F> &kB, double phi, double gphase,
-                                           unsigned long long *acc_in, unsigned long long *acc_out)
-{
-    using P = PassTraits<F, ET, TB, RB>;
-    using F2 = typename P::F2;
-    extern __shared__ __align__(16) unsigned char smem[];
-    F2 *tile = reinterpret_cast<F2 *>(smem);
-    F2 *lut = tile + P::TSP;
-    ET *etile = reinterpret_cast<ET *>(lut + lut_cap<ET>());
-    F2 *amp = reinterpret_cast<F2 *>(I.amp);
-    const ET *table = reinterpret_cast<const ET *>(I.table);
-    const uint32_t tid = threadIdx.x;
-    uint64_t tg_first = 0, tg_last = 0;
-#pragma unroll
-    for (int k = 0; k < P::WB; ++k) {
-        tg_first |= (uint64_t)((tid >> k) & 1u) << d.gpos_first[k];
-        tg_last |= (uint64_t)((tid >> k) & 1u) << d.gpos_last[k];
-    }
-    const uint64_t base = tile_base<F, ET, TB, RB>(d, w);
-    TileRegs<F, ET, TB, RB> ta;
-    pass_load<F, ET, TB, RB, PHASE>(ta, amp, table, d, base, tg_first, tid);
-    if constexpr (PHASE) {
-        const double scale = acc_in ? rsqrt((double)(*acc_in) * (1.0 / kNormFixedScale)) : 1.0;
-        for (int e = (int)tid; e <= I.emax; e += (int)P::WG) {
-            double sn, cs;
-            sincos(fma(phi, (double)e, gphase), &sn, &cs);
-            F2 L;
-            L.x = (F)(scale * cs);
-            L.y = (F)(-scale * sn);
-            lut[e] = L;
-        }
-    }
-    unsigned long long ss = 0ull;
-    pass_compute<F, ET, TB, RB, PHASE>(ta, amp, d, base, tg_last, tid, tile, lut, etile, kA, kB, acc_out != nullptr,
-                                       ss);
-    if (acc_out) norm_accumulate(acc_out, ss);
-    (void)kind_top;
-}
-
+// Workgroup b takes a chunk of up to chunk_tiles consecutive tiles of state
+// chunk_inst[b] (pipelined like pass_kernel); the pass kind, the rotation
+// and phase coefficients follow from the global step s, the pass index j
+// and the state's own schedule.
 template <typename F, typename ET, int TB, int RB>
 __global__ void __launch_bounds__(1 << (TB - RB), 2)
-batch_pass_kernel(const BatchInst *__restrict__ insts, int count, const PassDesc *__restrict__ structs, int64_t s,
-                  int j)
+batch_pass_kernel(const BatchInst *__restrict__ insts, const uint32_t *__restrict__ chunk_inst,
+                  const PassDesc *__restrict__ structs, int64_t s, int j, int chunk_tiles)
 {
-    // state of this workgroup: the last one whose first tile is <= blockIdx.x
     const uint64_t g = blockIdx.x;
-    int lo = 0, hi = count - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (insts[mid].tile_offset <= g)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    const BatchInst &I = insts[lo];
+    const BatchInst &I = insts[chunk_inst[g]];
     if (s >= I.N) return;
     const int r = I.r;
     const int idx = s == 0 ? j : j + 1;       // position in this step's set order
@@ -644,7 +610,9 @@ batch_pass_kernel(const BatchInst *__restrict__ insts, int count, const PassDesc
     else
         kind = set == r - 1 ? r + 1 : r + 2;
     const PassDesc &d = structs[I.struct_base + kind];
-    const uint64_t w = g - I.tile_offset;
+    const uint64_t ntiles = 1ull << (I.n - TB);
+    const uint64_t w0 = (g - I.chunk_offset) * (uint64_t)chunk_tiles;
+    const uint64_t w1 = w0 + (uint64_t)chunk_tiles < ntiles ? w0 + (uint64_t)chunk_tiles : ntiles;
 
     const double dt = I.T / (double)I.N;
     const DevCoef ck = dev_step_coef(I.T, I.N, s);
@@ -668,12 +636,18 @@ batch_pass_kernel(const BatchInst *__restrict__ insts, int count, const PassDesc
         const int64_t gj = s >> 1;
         acc_out = I.acc + gj % 3;
         acc_in = gj > 0 ? I.acc + (gj + 2) % 3 : nullptr;
-        if (w == 0 && threadIdx.x == 0) I.acc[(gj + 1) % 3] = 0ull;
+        if (w0 == 0 && threadIdx.x == 0) I.acc[(gj + 1) % 3] = 0ull;
     }
+    auto *amp = reinterpret_cast<typename V2<F>::T *>(I.amp);
+    const ET *table = reinterpret_cast<const ET *>(I.table);
+    unsigned long long ss;
     if (d.phase_at >= 0)
-        batch_tile<F, ET, TB, RB, true>(I, d, w, kind, kA, kB, phi, gph, acc_in, acc_out);
+        ss = tile_loop<F, ET, TB, RB, true, true>(amp, table, d, w0, 1, w1, phi, gph, I.emax, acc_in, kA, kB,
+                                                  acc_out != nullptr);
     else
-        batch_tile<F, ET, TB, RB, false>(I, d, w, kind, kA, kB, phi, gph, acc_in, acc_out);
+        ss = tile_loop<F, ET, TB, RB, false, true>(amp, table, d, w0, 1, w1, phi, gph, I.emax, acc_in, kA, kB,
+                                                   acc_out != nullptr);
+    if (acc_out) norm_accumulate(acc_out, ss);
 }
 
 // ---------------------------------------------------------------------------
@@ -980,8 +954,8 @@ hipError_t launch_pass(void *amp, int dtype, const void *table, int etype, int t
 }
 
 template <typename F, typename ET, int TB, int RB>
-hipError_t launch_batch_t(const BatchInst *insts, int count, const PassDesc *structs, int64_t s, int j,
-                          uint64_t grid_tiles, hipStream_t st)
+hipError_t launch_batch_t(const BatchInst *insts, const uint32_t *chunk_inst, uint64_t chunks, const PassDesc *structs,
+                          int64_t s, int j, int chunk_tiles, hipStream_t st)
 {
     using F2 = typename V2<F>::T;
     constexpr int DT = sizeof(F) == 4 ? 0 : 1;
@@ -990,22 +964,25 @@ hipError_t launch_batch_t(const BatchInst *insts, int count, const PassDesc *str
     const void *fn = reinterpret_cast<const void *>(&batch_pass_kernel<F, ET, TB, RB>);
     static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((batch_pass_kernel<F, ET, TB, RB>), dim3((unsigned)grid_tiles), dim3(1u << (TB - RB)),
-                       lds, st, insts, count, structs, s, j);
+    hipLaunchKernelGGL((batch_pass_kernel<F, ET, TB, RB>), dim3((unsigned)chunks), dim3(1u << (TB - RB)), lds, st,
+                       insts, chunk_inst, structs, s, j, chunk_tiles);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_pass(const BatchInst *insts, int count, const PassDesc *structs, int64_t s, int j,
-                             uint64_t grid_tiles, int dtype, int etype, int tile_bits, int reg_bits, hipStream_t st)
+hipError_t launch_batch_pass(const BatchInst *insts, const uint32_t *chunk_inst, uint64_t chunks,
+                             const PassDesc *structs, int64_t s, int j, int chunk_tiles, int dtype, int etype,
+                             int tile_bits, int reg_bits, hipStream_t st)
 {
-    if (grid_tiles == 0) return hipSuccess;
+    if (chunks == 0) return hipSuccess;
     if (dtype == 0 && tile_bits == 13 && reg_bits == 5) {
-        if (etype == 0) return launch_batch_t<float, uint8_t, 13, 5>(insts, count, structs, s, j, grid_tiles, st);
-        return launch_batch_t<float, uint16_t, 13, 5>(insts, count, structs, s, j, grid_tiles, st);
+        if (etype == 0)
+            return launch_batch_t<float, uint8_t, 13, 5>(insts, chunk_inst, chunks, structs, s, j, chunk_tiles, st);
+        return launch_batch_t<float, uint16_t, 13, 5>(insts, chunk_inst, chunks, structs, s, j, chunk_tiles, st);
     }
     if (dtype == 1 && tile_bits == 12 && reg_bits == 4) {
-        if (etype == 0) return launch_batch_t<double, uint8_t, 12, 4>(insts, count, structs, s, j, grid_tiles, st);
-        return launch_batch_t<double, uint16_t, 12, 4>(insts, count, structs, s, j, grid_tiles, st);
+        if (etype == 0)
+            return launch_batch_t<double, uint8_t, 12, 4>(insts, chunk_inst, chunks, structs, s, j, chunk_tiles, st);
+        return launch_batch_t<double, uint16_t, 12, 4>(insts, chunk_inst, chunks, structs, s, j, chunk_tiles, st);
     }
     return hipErrorInvalidValue;
 }

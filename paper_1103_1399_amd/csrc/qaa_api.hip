@@ -913,45 +913,70 @@ qaa_status upload(const std::vector<T> &host, T **dev, hipStream_t s)
     return QAA_OK;
 }
 
-// Lock-step batched passes for states of one dtype/etype above the resident size.
+// Lock-step batched passes for states of one dtype/etype above the resident
+// size.  States are grouped by their number of qubit sets r (a group runs
+// r - 1 passes per step, r in the first); inside a group they are sorted by
+// step count, longest first, so the states still running at step k are a
+// prefix, and each state's tiles are cut into chunks of kBatchChunkTiles
+// (one workgroup each).
+constexpr int kBatchChunkTiles = 8;
+
 qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states, const double *T,
                             const int64_t *steps, hipStream_t s)
 {
     if (idx.empty()) return QAA_OK;
     const int dty = (int)states[idx[0]].dtype, ety = (int)states[idx[0]].etype;
-    std::vector<int> order(idx);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return steps[a] > steps[b]; });
+    struct GroupPlan {
+        int r = 0;
+        std::vector<int> order;              // state indices, longest first
+        size_t inst_base = 0, chunk_base = 0;
+        std::vector<uint64_t> chunk_prefix;  // chunks of the first q states
+    };
+    std::map<int, GroupPlan> groups;
+    for (int i : idx) {
+        const Plan p = make_plan(states[i].inst->n, dty);
+        GroupPlan &g = groups[(int)p.sets.size()];
+        g.r = (int)p.sets.size();
+        g.order.push_back(i);
+    }
     std::vector<PassDesc> structs;
     std::map<int, int> base_of_n;
     std::vector<BatchInst> insts;
-    uint64_t tiles = 0;
-    int rmax = 0, TB = 0, RB = 0;
-    std::vector<uint64_t> prefix;       // tiles of the first q states
-    prefix.push_back(0);
-    for (int i : order) {
-        const int n = states[i].inst->n;
-        const Plan p = make_plan(n, dty);
-        if (!base_of_n.count(n)) {
-            base_of_n[n] = (int)structs.size();
-            batch_structs(p, n, dty, structs);
+    std::vector<uint32_t> chunk_inst;
+    int TB = 0, RB = 0;
+    int64_t maxN = 0;
+    for (auto &kv : groups) {
+        GroupPlan &g = kv.second;
+        std::stable_sort(g.order.begin(), g.order.end(), [&](int a, int b) { return steps[a] > steps[b]; });
+        g.inst_base = insts.size();
+        g.chunk_base = chunk_inst.size();
+        g.chunk_prefix.assign(1, 0);
+        for (int i : g.order) {
+            const int n = states[i].inst->n;
+            const Plan p = make_plan(n, dty);
+            if (!base_of_n.count(n)) {
+                base_of_n[n] = (int)structs.size();
+                batch_structs(p, n, dty, structs);
+            }
+            TB = p.tile_bits;
+            RB = p.reg_bits;
+            BatchInst b;
+            std::memset(&b, 0, sizeof b);
+            b.amp = states[i].amp;
+            b.table = states[i].table;
+            b.T = T[i];
+            b.N = steps[i];
+            b.chunk_offset = g.chunk_prefix.back();
+            b.n = n;
+            b.emax = states[i].inst->e_max;
+            b.r = g.r;
+            b.struct_base = base_of_n[n];
+            const uint64_t chunks = ((1ull << (n - TB)) + kBatchChunkTiles - 1) / kBatchChunkTiles;
+            for (uint64_t c = 0; c < chunks; ++c) chunk_inst.push_back((uint32_t)(insts.size() - g.inst_base));
+            g.chunk_prefix.push_back(g.chunk_prefix.back() + chunks);
+            insts.push_back(b);
+            maxN = std::max(maxN, steps[i]);
         }
-        TB = p.tile_bits;
-        RB = p.reg_bits;
-        rmax = std::max(rmax, (int)p.sets.size());
-        BatchInst b;
-        std::memset(&b, 0, sizeof b);
-        b.amp = states[i].amp;
-        b.table = states[i].table;
-        b.T = T[i];
-        b.N = steps[i];
-        b.tile_offset = tiles;
-        b.n = n;
-        b.emax = states[i].inst->e_max;
-        b.r = (int)p.sets.size();
-        b.struct_base = base_of_n[n];
-        tiles += 1ull << (n - TB);
-        prefix.push_back(tiles);
-        insts.push_back(b);
     }
     unsigned long long *acc = nullptr;
     const int cnt = (int)insts.size();
@@ -962,21 +987,31 @@ qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states
     }
     BatchInst *d_insts = nullptr;
     PassDesc *d_structs = nullptr;
+    uint32_t *d_chunks = nullptr;
     qaa_status r = upload(insts, &d_insts, s);
     if (r == QAA_OK) r = upload(structs, &d_structs, s);
+    if (r == QAA_OK) r = upload(chunk_inst, &d_chunks, s);
     if (r != QAA_OK) return r;
-    const int64_t maxN = insts[0].N;
-    int active = cnt;
+    std::map<int, int> active;
+    for (auto &kv : groups) active[kv.first] = (int)kv.second.order.size();
     for (int64_t k = 0; k < maxN; ++k) {
-        while (active > 0 && insts[active - 1].N <= k) --active;
-        const int jn = k == 0 ? rmax : rmax - 1;
-        for (int j = 0; j < jn; ++j) {
-            hipError_t e = launch_batch_pass(d_insts, active, d_structs, k, j, prefix[active], dty, ety, TB, RB, s);
-            if (e != hipSuccess) return fail(QAA_ERR_DEVICE, "batched pass launch failed: %s", hipGetErrorString(e));
+        for (auto &kv : groups) {
+            const GroupPlan &g = kv.second;
+            int &a = active[kv.first];
+            while (a > 0 && insts[g.inst_base + a - 1].N <= k) --a;
+            if (a == 0) continue;
+            const int jn = k == 0 ? g.r : g.r - 1;
+            for (int j = 0; j < jn; ++j) {
+                hipError_t e = launch_batch_pass(d_insts + g.inst_base, d_chunks + g.chunk_base, g.chunk_prefix[a],
+                                                 d_structs, k, j, kBatchChunkTiles, dty, ety, TB, RB, s);
+                if (e != hipSuccess)
+                    return fail(QAA_ERR_DEVICE, "batched pass launch failed: %s", hipGetErrorString(e));
+            }
         }
     }
     QAA_HIP(hipFreeAsync(d_insts, s));
     QAA_HIP(hipFreeAsync(d_structs, s));
+    QAA_HIP(hipFreeAsync(d_chunks, s));
     if (acc) QAA_HIP(hipFreeAsync(acc, s));
     return QAA_OK;
 }

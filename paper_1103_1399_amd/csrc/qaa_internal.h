@@ -133,7 +133,7 @@ struct BatchInst {
     unsigned long long *acc;   // 3 norm-control slots of this state
     double T;
     int64_t N;
-    uint64_t tile_offset;      // first global tile of this state
+    uint64_t chunk_offset;     // first workgroup chunk of this state in its launch group
     int32_t n, emax, r, struct_base;
 };
 
@@ -147,10 +147,13 @@ hipError_t launch_init_basis(void *amp, int dtype, int n, uint64_t z0, hipStream
 hipError_t launch_pass(void *amp, int dtype, const void *table, int etype, int tile_bits,
                        int reg_bits, const PassDesc &d, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, int count, hipStream_t s);
-// One lock-step pass (step s, sub-pass j) of a batch; grid = tiles of the
-// states listed (count of them, sorted so that running ones come first).
-hipError_t launch_batch_pass(const BatchInst *insts, int count, const PassDesc *structs, int64_t s, int j,
-                             uint64_t grid_tiles, int dtype, int etype, int tile_bits, int reg_bits, hipStream_t st);
+// One lock-step pass (step s, sub-pass j) over a group of states with the
+// same number of qubit sets: workgroup b takes up to chunk_tiles tiles of
+// state chunk_inst[b]; chunks = workgroups launched (the chunks of the
+// states still running, which come first).
+hipError_t launch_batch_pass(const BatchInst *insts, const uint32_t *chunk_inst, uint64_t chunks,
+                             const PassDesc *structs, int64_t s, int j, int chunk_tiles, int dtype, int etype,
+                             int tile_bits, int reg_bits, hipStream_t st);
 // Resident evolution: one state (one != nullptr, descriptor by value) or a
 // batch of `count` states whose descriptors are in device memory.
 hipError_t launch_resident(const ResidentDesc *descs_dev, const ResidentDesc *one, int count, int dtype,
