@@ -111,6 +111,7 @@ def test_evolve_rejects_before_any_device_call():
     (28, 0, (13, 3, 2)),
     (29, 0, (13, 3, 2)),
     (30, 0, (13, 4, 3)),
+    (34, 0, (13, 4, 3)),
     (12, 1, (0, 1, 0)),
     (13, 1, (12, 2, 1)),
     (28, 1, (12, 3, 2)),

@@ -342,11 +342,16 @@ def test_full_size_c64_vs_c128_first_steps(qaa):
     assert abs(oa["norm"] - 1.0) < 1e-5
 
 
-@pytest.mark.parametrize("n", [29, 30, 31])
-def test_large_n_driver_only_closed_form(qaa, n):
+@pytest.mark.parametrize("n,N", [(29, 5), (30, 5), (31, 5), (34, 2)])
+def test_large_n_driver_only_closed_form(qaa, n, N):
     """n = 29 (3 sets), 30 and 31 (4 sets, 3 passes per step; 8 and 16 GiB
-    states): the m = 0 closed form from a basis state, sampled."""
-    T, N, z0 = 20.0, 5, (0x2B6D5A93 & ((1 << n) - 1))
+    states) and the largest n the library accepts, 34 (128 GiB state +
+    16 GiB table): the m = 0 closed form from a basis state, sampled."""
+    assert n <= qaa.QAA_MAX_QUBITS
+    free, _ = torch.cuda.mem_get_info()
+    if free < (9 << n) + (4 << 30):
+        pytest.skip("needs %d GiB of free device memory" % (((9 << n) >> 30) + 4))
+    T, z0 = 20.0, (0x2B6D5A93 & ((1 << n) - 1))
     assert qaa.qaa_plan_info(n)["sets"] == (3 if n == 29 else 4)
     inst = qaa.Instance(n, [])
     table = inst.energy_table()
