@@ -195,6 +195,8 @@ def main():
     ap.add_argument("--serve-t", type=str, default="10,50", help="T range lo,hi of served requests")
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--precision", action="store_true",
+                    help="also run the same job with a complex128 state and report the complex64 error")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -288,6 +290,26 @@ def main():
         cpu = cpu_baseline(inst_in, n, T, N, args.cpu_sample_steps)
 
     extras = {}
+    if args.precision:
+        log("precision study: complex128 run of the same %d steps" % K)
+        ref = torch.empty(1 << n, dtype=torch.complex128, device=dev)
+        h2 = qaa.Instance(n, lits)
+        qaa.qaa_energy_table(h2.handle, table, qaa.QAA_E_U8)
+        st2 = qaa.make_state(h2.handle, ref, table, qaa.QAA_E_U8)
+        qaa.qaa_state_init_uniform(st2)
+        qaa.qaa_evolve_range(st2, T, N, 0, K)
+        obs2 = qaa.qaa_observables(st2)
+        l2 = float(torch.linalg.vector_norm(amp.to(torch.complex128) - ref).item())
+        extras["precision"] = {
+            "reference": "complex128 state on the GPU, same kernels' FP64 variant",
+            "l2_state": l2,
+            "abs_dp_success": abs(obs["p_success"] - obs2["p_success"]),
+            "abs_d_energy": abs(obs["energy"] - obs2["energy"]),
+            "norm_c64_minus_1": obs["norm"] - 1.0,
+            "p_success_c128": obs2["p_success"],
+        }
+        h2.close()
+        del ref
     if args.batch:
         log("batched workload (%d instances)" % args.batch)
         extras["batch"] = run_batch(qaa, torch, args.batch, 2024, min(args.batch, args.batch_loop_sample))

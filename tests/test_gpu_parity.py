@@ -342,6 +342,28 @@ def test_full_size_c64_vs_c128_first_steps(qaa):
     assert abs(oa["norm"] - 1.0) < 1e-5
 
 
+def test_full_size_full_job_c64_vs_c128(qaa):
+    """The benchmark's job in full (n = 28 seed 0, T = 50, 5000 steps):
+    complex64 against the complex128 GPU path at the workload's tolerances
+    (final-state L2 <= 1e-4, |dP_success| <= 1e-5)."""
+    n, T, N = 28, 50.0, 5000
+    inst_in = planted_unique_3sat(n, 0)
+    inst = qaa.Instance(n, inst_in.literals())
+    table = inst.energy_table()
+    a = qaa.State(inst, table, dtype=torch.complex64).init_uniform().evolve(T, N)
+    oa = a.observables()
+    b = qaa.State(inst, table, dtype=torch.complex128).init_uniform().evolve(T, N)
+    ob = b.observables()
+    l2 = float(torch.linalg.vector_norm(a.amp.to(torch.complex128) - b.amp).item())
+    assert l2 <= L2_TOL_C64, l2
+    assert abs(oa["p_success"] - ob["p_success"]) <= P_TOL_C64
+    assert abs(oa["energy"] - ob["energy"]) <= 1e-4 * max(1.0, ob["energy"])
+    assert abs(ob["norm"] - 1.0) < 1e-10
+    assert ob["p_success"] > 0.5          # T = 50 is slow enough to find the planted solution
+    del a, b, table
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("n,N", [(29, 5), (30, 5), (31, 5), (34, 2)])
 def test_large_n_driver_only_closed_form(qaa, n, N):
     """n = 29 (3 sets), 30 and 31 (4 sets, 3 passes per step; 8 and 16 GiB
