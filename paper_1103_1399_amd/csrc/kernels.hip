@@ -435,17 +435,32 @@ __device__ __forceinline__ void pass_compute(TileRegs<F, ET, TB, RB> &tr, typena
         for (int j = 0; j < R; ++j) st = fma(v[j].x, v[j].x, fma(v[j].y, v[j].y, st));
         ssq += (unsigned long long)((double)st * kNormFixedScale + 0.5);
     }
+    // Passes without a phase store with non-temporal (streaming) hints:
+    // measured 5 % faster.  With a phase the hint's register constraints
+    // push the kernel past 256 VGPRs, so those keep plain stores.
 #pragma unroll
     for (int j = 0; j < R; j += VW) {
         if constexpr (VW == 2) {
-            float4 q;
-            q.x = v[j].x;
-            q.y = v[j].y;
-            q.z = v[j + 1].x;
-            q.w = v[j + 1].y;
-            *reinterpret_cast<float4 *>(p + d.goff_last[j]) = q;
+            if constexpr (!PHASE) {
+                typedef float f32x4 __attribute__((ext_vector_type(4)));
+                f32x4 q = {v[j].x, v[j].y, v[j + 1].x, v[j + 1].y};
+                __builtin_nontemporal_store(q, reinterpret_cast<f32x4 *>(p + d.goff_last[j]));
+            } else {
+                float4 q;
+                q.x = v[j].x;
+                q.y = v[j].y;
+                q.z = v[j + 1].x;
+                q.w = v[j + 1].y;
+                *reinterpret_cast<float4 *>(p + d.goff_last[j]) = q;
+            }
         } else {
-            p[d.goff_last[j]] = v[j];
+            if constexpr (!PHASE) {
+                typedef double f64x2 __attribute__((ext_vector_type(2)));
+                f64x2 q = {v[j].x, v[j].y};
+                __builtin_nontemporal_store(q, reinterpret_cast<f64x2 *>(p + d.goff_last[j]));
+            } else {
+                p[d.goff_last[j]] = v[j];
+            }
         }
     }
 }
