@@ -298,7 +298,14 @@ __device__ __forceinline__ void pass_load(TileRegs<F, ET, TB, RB> &tr, const typ
     const F2 *p = amp + (base | tg);
 #pragma unroll
     for (int j = 0; j < P::R; j += P::VW) {
-        if constexpr (P::VW == 2) {
+        if constexpr (P::VW == 2 && PHASE) {
+            typedef float f32x4 __attribute__((ext_vector_type(4)));
+            const f32x4 q = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(p + d.goff_first[j]));
+            v[j].x = q.x;
+            v[j].y = q.y;
+            v[j + 1].x = q.z;
+            v[j + 1].y = q.w;
+        } else if constexpr (P::VW == 2) {
             const float4 q = *reinterpret_cast<const float4 *>(p + d.goff_first[j]);
             v[j].x = q.x;
             v[j].y = q.y;
@@ -499,8 +506,11 @@ __device__ __forceinline__ unsigned long long tile_loop(typename V2<F>::T *__res
     // memory operations in flight is the same on every path; otherwise the
     // compiler's wait counts assume the worst path and stall on the prefetch.
     TileRegs<F, ET, TB, RB> ta, tb;
+    // d.reverse: slot w holds tile (tile_begin + tile_count - 1) - (w - tile_begin)
+    const uint64_t mirror = d.reverse ? 2 * d.tile_begin + d.tile_count - 1 : 0;
+    auto tile_at = [&](uint64_t x) { return tile_base<F, ET, TB, RB>(d, d.reverse ? mirror - x : x); };
     uint64_t w = first;             // callers pass first < end
-    pass_load<F, ET, TB, RB, PHASE>(ta, amp, table, d, tile_base<F, ET, TB, RB>(d, w), tg_first, tid);
+    pass_load<F, ET, TB, RB, PHASE>(ta, amp, table, d, tile_at(w), tg_first, tid);
 
     if constexpr (PHASE) {
         const double scale = acc_in ? rsqrt((double)(*acc_in) * (1.0 / kNormFixedScale)) : 1.0;
@@ -516,20 +526,20 @@ __device__ __forceinline__ unsigned long long tile_loop(typename V2<F>::T *__res
 
     unsigned long long ss = 0ull;
     if constexpr (!PIPE) {
-        pass_compute<F, ET, TB, RB, PHASE>(ta, amp, d, tile_base<F, ET, TB, RB>(d, w), tg_last, tid, tile, lut, etile,
+        pass_compute<F, ET, TB, RB, PHASE>(ta, amp, d, tile_at(w), tg_last, tid, tile, lut, etile,
                                            kA, kB, meas, ss);
     }
     while (PIPE) {
         const uint64_t w1 = w + stride;
-        pass_load<F, ET, TB, RB, PHASE>(tb, amp, table, d, tile_base<F, ET, TB, RB>(d, w1 < end ? w1 : w), tg_first,
+        pass_load<F, ET, TB, RB, PHASE>(tb, amp, table, d, tile_at(w1 < end ? w1 : w), tg_first,
                                         tid);
-        pass_compute<F, ET, TB, RB, PHASE>(ta, amp, d, tile_base<F, ET, TB, RB>(d, w), tg_last, tid, tile, lut, etile,
+        pass_compute<F, ET, TB, RB, PHASE>(ta, amp, d, tile_at(w), tg_last, tid, tile, lut, etile,
                                            kA, kB, meas, ss);
         if (w1 >= end) break;
         const uint64_t w2 = w1 + stride;
-        pass_load<F, ET, TB, RB, PHASE>(ta, amp, table, d, tile_base<F, ET, TB, RB>(d, w2 < end ? w2 : w1), tg_first,
+        pass_load<F, ET, TB, RB, PHASE>(ta, amp, table, d, tile_at(w2 < end ? w2 : w1), tg_first,
                                         tid);
-        pass_compute<F, ET, TB, RB, PHASE>(tb, amp, d, tile_base<F, ET, TB, RB>(d, w1), tg_last, tid, tile, lut,
+        pass_compute<F, ET, TB, RB, PHASE>(tb, amp, d, tile_at(w1), tg_last, tid, tile, lut,
                                            etile, kA, kB, meas, ss);
         if (w2 >= end) break;
         w = w2;

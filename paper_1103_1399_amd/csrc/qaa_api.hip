@@ -791,7 +791,18 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, double T, int64_t N, i
     const double dim = std::ldexp(1.0, st->inst->n);
     int64_t gj = 0;     // index of the next norm-carrying pass
     const int top = (int)p.sets.size() - 1;
+    // Passes over the sets below the top one keep the top set's index bits
+    // as the high bits of their tile numbers, so the region a pass wrote
+    // last is the region the next such pass visits first if it runs in the
+    // opposite direction: consecutive lower-set passes alternate direction
+    // and start on data still in the last-level cache.
+    bool prev_low = false, prev_rev = false;
     for (PassDesc d : ps) {
+        const bool full = d.tile_begin == 0 && d.tile_count == (1ull << d.n_rest);
+        const bool low = d.set_id != top && full;
+        d.reverse = (low && prev_low && !prev_rev) ? 1 : 0;
+        prev_low = low;
+        prev_rev = d.reverse != 0;
         // Norm control rides on the passes over the top qubit set: each one
         // measures the norm of its output, and rescales by the norm the
         // previous one measured (passes over other sets carry no norm work).
