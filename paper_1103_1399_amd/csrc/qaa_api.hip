@@ -341,6 +341,22 @@ struct Plan {
     std::vector<SetPlan> sets;
 };
 
+// Whether the top set takes set 0's highest qubits (see make_plan).
+// Measured per n (complex64): with two sets (n <= 21 at 2^13 tiles) the turn
+// over set 0 otherwise rotates up to 13 qubits twice against a handful in
+// the other turn, and balancing gains up to 6 % (n = 20); with three sets
+// the top set's shorter contiguous runs cost as much as set 0 saves (within
+// 1 %, n = 26 and 28 lose), so it stays off.  QAA_PLAN_BALANCE=0 / 1
+// overrides (tuning).
+bool plan_balance(int sets)
+{
+    static const int force = [] {
+        const char *e = std::getenv("QAA_PLAN_BALANCE");
+        return e ? (e[0] == '1' ? 1 : 0) : -1;
+    }();
+    return force >= 0 ? force == 1 : sets == 2;
+}
+
 Plan make_plan(int n, int dtype)
 {
     Plan p;
@@ -352,20 +368,36 @@ Plan make_plan(int n, int dtype)
     p.tile_bits = TB;
     p.reg_bits = kPassRegBits[dtype];
     const int pas = kPassengerBits[dtype];
+    const int q = TB - pas;                    // qubits a set above set 0 can rotate
+    // Qubits above the tile go to sets of q, ascending.  The top set then
+    // takes set 0's highest qubits until it rotates q of them (set 0 keeps at
+    // least the passenger bits, which only it rotates): the turn passes over
+    // set 0 and over the top set then rotate comparable numbers of qubits.
+    std::vector<std::vector<int>> hi_sets;
+    for (int b = TB; b < n; b += q) {
+        std::vector<int> r;
+        for (int j = b; j < std::min(n, b + q); ++j) r.push_back(j);
+        hi_sets.push_back(r);
+    }
+    int moved = 0;
+    if (!hi_sets.empty() && plan_balance(1 + (int)hi_sets.size()))
+        moved = std::min(q - (int)hi_sets.back().size(), TB - pas);
+    for (int j = 0; j < moved; ++j) hi_sets.back().push_back(TB - 1 - j);
     SetPlan s0;
     for (int b = 0; b < TB; ++b) {
         s0.tile.push_back(b);
-        s0.rot_local.push_back(b);
+        if (b < TB - moved) s0.rot_local.push_back(b);
     }
     p.sets.push_back(s0);
-    const int q = TB - pas;
-    for (int b = TB; b < n; b += q) {
-        const int hi = std::min(n, b + q);
+    for (std::vector<int> r : hi_sets) {
+        std::sort(r.begin(), r.end());
         SetPlan s;
-        const int extra = TB - (hi - b);       // low passenger bits
+        const int extra = TB - (int)r.size();  // low passenger bits
         for (int j = 0; j < extra; ++j) s.tile.push_back(j);
-        for (int j = b; j < hi; ++j) s.tile.push_back(j);
-        for (int j = extra; j < TB; ++j) s.rot_local.push_back(j);
+        for (int b : r) s.tile.push_back(b);
+        std::sort(s.tile.begin(), s.tile.end());
+        for (int j = 0; j < TB; ++j)
+            if (std::find(r.begin(), r.end(), s.tile[j]) != r.end()) s.rot_local.push_back(j);
         p.sets.push_back(s);
     }
     return p;
@@ -396,15 +428,27 @@ std::vector<Group> make_groups(const std::vector<int> &rot, int tb, int rb, int 
     }
     std::sort(members.rbegin(), members.rend());
     const int cap = vw == 2 ? rb - 1 : rb;
+    // the first group must be able to talk to HBM (see io_capable): it takes
+    // only members above the low bits, topped up with high filler bits
+    const int lo_end = vw == 2 ? 5 : 4;
+    size_t first = 0;
+    while (first < members.size() && (int)first < cap && members[first] >= lo_end) ++first;
+    std::vector<size_t> cuts{0};
+    if (first > 0 || members.empty()) cuts.push_back(first);
+    for (size_t i = cuts.back(); i < members.size();) {
+        i = std::min(members.size(), i + cap);
+        cuts.push_back(i);
+    }
     std::vector<Group> gs;
-    for (size_t i = 0; i < members.size() || (gs.empty() && rot0); i += cap) {
+    for (size_t c = 0; c + 1 < cuts.size() || (gs.empty() && rot0); ++c) {
+        const size_t lo = c + 1 < cuts.size() ? cuts[c] : 0, hi = c + 1 < cuts.size() ? cuts[c + 1] : 0;
         Group g;
         g.rot = 0;
         if (vw == 2) {
             g.bits.push_back(0);
             if (rot0 && gs.empty()) g.rot |= 1u;
         }
-        for (size_t j = i; j < std::min(members.size(), i + cap); ++j) {
+        for (size_t j = lo; j < hi; ++j) {
             g.rot |= 1u << g.bits.size();
             g.bits.push_back(members[j]);
         }
@@ -664,10 +708,11 @@ std::vector<PassDesc> schedule_passes(const std::vector<PassDesc> &in, const Pla
     if (lg <= 0 || top < 2) return in;
     // the group index is made of the highest index bits, which must all be
     // rotated by the top set (so that no other pass mixes groups)
-    int top_lo = n;
-    for (size_t j = 0; j < p.sets[top].rot_local.size(); ++j)
-        top_lo = std::min(top_lo, p.sets[top].tile[p.sets[top].rot_local[j]]);
-    const int cbits = std::min(std::max(0, n + amp_log2_bytes - lg), n - top_lo);
+    std::vector<int> top_rot;
+    for (int j : p.sets[top].rot_local) top_rot.push_back(p.sets[top].tile[j]);
+    int run = 0;
+    while (run < n && contains(top_rot, n - 1 - run)) ++run;
+    const int cbits = std::min(std::max(0, n + amp_log2_bytes - lg), run);
     if (cbits == 0) return in;
     std::vector<PassDesc> out;
     size_t i = 0;
