@@ -179,6 +179,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5000, help="second-order steps timed (default: the full job)")
     ap.add_argument("--warmup", type=int, default=20, help="untimed warm-up steps")
     ap.add_argument("--n", type=int, default=28)
+    ap.add_argument("--T", type=float, default=50.0, help="total evolution time of the schedule")
+    ap.add_argument("--schedule-steps", type=int, default=5000, help="second-order steps of the whole schedule")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=2)
@@ -209,7 +211,7 @@ def main():
     import paper_1103_1399_amd as qaa
     from qaa_inputs import planted_unique_3sat
 
-    n, T, N = args.n, 50.0, 5000
+    n, T, N = args.n, args.T, args.schedule_steps
     K, W = args.steps, args.warmup
     if not (1 <= K <= N) or not (0 <= W <= N):
         print("--steps must be in [1, %d] and --warmup in [0, %d]" % (N, N), file=sys.stderr)

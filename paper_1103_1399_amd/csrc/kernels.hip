@@ -699,6 +699,28 @@ __device__ __forceinline__ void resident_body(const ResidentDesc &d)
     const bool active = tid < nthr;
     const uint32_t used = (1u << d.reg_bits) - 1u;   // register-index bits in use
 
+    // Per-group index maps, computed once: thread part lt (per thread) and
+    // register offsets lj (uniform) of every group; reading them from the
+    // descriptor inside the step loop would put a chain of memory loads on
+    // every step.
+    __shared__ uint32_t lt_s[8][1 << WB];
+    __shared__ uint32_t lj_s[8][R];
+    __shared__ uint32_t gm_s[8];
+    for (int g = 0; g < d.n_groups; ++g) {
+        uint32_t lt = 0;
+        for (int k = 0; k < d.thr_bits; ++k) lt |= ((tid >> k) & 1u) << d.tpos[g][k];
+        lt_s[g][tid] = lt;
+    }
+    for (uint32_t x = tid; x < 8u * R; x += blockDim.x) {
+        const int g = (int)(x / R), j = (int)(x % R);
+        uint32_t o = 0;
+        if (g < d.n_groups)
+            for (int i = 0; i < RB && i < d.reg_bits; ++i)
+                if ((j >> i) & 1) o |= 1u << d.gbits[g][i];
+        lj_s[g][j] = o;
+    }
+    if (tid < 8) gm_s[tid] = d.gmask[tid];
+
     for (uint32_t z = tid; z < dim; z += blockDim.x) {
         tile[swz<F>(z)] = amp[z];
         etile[z] = table[z];
@@ -707,20 +729,21 @@ __device__ __forceinline__ void resident_body(const ResidentDesc &d)
     const double T = d.T;
     const double Nd = (double)d.N;
     const double dt = T / Nd;
-    __shared__ double red[1 << WB];
-    __shared__ double norm_sh;
+    __shared__ double red[(1 << WB) / 64];
     double part = 0.0;     // this thread's share of |psi|^2 after the last residency
-    // Norm of the state from the per-thread partials (fixed order).
+    // Norm of the state from the per-thread partials: butterfly sums inside
+    // each wave, then the wave sums in order (a fixed order: deterministic).
     auto measure = [&]() {
-        red[tid] = part;
+        double t = part;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+        if ((tid & 63) == 0) red[tid >> 6] = t;
         __syncthreads();
-        if (tid == 0) {
-            double t = 0.0;
-            for (uint32_t k = 0; k < blockDim.x; ++k) t += red[k];
-            norm_sh = t;
-        }
-        __syncthreads();
-        return norm_sh;
+        double total = 0.0;
+#pragma unroll
+        for (int w = 0; w < (1 << WB) / 64; ++w) total += red[w];
+        __syncthreads();      // red is rewritten by the next measure
+        return total;
     };
     auto build_lut = [&](double phi, double gph, double scale) {
         __syncthreads();
@@ -736,18 +759,11 @@ __device__ __forceinline__ void resident_body(const ResidentDesc &d)
     };
     auto residency = [&](int g, bool phase, uint32_t rmask, const Rot<F> &k, bool meas) {
         if (active) {
-            uint32_t lt = 0;
-            for (int k = 0; k < d.thr_bits; ++k) lt |= ((tid >> k) & 1u) << d.tpos[g][k];
+            const uint32_t lt = lt_s[g][tid];
             const uint32_t slt = swz<F>(lt);
             uint32_t lj[R];
 #pragma unroll
-            for (int j = 0; j < R; ++j) {
-                uint32_t x = 0;
-#pragma unroll
-                for (int i = 0; i < RB; ++i)
-                    if (((j >> i) & 1) && i < d.reg_bits) x |= 1u << d.gbits[g][i];
-                lj[j] = x;
-            }
+            for (int j = 0; j < R; ++j) lj[j] = lj_s[g][j];
             F2 v[R];
 #pragma unroll
             for (int j = 0; j < R; ++j)
@@ -788,7 +804,7 @@ __device__ __forceinline__ void resident_body(const ResidentDesc &d)
         double rt, rs;
         rot_params(theta, rt, rs, flip_prev);
         const Rot<F> rk = make_rot<F>(rt, rs);
-        for (int g = 0; g < d.n_groups; ++g) residency(g, g == 0, d.gmask[g], rk, g == d.n_groups - 1);
+        for (int g = 0; g < d.n_groups; ++g) residency(g, g == 0, gm_s[g], rk, g == d.n_groups - 1);
         theta_prev = theta;
         s_prev = sk;
     }
