@@ -28,6 +28,14 @@
  *    queued on the stream has finished.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Calls are asynchronous on it unless stated otherwise.
+ *  - Library-owned device memory: a per-device block of reduction scratch
+ *    (created on first use, kept until the process ends), a device copy of
+ *    each instance's clause list, and small per-call buffers (norm
+ *    accumulators, batch descriptors) taken from the stream-ordered
+ *    allocator and released in stream order by the call that took them.
+ *  - Calls that read back results (qaa_energy_table, qaa_observables) are
+ *    serialised per device; evolution calls on different streams run
+ *    concurrently.
  *  - Errors: every call returns a qaa_status; nothing throws or aborts
  *    across the ABI.  qaa_last_error() returns a thread-local message for
  *    the last failing call of the calling thread.
@@ -239,8 +247,9 @@ qaa_status qaa_server_wait(qaa_server *sv, int64_t ticket, qaa_server_result *ou
 /* Queue length, running solves and admitted footprint in bytes (any may be NULL). */
 qaa_status qaa_server_stats(qaa_server *sv, int64_t *queued, int64_t *running, uint64_t *bytes_in_use);
 
-/* Stop the server: solves already admitted finish, queued ones are dropped.
- * No thread may wait on a ticket of a dropped request.  NULL is ignored. */
+/* Stop the server: solves already admitted finish, queued ones are dropped,
+ * then the server is freed.  No other call on this server may run
+ * concurrently with or after this one.  NULL is ignored. */
 void qaa_server_destroy(qaa_server *sv);
 
 /* ---------------------------------------------------------------------
