@@ -228,6 +228,43 @@ def test_zero_steps_and_zero_time_are_identity(qaa):
     assert abs(obs["energy"] - inst_in.m / 8.0) < inst_in.m / 8.0 * 1e-6
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_evolve_tiny_states(qaa, n):
+    """The smallest states (a single clause when n >= 3, none below) through
+    the resident path, against the oracle, complex64 and complex128."""
+    clauses = np.asarray([[1, -2, 3]] if n >= 3 else np.zeros((0, 3)), np.int32).reshape(-1, 3)
+    T, N = 3.0, 25
+    psi, ref = _oracle_run(n, clauses, T, N)
+    for dtype, l2_tol in ((torch.complex64, L2_TOL_C64), (torch.complex128, L2_TOL_C128)):
+        inst = qaa.Instance(n, clauses.reshape(-1))
+        table = inst.energy_table()
+        st = qaa.State(inst, table, dtype=dtype).init_uniform()
+        st.evolve(T, N)
+        obs = st.observables()
+        got = st.amp.cpu().numpy().astype(np.complex128)
+        assert np.linalg.norm(got - psi) <= l2_tol
+        assert abs(obs["p_success"] - ref["p_success"]) <= max(l2_tol, 1e-12)
+        inst.close()
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_configurations_vs_oracle(qaa, seed):
+    """Seeded random draws of n (5..23), T, step count, dtype and the table
+    type against the oracle: resident, two-set and three-set plans, both
+    energy widths, any step size (angles reduced by pi included)."""
+    rng = SplitMix64(9000 + seed)
+    n = 5 + rng.below(19)
+    T = rng.uniform(0.5, 40.0)
+    N = 1 + rng.below(60)
+    dtype = torch.complex128 if rng.below(3) == 0 else torch.complex64
+    et = qaa.QAA_E_U16 if rng.below(2) else qaa.QAA_E_U8
+    inst_in = planted_unique_3sat(n, 9100 + seed)
+    psi, ref = _oracle_run(n, inst_in.clauses, T, N)
+    _, _, st, obs = _run_gpu(qaa, n, inst_in.clauses, T, N, dtype=dtype, etype=et)
+    tol = L2_TOL_C128 if dtype == torch.complex128 else L2_TOL_C64
+    _compare(st, obs, psi, ref, tol, max(tol, 1e-12) if dtype == torch.complex128 else P_TOL_C64)
+
+
 def test_deterministic(qaa):
     n, T, N = 18, 5.0, 20
     inst_in = planted_unique_3sat(n, 71)
