@@ -357,6 +357,16 @@ bool plan_balance(int sets)
     return force >= 0 ? force == 1 : sets == 2;
 }
 
+// Tuning switch QAA_PLAN_PASSENGERS (default on): see make_plan.
+bool plan_passengers_to_set1()
+{
+    static const bool on = [] {
+        const char *e = std::getenv("QAA_PLAN_PASSENGERS");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
+
 Plan make_plan(int n, int dtype)
 {
     Plan p;
@@ -399,6 +409,24 @@ Plan make_plan(int n, int dtype)
         for (int j = 0; j < TB; ++j)
             if (std::find(r.begin(), r.end(), s.tile[j]) != r.end()) s.rot_local.push_back(j);
         p.sets.push_back(s);
+    }
+    // With three or more sets, every step visits set 1 once, next to set 0
+    // and with no phase in between, and set 1's tile holds the passenger
+    // bits.  Those qubits' rotations move from set 0 to set 1: the turn
+    // over set 0 then rotates 8 qubits twice instead of 13, the middle
+    // passes (HBM-bound, with VALU to spare) 13 instead of 8.
+    if (p.sets.size() >= 3 && plan_passengers_to_set1()) {
+        // (complex64: bit 0 stays with set 0; it is a register bit of every
+        // group, so it costs set 0 no extra exchange)
+        const int lo = dtype == 0 ? 1 : 0;
+        std::vector<int> keep;
+        for (int j : p.sets[0].rot_local)
+            if (j < lo || j >= pas) keep.push_back(j);
+        p.sets[0].rot_local = keep;
+        std::vector<int> r1;
+        for (int j = lo; j < pas; ++j) r1.push_back(j);     // tile-local = physical for passengers
+        for (int j : p.sets[1].rot_local) r1.push_back(j);
+        p.sets[1].rot_local = r1;
     }
     return p;
 }
@@ -525,8 +553,19 @@ uint32_t pad_index(uint32_t l, int dt) { return l + (uint32_t)kPadN[dt] * (l >> 
 void fill_residencies(PassDesc &d, const SetPlan &sp, int tb, int rb, int dt, bool v1, bool ph, bool v2)
 {
     const int vw = dt == 0 ? 2 : 1;
-    const std::vector<Group> gs = make_groups(sp.rot_local, tb, rb, vw);
+    std::vector<Group> gs = make_groups(sp.rot_local, tb, rb, vw);
     const int G = (int)gs.size();
+    // Group order: the first group (always HBM-capable) first, then the
+    // groups that cannot talk to HBM, then the other HBM-capable ones, so
+    // that passes ending on the last group store directly when possible.
+    {
+        std::vector<Group> ord{gs[0]};
+        for (int g = 1; g < G; ++g)
+            if (!io_capable(gs[g], vw)) ord.push_back(gs[g]);
+        for (int g = 1; g < G; ++g)
+            if (io_capable(gs[g], vw)) ord.push_back(gs[g]);
+        gs = ord;
+    }
     struct Res {
         int g;
         uint32_t ma, mb;
