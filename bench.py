@@ -38,8 +38,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
 # WRITE_SIZE runs, scaled by the same counters' reading for a plain copy of
 # known size).  Valid only for the kernel source it was taken on.
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "c8dbc11eb9457cee7f2207271276c85d75f14f727a4b0a061a97f4e3b2df2cd6",
-    "bytes_per_launch": 4.520424e+09,
+    "kernel_source_sha256": "775dc9c5552bc44ad70dfcc2c8b1911c83e752c655e0af71dac79e730c1e1b06",
+    "bytes_per_launch": 4.521251e+09,
 }
 
 
