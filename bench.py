@@ -203,7 +203,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build evolves each state on a single MI355X and has no "
+        print("bench.py measures one GPU: the library evolves each state on a single MI355X and has no "
               "multi-GPU path (asked for --gpus %d, WORLD_SIZE=%d)" % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
 

@@ -20,8 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libqaa.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        "libqaa.so is not built (expected at %s); run `python -c \"import __graft_entry__ as g; g.build()\"` "
-        "or `python paper_1103_1399_amd/build.py`" % LIB_PATH)
+        "libqaa.so is not built (expected at %s); run `python paper_1103_1399_amd/build.py`" % LIB_PATH)
 
 # One HIP runtime per process.  PyTorch's ROCm wheels carry their own copies
 # of the HIP and HSA runtimes; when torch is loaded first, libqaa's runtime
