@@ -197,6 +197,8 @@ def main():
     ap.add_argument("--serve-t", type=str, default="10,50", help="T range lo,hi of served requests")
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the plan autotuner for this n before the timed region (qaa_autotune)")
     ap.add_argument("--precision", action="store_true",
                     help="also run the same job with a complex128 state and report the complex64 error")
     args = ap.parse_args()
@@ -242,6 +244,9 @@ def main():
     h = qaa.Instance(n, lits)
     qaa.qaa_energy_table(h.handle, table, qaa.QAA_E_U8)
     st = qaa.make_state(h.handle, amp, table, qaa.QAA_E_U8)
+    if args.autotune:
+        tuned = qaa.qaa_autotune(st, steps=10)
+        log("autotune: %s" % tuned)
     qaa.qaa_state_init_uniform(st)
     if W:
         qaa.qaa_evolve_range(st, T, N, 0, W)
@@ -345,6 +350,7 @@ def main():
                         % (n, inst_in.m, args.seed, T, N),
             "n": n, "m": inst_in.m, "T": T, "schedule_steps": N,
             "plan": plan,
+            "plan_choice": qaa.qaa_plan_get(n, qaa.QAA_C64),
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -267,6 +267,42 @@ qaa_status qaa_plan_info(int32_t n, qaa_dtype dtype, int32_t *tile_bits, int32_t
                          int32_t *passes_per_step);
 
 /*
+ * Qubit assignment of a plan with two or more sets (the tile shapes are
+ * fixed; which set rotates which qubit is not):
+ *   balance    : 1 = the top set also rotates set 0's highest qubits, up to
+ *                as many as a set above set 0 can hold.
+ *   passengers : 1 = with three or more sets, the low "passenger" qubits
+ *                (1..4 for complex64, 0..3 for complex128), which ride in
+ *                every set's tiles, rotate in the set-1 passes instead of
+ *                the set-0 turn.
+ * Results do not depend on the choice beyond FP32 rounding order.  The
+ * choice is process-wide per (n, dtype); the environment variables
+ * QAA_PLAN_BALANCE / QAA_PLAN_PASSENGERS (0 or 1), if set, override it.
+ */
+typedef struct qaa_plan_choice {
+    int32_t balance;
+    int32_t passengers;
+} qaa_plan_choice;
+
+/* The choice in effect for (n, dtype): recorded, else the built-in default
+ * (balance for two sets, passengers for three or more). */
+qaa_status qaa_plan_get(int32_t n, qaa_dtype dtype, qaa_plan_choice *out);
+
+/* Record a choice for (n, dtype) (each field 0 or 1); NULL restores the
+ * default.  Affects calls made after it returns. */
+qaa_status qaa_plan_set(int32_t n, qaa_dtype dtype, const qaa_plan_choice *choice);
+
+/*
+ * Autotuner: time `steps` steps (step size 0.01) of every candidate choice
+ * for the scratch state's (n, dtype) on the stream, record the fastest with
+ * qaa_plan_set, and return it (*best, *ms_per_step may be NULL).  The
+ * scratch state's amplitudes are overwritten; its energy table must have
+ * been computed.  SYNCHRONOUS.
+ */
+qaa_status qaa_autotune(const qaa_state *scratch, int64_t steps, qaa_plan_choice *best, double *ms_per_step,
+                        void *stream);
+
+/*
  * Diagnostic: the pass descriptors qaa_evolve_range would launch for an
  * n-qubit state (energies up to emax) over steps k0..k1-1 of `steps`.
  * Writes up to `capacity` descriptors of *desc_bytes bytes each into the

@@ -71,6 +71,10 @@ class qaa_obs(ctypes.Structure):
                 ("e_min", ctypes.c_int32), ("degeneracy", ctypes.c_int64)]
 
 
+class qaa_plan_choice(ctypes.Structure):
+    _fields_ = [("balance", ctypes.c_int32), ("passengers", ctypes.c_int32)]
+
+
 class qaa_server_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("slots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
@@ -111,6 +115,10 @@ _SIGS = {
     "qaa_server_wait": (_st, [_vp, ctypes.c_int64, ctypes.POINTER(qaa_server_result)]),
     "qaa_server_stats": (_st, [_vp, _i64p, _i64p, ctypes.POINTER(ctypes.c_uint64)]),
     "qaa_server_destroy": (None, [_vp]),
+    "qaa_plan_get": (_st, [ctypes.c_int32, ctypes.c_int, ctypes.POINTER(qaa_plan_choice)]),
+    "qaa_plan_set": (_st, [ctypes.c_int32, ctypes.c_int, ctypes.POINTER(qaa_plan_choice)]),
+    "qaa_autotune": (_st, [ctypes.POINTER(qaa_state), ctypes.c_int64, ctypes.POINTER(qaa_plan_choice),
+                           ctypes.POINTER(ctypes.c_double), _vp]),
     "qaa_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "qaa_last_error": (ctypes.c_char_p, []),
     "qaa_version": (ctypes.c_int32, []),
@@ -272,6 +280,29 @@ def qaa_profile_read(reset: bool = True) -> dict:
     _check(_lib.qaa_profile_read(ctypes.byref(out), 1 if reset else 0), "qaa_profile_read")
     return {"launches": out.launches, "kernel_ms": out.kernel_ms, "min_ms": out.min_ms, "max_ms": out.max_ms,
             "alg_bytes": out.alg_bytes}
+
+
+def qaa_plan_get(n: int, dtype: int = QAA_C64) -> dict:
+    c = qaa_plan_choice()
+    _check(_lib.qaa_plan_get(int(n), int(dtype), ctypes.byref(c)), "qaa_plan_get")
+    return {"balance": c.balance, "passengers": c.passengers}
+
+
+def qaa_plan_set(n: int, dtype: int = QAA_C64, choice: dict | None = None) -> None:
+    """Record a plan choice for (n, dtype); None restores the default."""
+    if choice is None:
+        _check(_lib.qaa_plan_set(int(n), int(dtype), None), "qaa_plan_set")
+        return
+    c = qaa_plan_choice(int(choice["balance"]), int(choice["passengers"]))
+    _check(_lib.qaa_plan_set(int(n), int(dtype), ctypes.byref(c)), "qaa_plan_set")
+
+
+def qaa_autotune(state: qaa_state, steps: int = 20, stream=None) -> dict:
+    best = qaa_plan_choice()
+    ms = ctypes.c_double()
+    _check(_lib.qaa_autotune(ctypes.byref(state), int(steps), ctypes.byref(best), ctypes.byref(ms),
+                             _stream_ptr(stream)), "qaa_autotune")
+    return {"balance": best.balance, "passengers": best.passengers, "ms_per_step": ms.value}
 
 
 def _result_dict(r: qaa_server_result) -> dict:

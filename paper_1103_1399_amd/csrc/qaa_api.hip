@@ -341,30 +341,45 @@ struct Plan {
     std::vector<SetPlan> sets;
 };
 
-// Whether the top set takes set 0's highest qubits (see make_plan).
-// Measured per n (complex64): with two sets (n <= 21 at 2^13 tiles) the turn
-// over set 0 otherwise rotates up to 13 qubits twice against a handful in
-// the other turn, and balancing gains up to 6 % (n = 20); with three sets
-// the top set's shorter contiguous runs cost as much as set 0 saves (within
-// 1 %, n = 26 and 28 lose), so it stays off.  QAA_PLAN_BALANCE=0 / 1
-// overrides (tuning).
-bool plan_balance(int sets)
+// Plan choices per (n, dtype).  balance: the top set takes set 0's highest
+// qubits until it rotates as many as a set above set 0 can.  passengers:
+// with three or more sets, the passenger qubits (except complex64's bit 0)
+// rotate in the set-1 passes (see make_plan).  Defaults, measured per n
+// (complex64): with two sets the turn over set 0 otherwise rotates up to 13
+// qubits twice against a handful in the other turn, and balancing gains up
+// to 6 % (n = 20); with three sets the top set's shorter contiguous runs
+// cost as much as set 0 saves (n = 26 and 28 lose about 1 %), so balancing
+// is off there, while moving the passengers is 3 % faster at n = 28.
+// qaa_plan_set / qaa_autotune record other choices; the environment
+// variables QAA_PLAN_BALANCE and QAA_PLAN_PASSENGERS (0 or 1) override all.
+struct PlanChoice {
+    int balance, passengers;
+};
+
+std::mutex g_plan_mu;
+std::map<std::pair<int, int>, PlanChoice> g_plan_choice;
+
+PlanChoice default_plan_choice(int sets) { return PlanChoice{sets == 2 ? 1 : 0, sets >= 3 ? 1 : 0}; }
+
+int env_knob(const char *name)
 {
-    static const int force = [] {
-        const char *e = std::getenv("QAA_PLAN_BALANCE");
-        return e ? (e[0] == '1' ? 1 : 0) : -1;
-    }();
-    return force >= 0 ? force == 1 : sets == 2;
+    const char *e = std::getenv(name);
+    return e ? (e[0] == '1' ? 1 : 0) : -1;
 }
 
-// Tuning switch QAA_PLAN_PASSENGERS (default on): see make_plan.
-bool plan_passengers_to_set1()
+PlanChoice plan_choice(int n, int dtype, int sets)
 {
-    static const bool on = [] {
-        const char *e = std::getenv("QAA_PLAN_PASSENGERS");
-        return !(e && e[0] == '0');
-    }();
-    return on;
+    PlanChoice c = default_plan_choice(sets);
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        auto it = g_plan_choice.find({n, dtype});
+        if (it != g_plan_choice.end()) c = it->second;
+    }
+    static const int force_balance = env_knob("QAA_PLAN_BALANCE");
+    static const int force_passengers = env_knob("QAA_PLAN_PASSENGERS");
+    if (force_balance >= 0) c.balance = force_balance;
+    if (force_passengers >= 0) c.passengers = force_passengers;
+    return c;
 }
 
 Plan make_plan(int n, int dtype)
@@ -389,8 +404,9 @@ Plan make_plan(int n, int dtype)
         for (int j = b; j < std::min(n, b + q); ++j) r.push_back(j);
         hi_sets.push_back(r);
     }
+    const PlanChoice choice = plan_choice(n, dtype, 1 + (int)hi_sets.size());
     int moved = 0;
-    if (!hi_sets.empty() && plan_balance(1 + (int)hi_sets.size()))
+    if (!hi_sets.empty() && choice.balance)
         moved = std::min(q - (int)hi_sets.back().size(), TB - pas);
     for (int j = 0; j < moved; ++j) hi_sets.back().push_back(TB - 1 - j);
     SetPlan s0;
@@ -415,7 +431,7 @@ Plan make_plan(int n, int dtype)
     // bits.  Those qubits' rotations move from set 0 to set 1: the turn
     // over set 0 then rotates 8 qubits twice instead of 13, the middle
     // passes (HBM-bound, with VALU to spare) 13 instead of 8.
-    if (p.sets.size() >= 3 && plan_passengers_to_set1()) {
+    if (p.sets.size() >= 3 && choice.passengers) {
         // (complex64: bit 0 stays with set 0; it is a register bit of every
         // group, so it costs set 0 no extra exchange)
         const int lo = dtype == 0 ? 1 : 0;
@@ -1195,6 +1211,85 @@ extern "C" qaa_status qaa_observables(const qaa_state *st, qaa_obs *out, void *s
 // ---------------------------------------------------------------------------
 // Plan introspection, errors, version
 // ---------------------------------------------------------------------------
+extern "C" qaa_status qaa_plan_get(int32_t n, qaa_dtype dtype, qaa_plan_choice *out)
+{
+    if (n < 1 || n > QAA_MAX_QUBITS || (dtype != QAA_C64 && dtype != QAA_C128) || !out)
+        return fail(QAA_ERR_INVALID_ARG, "qaa_plan_get: bad argument");
+    const Plan p = make_plan(n, (int)dtype);
+    const PlanChoice c = plan_choice(n, (int)dtype, p.resident ? 1 : (int)p.sets.size());
+    out->balance = c.balance;
+    out->passengers = c.passengers;
+    return ok();
+}
+
+extern "C" qaa_status qaa_plan_set(int32_t n, qaa_dtype dtype, const qaa_plan_choice *choice)
+{
+    if (n < 1 || n > QAA_MAX_QUBITS || (dtype != QAA_C64 && dtype != QAA_C128))
+        return fail(QAA_ERR_INVALID_ARG, "qaa_plan_set: bad argument");
+    if (choice && ((choice->balance != 0 && choice->balance != 1) ||
+                   (choice->passengers != 0 && choice->passengers != 1)))
+        return fail(QAA_ERR_INVALID_ARG, "qaa_plan_set: choices are 0 or 1");
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    if (choice)
+        g_plan_choice[{n, (int)dtype}] = PlanChoice{choice->balance, choice->passengers};
+    else
+        g_plan_choice.erase({n, (int)dtype});
+    return ok();
+}
+
+extern "C" qaa_status qaa_autotune(const qaa_state *scratch, int64_t steps, qaa_plan_choice *best,
+                                   double *ms_per_step, void *stream)
+{
+    qaa_status r = check_state_table(scratch, "qaa_autotune");
+    if (r != QAA_OK) return r;
+    if (steps < 1) return fail(QAA_ERR_INVALID_ARG, "qaa_autotune: steps < 1");
+    const int n = scratch->inst->n, dt = (int)scratch->dtype;
+    const Plan p0 = make_plan(n, dt);
+    std::vector<PlanChoice> cands;
+    if (p0.resident || p0.sets.size() < 2)
+        cands.push_back(default_plan_choice(1));
+    else if (p0.sets.size() == 2)
+        cands = {PlanChoice{0, 0}, PlanChoice{1, 0}};
+    else
+        cands = {PlanChoice{0, 0}, PlanChoice{0, 1}, PlanChoice{1, 0}, PlanChoice{1, 1}};
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    QAA_HIP(hipEventCreate(&e0));
+    QAA_HIP(hipEventCreate(&e1));
+    const double T = 0.01 * (double)steps;     // the step size of the workloads
+    float best_ms = 0.0f;
+    PlanChoice best_c = cands[0];
+    for (const PlanChoice &c : cands) {
+        const qaa_plan_choice qc{c.balance, c.passengers};
+        qaa_plan_set(n, scratch->dtype, &qc);
+        r = qaa_state_init_uniform(scratch, stream);
+        if (r == QAA_OK) r = qaa_evolve_range(scratch, nullptr, T, steps, 0, 1, stream);     // warm-up
+        hipError_t he = r == QAA_OK ? hipEventRecord(e0, s) : hipSuccess;
+        if (r == QAA_OK && he == hipSuccess) r = qaa_evolve_range(scratch, nullptr, T, steps, 0, steps, stream);
+        if (r == QAA_OK && he == hipSuccess) he = hipEventRecord(e1, s);
+        if (r == QAA_OK && he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (r == QAA_OK && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (r != QAA_OK || he != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            qaa_plan_set(n, scratch->dtype, nullptr);
+            return r != QAA_OK ? r : fail(QAA_ERR_DEVICE, "qaa_autotune: %s", hipGetErrorString(he));
+        }
+        if (&c == &cands[0] || ms < best_ms) {
+            best_ms = ms;
+            best_c = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const qaa_plan_choice qb{best_c.balance, best_c.passengers};
+    qaa_plan_set(n, scratch->dtype, &qb);
+    if (best) *best = qb;
+    if (ms_per_step) *ms_per_step = (double)best_ms / (double)steps;
+    return ok();
+}
+
 extern "C" qaa_status qaa_plan_info(int32_t n, qaa_dtype dtype, int32_t *tile_bits, int32_t *sets,
                                     int32_t *passes_per_step)
 {

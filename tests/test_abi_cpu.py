@@ -157,3 +157,21 @@ def test_one_hip_runtime_in_process():
     maps = open("/proc/self/maps").read().splitlines()
     hip = {line.split()[-1] for line in maps if "libamdhip64" in line}
     assert len(hip) == 1, hip
+
+
+def test_plan_choice_defaults_set_and_reset():
+    assert qaa.qaa_plan_get(16) == {"balance": 1, "passengers": 0}      # two sets
+    assert qaa.qaa_plan_get(28) == {"balance": 0, "passengers": 1}      # three sets
+    try:
+        qaa.qaa_plan_set(28, qaa.QAA_C64, {"balance": 1, "passengers": 0})
+        assert qaa.qaa_plan_get(28) == {"balance": 1, "passengers": 0}
+        assert qaa.qaa_plan_get(28, qaa.QAA_C128) == {"balance": 0, "passengers": 1}   # per dtype
+    finally:
+        qaa.qaa_plan_set(28, qaa.QAA_C64, None)
+    assert qaa.qaa_plan_get(28) == {"balance": 0, "passengers": 1}
+    lib = qaa._lib
+    bad = qaa.qaa_plan_choice(2, 0)
+    assert lib.qaa_plan_set(28, 0, ctypes.byref(bad)) == qaa.QAA_ERR_INVALID_ARG
+    assert lib.qaa_plan_set(35, 0, None) == qaa.QAA_ERR_INVALID_ARG
+    assert lib.qaa_plan_get(28, 0, None) == qaa.QAA_ERR_INVALID_ARG
+    assert lib.qaa_autotune(None, 10, None, None, None) == qaa.QAA_ERR_INVALID_ARG

@@ -265,6 +265,40 @@ def test_random_configurations_vs_oracle(qaa, seed):
     _compare(st, obs, psi, ref, tol, max(tol, 1e-12) if dtype == torch.complex128 else P_TOL_C64)
 
 
+@pytest.mark.parametrize("choice", [{"balance": 0, "passengers": 0}, {"balance": 1, "passengers": 0},
+                                    {"balance": 0, "passengers": 1}, {"balance": 1, "passengers": 1}])
+def test_plan_choices_vs_oracle(qaa, choice):
+    """Every qubit assignment of a three-set plan (n = 22) on the GPU."""
+    n, T, N = 22, 5.0, 12
+    inst_in = planted_unique_3sat(n, 77)
+    psi, ref = _oracle_run(n, inst_in.clauses, T, N)
+    try:
+        qaa.qaa_plan_set(n, qaa.QAA_C64, choice)
+        _, _, st, obs = _run_gpu(qaa, n, inst_in.clauses, T, N)
+    finally:
+        qaa.qaa_plan_set(n, qaa.QAA_C64, None)
+    _compare(st, obs, psi, ref, L2_TOL_C64, P_TOL_C64)
+
+
+def test_autotune_records_a_choice(qaa):
+    n = 23
+    inst_in = planted_unique_3sat(n, 5)
+    inst = qaa.Instance(n, inst_in.literals())
+    table = inst.energy_table()
+    st = qaa.State(inst, table)
+    try:
+        best = qaa.qaa_autotune(st.c, steps=10)
+        assert best["balance"] in (0, 1) and best["passengers"] in (0, 1) and best["ms_per_step"] > 0
+        assert qaa.qaa_plan_get(n) == {"balance": best["balance"], "passengers": best["passengers"]}
+        # the tuned plan evolves correctly
+        T, N = 4.0, 6
+        psi, ref = _oracle_run(n, inst_in.clauses, T, N)
+        st.init_uniform().evolve(T, N)
+        _compare(st, st.observables(), psi, ref, L2_TOL_C64, P_TOL_C64)
+    finally:
+        qaa.qaa_plan_set(n, qaa.QAA_C64, None)
+
+
 def test_deterministic(qaa):
     n, T, N = 18, 5.0, 20
     inst_in = planted_unique_3sat(n, 71)

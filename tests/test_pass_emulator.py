@@ -150,6 +150,26 @@ def test_chunked_schedule_replays_the_oracle(n, T, N, chunk_log2, monkeypatch):
     assert np.max(np.abs(got - ref)) < 1e-12
 
 
+@pytest.mark.parametrize("n,choice", [(16, {"balance": 0, "passengers": 0}), (16, {"balance": 1, "passengers": 0}),
+                                      (22, {"balance": 0, "passengers": 0}), (22, {"balance": 1, "passengers": 0}),
+                                      (22, {"balance": 0, "passengers": 1}), (22, {"balance": 1, "passengers": 1})])
+def test_every_plan_choice_replays_the_oracle(n, choice):
+    """Which set rotates which qubit is a free choice (qaa_plan_set); every
+    choice must still rotate each qubit exactly once per step."""
+    T, N = 5.0, 3
+    inst = planted_unique_3sat(n, 700 + n)
+    E = oracle.energy(n, inst.clauses).astype(np.int64)
+    psi = np.full(1 << n, 2.0 ** (-n / 2), np.complex128)
+    try:
+        qaa.qaa_plan_set(n, 0, choice)
+        got, _ = _replay(n, 0, E, psi, T, N, 0, N)
+    finally:
+        qaa.qaa_plan_set(n, 0, None)
+    ref = oracle.init_uniform(n)
+    oracle.evolve(n, inst.clauses, ref, T, N)
+    assert np.max(np.abs(got - ref)) < 1e-12
+
+
 def test_pass_plan_range_replay():
     n, T, N = 17, 5.0, 9
     inst = planted_unique_3sat(n, 7)
