@@ -75,7 +75,6 @@ struct DeviceCtx {
     double *obs_out = nullptr;              // [4]
     void *host_pinned = nullptr;            // 256 B staging for readbacks
     hipStream_t side = nullptr;             // second stream for batched small states
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 std::mutex g_dev_mu;
@@ -103,8 +102,6 @@ qaa_status device_ctx(DeviceCtx **out)
         ctx->partials = reinterpret_cast<double *>(base + 256);
         QAA_HIP(hipHostMalloc(&ctx->host_pinned, 256, hipHostMallocDefault));
         QAA_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
-        QAA_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
-        QAA_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
         ctx->ready = true;
     }
     *out = ctx;
@@ -1015,12 +1012,18 @@ qaa_status upload(const std::vector<T> &host, T **dev, hipStream_t s)
     const size_t bytes = sizeof(T) * std::max<size_t>(1, host.size());
     QAA_HIP(hipMallocAsync(reinterpret_cast<void **>(dev), bytes, s));
     void *pinned = nullptr;
-    QAA_HIP(hipHostMalloc(&pinned, bytes, hipHostMallocDefault));
-    std::memcpy(pinned, host.data(), sizeof(T) * host.size());
-    hipError_t e = hipMemcpyAsync(*dev, pinned, sizeof(T) * host.size(), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipHostFree(pinned);
-    if (e != hipSuccess) return fail(QAA_ERR_DEVICE, "descriptor upload failed: %s", hipGetErrorString(e));
+    hipError_t e = hipHostMalloc(&pinned, bytes, hipHostMallocDefault);
+    if (e == hipSuccess) {
+        std::memcpy(pinned, host.data(), sizeof(T) * host.size());
+        e = hipMemcpyAsync(*dev, pinned, sizeof(T) * host.size(), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        (void)hipHostFree(pinned);
+    }
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(*dev, s);
+        *dev = nullptr;
+        return fail(QAA_ERR_DEVICE, "descriptor upload failed: %s", hipGetErrorString(e));
+    }
     return QAA_OK;
 }
 
@@ -1099,10 +1102,20 @@ qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states
     BatchInst *d_insts = nullptr;
     PassDesc *d_structs = nullptr;
     uint32_t *d_chunks = nullptr;
+    // every buffer this call took goes back in stream order, on every path
+    auto release = [&]() {
+        if (d_insts) (void)hipFreeAsync(d_insts, s);
+        if (d_structs) (void)hipFreeAsync(d_structs, s);
+        if (d_chunks) (void)hipFreeAsync(d_chunks, s);
+        if (acc) (void)hipFreeAsync(acc, s);
+    };
     qaa_status r = upload(insts, &d_insts, s);
     if (r == QAA_OK) r = upload(structs, &d_structs, s);
     if (r == QAA_OK) r = upload(chunk_inst, &d_chunks, s);
-    if (r != QAA_OK) return r;
+    if (r != QAA_OK) {
+        release();
+        return r;
+    }
     std::map<int, int> active;
     for (auto &kv : groups) active[kv.first] = (int)kv.second.order.size();
     for (int64_t k = 0; k < maxN; ++k) {
@@ -1115,15 +1128,14 @@ qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states
             for (int j = 0; j < jn; ++j) {
                 hipError_t e = launch_batch_pass(d_insts + g.inst_base, d_chunks + g.chunk_base, g.chunk_prefix[a],
                                                  d_structs, k, j, kBatchChunkTiles, dty, ety, TB, RB, s);
-                if (e != hipSuccess)
+                if (e != hipSuccess) {
+                    release();
                     return fail(QAA_ERR_DEVICE, "batched pass launch failed: %s", hipGetErrorString(e));
+                }
             }
         }
     }
-    QAA_HIP(hipFreeAsync(d_insts, s));
-    QAA_HIP(hipFreeAsync(d_structs, s));
-    QAA_HIP(hipFreeAsync(d_chunks, s));
-    if (acc) QAA_HIP(hipFreeAsync(acc, s));
+    release();
     return QAA_OK;
 }
 
@@ -1159,26 +1171,49 @@ extern "C" qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, c
         else
             large[dt][et].push_back(i);
     }
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    QAA_HIP(hipEventRecord(ctx->ev_fork, s));
-    QAA_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
-    for (int dt = 0; dt < 2; ++dt)
-        for (int et = 0; et < 2; ++et) {
-            if (small[dt][et].empty()) continue;
-            ResidentDesc *d = nullptr;
-            r = upload(small[dt][et], &d, ctx->side);
-            if (r != QAA_OK) return r;
-            QAA_HIP(launch_resident(d, nullptr, (int)small[dt][et].size(), dt, et, ctx->side));
-            QAA_HIP(hipFreeAsync(d, ctx->side));
-        }
-    for (int dt = 0; dt < 2; ++dt)
-        for (int et = 0; et < 2; ++et) {
-            r = run_batch_passes(large[dt][et], states, T, steps, s);
-            if (r != QAA_OK) return r;
-        }
-    QAA_HIP(hipEventRecord(ctx->ev_join, ctx->side));
-    QAA_HIP(hipStreamWaitEvent(s, ctx->ev_join, 0));
-    return ok();
+    // The small states go to the device's side stream, forked from and
+    // joined back into the caller's stream with events of this call; the
+    // lock covers only the enqueueing on the shared side stream.
+    hipEvent_t fork = nullptr, join = nullptr;
+    QAA_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    hipError_t he = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(fork);
+        return fail(QAA_ERR_DEVICE, "qaa_evolve_batch: event creation failed: %s", hipGetErrorString(he));
+    }
+    auto done = [&](qaa_status st) {
+        (void)hipEventDestroy(fork);
+        (void)hipEventDestroy(join);
+        return st;
+    };
+    bool joined = false;      // join recorded on the side stream
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        he = hipEventRecord(fork, s);
+        if (he == hipSuccess) he = hipStreamWaitEvent(ctx->side, fork, 0);
+        if (he != hipSuccess)
+            return done(fail(QAA_ERR_DEVICE, "qaa_evolve_batch: fork failed: %s", hipGetErrorString(he)));
+        for (int dt = 0; dt < 2 && he == hipSuccess && r == QAA_OK; ++dt)
+            for (int et = 0; et < 2 && he == hipSuccess && r == QAA_OK; ++et) {
+                if (small[dt][et].empty()) continue;
+                ResidentDesc *d = nullptr;
+                r = upload(small[dt][et], &d, ctx->side);
+                if (r != QAA_OK) break;
+                he = launch_resident(d, nullptr, (int)small[dt][et].size(), dt, et, ctx->side);
+                (void)hipFreeAsync(d, ctx->side);
+            }
+        joined = hipEventRecord(join, ctx->side) == hipSuccess;
+    }
+    if (r == QAA_OK && he != hipSuccess)
+        r = fail(QAA_ERR_DEVICE, "qaa_evolve_batch: resident launch failed: %s", hipGetErrorString(he));
+    for (int dt = 0; dt < 2 && r == QAA_OK; ++dt)
+        for (int et = 0; et < 2 && r == QAA_OK; ++et) r = run_batch_passes(large[dt][et], states, T, steps, s);
+    // the caller's stream waits for the side stream's work of this call on
+    // every path, so none of it outlives the caller's stream unordered
+    he = joined ? hipStreamWaitEvent(s, join, 0) : hipErrorUnknown;
+    if (r != QAA_OK) return done(r);
+    if (he != hipSuccess) return done(fail(QAA_ERR_DEVICE, "qaa_evolve_batch: join failed"));
+    return done(ok());
 }
 
 // ---------------------------------------------------------------------------
