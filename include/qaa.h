@@ -238,7 +238,8 @@ qaa_status qaa_server_create(const qaa_server_config *cfg, qaa_server **out);
 qaa_status qaa_server_submit(qaa_server *sv, int32_t n, int32_t m, const int32_t *lits, double T,
                              int64_t steps, int64_t *ticket);
 
-/* Non-blocking status of a ticket. */
+/* Non-blocking status of a ticket.  A finished request's record (its
+ * status, observables and times, about 100 bytes) is kept until destroy. */
 qaa_status qaa_server_poll(qaa_server *sv, int64_t ticket, qaa_server_result *out);
 
 /* Block until the ticket's solve has finished, then fill *out. */

@@ -139,6 +139,7 @@ void worker_main(qaa_server *sv)
         done.obs = work.obs;
         done.t_done = now_s();
         done.state = st == QAA_OK ? 2 : 3;
+        std::vector<int32_t>().swap(done.lits);    // finished records keep only their results
         sv->in_use -= done.footprint;
         sv->cv_work.notify_all();
         sv->cv_done.notify_all();
