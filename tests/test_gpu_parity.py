@@ -280,6 +280,17 @@ def test_plan_choices_vs_oracle(qaa, choice):
     _compare(st, obs, psi, ref, L2_TOL_C64, P_TOL_C64)
 
 
+def test_cache_blocked_schedule_vs_oracle(qaa, monkeypatch):
+    """The cache-blocking switch (passes between two top-set passes run group
+    by group over the top index bits) on the GPU: same result."""
+    monkeypatch.setenv("QAA_CHUNK_LOG2_BYTES", "22")
+    n, T, N = 23, 4.0, 5
+    inst_in = planted_unique_3sat(n, 41)
+    psi, ref = _oracle_run(n, inst_in.clauses, T, N)
+    _, _, st, obs = _run_gpu(qaa, n, inst_in.clauses, T, N)
+    _compare(st, obs, psi, ref, L2_TOL_C64, P_TOL_C64)
+
+
 def test_autotune_records_a_choice(qaa):
     n = 23
     inst_in = planted_unique_3sat(n, 5)
