@@ -17,6 +17,12 @@ Also reported on the same JSON line:
   roofline     -- HBM roofline of the dominant kernel (the fused pass):
                   algorithmic bytes per launch / event-measured launch time.
   cpu_baseline -- the CPU oracle timed on a bounded sample of the same job.
+  batch        -- 512 planted instances (n ~ U{12..22}, T ~ U[10,100)) in one
+                  qaa_evolve_batch call: solves/s and amplitude-steps/s, against
+                  one qaa_evolve call per instance on a sample.
+  serving      -- Poisson request streams through the request server: p50/p99
+                  latency and solves/s per arrival rate.
+(--no-extras skips the last two; they run after the timed region.)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -187,12 +193,13 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 2 GiB device copy (torch copy_), the reference dispatch for "
                          "scaling HBM counter readings")
-    ap.add_argument("--batch", type=int, default=0, metavar="COUNT",
-                    help="also run the batched workload with COUNT instances (512 is the full one)")
+    ap.add_argument("--batch", type=int, default=512, metavar="COUNT",
+                    help="batched workload size (512 is the full one; 0 skips it)")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and serving workloads")
     ap.add_argument("--batch-loop-sample", type=int, default=64)
-    ap.add_argument("--serve", type=str, default="", metavar="RATES",
-                    help="also run open-loop serving at these comma-separated arrival rates (requests/s)")
-    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve", type=str, default="4,8", metavar="RATES",
+                    help="open-loop serving at these comma-separated arrival rates (requests/s); '' skips it")
+    ap.add_argument("--serve-requests", type=int, default=60)
     ap.add_argument("--serve-n", type=str, default="16,24", help="n range lo,hi of served requests")
     ap.add_argument("--serve-t", type=str, default="10,50", help="T range lo,hi of served requests")
     ap.add_argument("--serve-slots", type=int, default=8)
@@ -297,6 +304,8 @@ def main():
         cpu = cpu_baseline(inst_in, n, T, N, args.cpu_sample_steps)
 
     extras = {}
+    if args.no_extras:
+        args.batch, args.serve = 0, ""
     if args.precision:
         log("precision study: complex128 run of the same %d steps" % K)
         ref = torch.empty(1 << n, dtype=torch.complex128, device=dev)
