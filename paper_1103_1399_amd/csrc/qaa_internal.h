@@ -47,7 +47,9 @@ struct ClauseRec {
 //      coefficient set B.
 // A rotation is the single-qubit factor of exp(-i theta H_B) without its
 // global phase: [[c, i s], [i s, c]], c = cos(theta/2), s = sin(theta/2),
-// given as cm1 = c - 1 = -2 sin^2(theta/4) (accurate for small theta) and s.
+// applied in place as three shears, given as t = tan(theta/4) and s (the
+// host reduces theta/2 to [-pi/2, pi/2]; the sign flip of the reduction
+// goes into the global phase).
 // The global phase exp(-i n theta / 2) of each step is folded into gphase.
 // The kernel reads the per-residency tables as whole 32-bit words so that
 // they come through the scalar cache (a sub-word load at a run-time index
