@@ -14,7 +14,8 @@ of the paper it follows:
                       (i-1) of z (basis order |q_n ... q_1> of Sec. 2.1).
 * init_uniform     -- Sec. 2.1: uniform superposition, the ground state of
                       H_B = sum_i (1 - sigma^x_i)/2.
-* evolve           -- eq. 1 of Sec. 2.1, H(s) = (1-s) H_B + s H_P with s = t/T,
+* evolve           -- eq. 1 of Sec. 2.1, H(s) = (1-s) H_B + s H_P with s = t/T
+                      (or s(t/T) from a piecewise-linear schedule table),
                       integrated by N second-order (Strang) steps with the
                       schedule evaluated at step midpoints (the paper is silent
                       on the integrator; this reading is the documented one).
@@ -69,7 +70,7 @@ def _load():
             lib.oracle_init_uniform.argtypes = [ctypes.c_int, f64p]
             lib.oracle_init_uniform.restype = None
             lib.oracle_evolve.argtypes = [ctypes.c_int, ctypes.c_int, i32p, f64p, ctypes.c_double,
-                                          ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
+                                          ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, f64p, ctypes.c_int]
             lib.oracle_evolve.restype = ctypes.c_int
             lib.oracle_observables.argtypes = [ctypes.c_int, ctypes.c_int, i32p, f64p, f64p, i32p, i64p]
             lib.oracle_observables.restype = ctypes.c_int
@@ -121,18 +122,23 @@ def init_uniform(n: int) -> np.ndarray:
     return psi
 
 
-def evolve(n: int, clauses, psi: np.ndarray, T: float, N: int, k0: int = 0, k1: int | None = None) -> np.ndarray:
+def evolve(n: int, clauses, psi: np.ndarray, T: float, N: int, k0: int = 0, k1: int | None = None,
+           knots=None) -> np.ndarray:
     """Apply steps k0 .. k1-1 of the N-step second-order evolution (in place).
 
-    psi must be a C-contiguous complex128 array of length 2^n.
+    psi must be a C-contiguous complex128 array of length 2^n.  knots: None
+    (linear schedule s = t/T) or the values of s at u = j/(len - 1).
     """
     if k1 is None:
         k1 = N
     if psi.dtype != np.complex128 or not psi.flags.c_contiguous or psi.shape != (1 << n,):
         raise ValueError("psi must be contiguous complex128 of length 2^n")
     lits = _lits(clauses)
+    kn = np.ascontiguousarray(np.asarray([] if knots is None else knots, dtype=np.float64))
+    kn_ptr = _ptr(kn, ctypes.c_double) if kn.size else None
     rc = _load().oracle_evolve(n, lits.shape[0], _ptr(lits, ctypes.c_int32),
-                               _ptr(psi.view(np.float64), ctypes.c_double), float(T), int(N), int(k0), int(k1))
+                               _ptr(psi.view(np.float64), ctypes.c_double), float(T), int(N), int(k0), int(k1),
+                               kn_ptr, int(kn.size))
     if rc != 0:
         raise ValueError("oracle_evolve: bad arguments")
     return psi

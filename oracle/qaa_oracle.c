@@ -19,12 +19,15 @@
  *    proportionality constant is taken as 1; duplicated clauses count once
  *    per copy).
  *  - Interpolation (Sec. 2.1, eq. 1): H(s) = (1-s) H_B + s H_P, s = t/T.
+ *    The paper asks only that s go from 0 to 1 slowly enough; besides its
+ *    linear s(u) = u (u = t/T) the oracle takes a schedule table: s(u)
+ *    piecewise linear through the points (j/(count-1), knots[j]).
  *  - Initial Hamiltonian: H_B = sum_i (1 - sigma^x_i)/2, whose ground state is
  *    the uniform superposition of Sec. 2.1 (eigenvalue 0).
  *
  * Integrator (the paper does not state one): N second-order (Strang) steps
  * of size dt = T/N.  Step k (k = 0..N-1) evaluates the schedule at the step
- * midpoint s_k = (k + 1/2)/N and applies, in time order,
+ * midpoint, s_k = s(u_k) with u_k = (k + 1/2)/N, and applies, in time order,
  *      exp(-i (dt/2) s_k H_P)  exp(-i dt (1-s_k) H_B)  exp(-i (dt/2) s_k H_P).
  * exp(-i theta H_B) factorises over qubits into 2x2 blocks
  *      exp(-i theta (1 - sigma^x)/2) = [[alpha, beta], [beta, alpha]],
@@ -131,14 +134,35 @@ void oracle_init_uniform(int n, double *psi_ri)
 }
 
 /*
+ * The schedule s(u), u = t/T in [0, 1]: u itself when count == 0, else the
+ * straight line between the two knots whose abscissae j h, (j+1) h
+ * (h = 1/(count-1)) enclose u.
+ */
+static double schedule_value(double u, const double *knots, int count)
+{
+    if (count == 0) return u;
+    const double h = 1.0 / (double)(count - 1);
+    int j = (int)floor(u / h);
+    if (j > count - 2) j = count - 2;
+    if (j < 0) j = 0;
+    const double w = (u - (double)j * h) / h;     /* 0 <= w <= 1 inside the segment */
+    return (1.0 - w) * knots[j] + w * knots[j + 1];
+}
+
+/*
  * Steps k0 .. k1-1 of the N-step second-order evolution over total time T.
  * psi_ri: 2^n complex128 amplitudes, interleaved (re, im), updated in place.
+ * knots/count: the schedule table (count == 0: linear schedule; else
+ * 2 <= count and knots[0..count) in [0, 1]).
  * Returns 0, or -1 on bad arguments.
  */
 int oracle_evolve(int n, int m, const int32_t *lits, double *psi_ri,
-                  double T, int64_t N, int64_t k0, int64_t k1)
+                  double T, int64_t N, int64_t k0, int64_t k1, const double *knots, int count)
 {
     if (n < 1 || n > 34 || m < 0 || N < 0 || k0 < 0 || k1 < k0 || k1 > N) return -1;
+    if (count != 0 && (count < 2 || !knots)) return -1;
+    for (int j = 0; j < count; ++j)
+        if (!(knots[j] >= 0.0 && knots[j] <= 1.0)) return -1;
     if (N == 0 || k0 == k1) return 0;
     const int64_t dim = (int64_t)1 << n;
     int32_t *E = (int32_t *)malloc(sizeof(int32_t) * (size_t)dim);
@@ -147,7 +171,7 @@ int oracle_evolve(int n, int m, const int32_t *lits, double *psi_ri,
     cplx *psi = (cplx *)psi_ri;
     const double dt = T / (double)N;
     for (int64_t k = k0; k < k1; ++k) {
-        const double s = ((double)k + 0.5) / (double)N;
+        const double s = schedule_value(((double)k + 0.5) / (double)N, knots, count);
         apply_problem_phase(psi, E, dim, 0.5 * dt * s);
         apply_driver(psi, n, dt * (1.0 - s));
         apply_problem_phase(psi, E, dim, 0.5 * dt * s);

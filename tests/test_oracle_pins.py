@@ -290,3 +290,129 @@ def test_slow_sweep_reaches_the_solution(worked_example):
     oracle.evolve(n, cl, fast, T=1.0, N=100)
     assert obs["p_success"] > 0.9
     assert oracle.observables(n, cl, fast)["p_success"] < obs["p_success"]
+
+
+# --------------------------------------------------------------------------
+# Schedule tables: s(u) piecewise linear through equally spaced knots
+# (u = t/T).  The paper's schedule is s = u (Sec. 2.1, eq. 1); the table
+# is checked against numpy's own piecewise-linear interpolation, dense
+# exponentials, exact decompositions and closed forms.
+# --------------------------------------------------------------------------
+
+def _dense_step_at(n, E, dt, s):
+    """expm(-i dt/2 s H_P) expm(-i dt (1-s) H_B) expm(-i dt/2 s H_P)."""
+    hp = np.diag(E.astype(np.float64))
+    half = expm(-1j * (dt / 2.0) * s * hp)
+    return half @ expm(-1j * dt * (1.0 - s) * oracle.dense_h_b(n)) @ half
+
+
+def test_two_knot_table_is_the_linear_schedule():
+    n = 7
+    inst = planted_unique_3sat(n, 31)
+    a = oracle.init_uniform(n)
+    b = oracle.init_uniform(n)
+    oracle.evolve(n, inst.clauses, a, T=6.0, N=40)
+    oracle.evolve(n, inst.clauses, b, T=6.0, N=40, knots=[0.0, 1.0])
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("count", [3, 5, 33, 256])
+def test_knots_on_the_line_give_the_linear_schedule(count):
+    """Interpolating knots that lie on s = u reproduces s = u."""
+    n = 7
+    inst = planted_unique_3sat(n, 32)
+    a = oracle.init_uniform(n)
+    b = oracle.init_uniform(n)
+    oracle.evolve(n, inst.clauses, a, T=6.0, N=45)
+    oracle.evolve(n, inst.clauses, b, T=6.0, N=45, knots=np.linspace(0.0, 1.0, count))
+    assert np.max(np.abs(a - b)) < 1e-13
+
+
+@pytest.mark.parametrize("knots", [[0.0, 0.9, 0.2, 1.0], [0.3, 0.3], list(np.linspace(0, 1, 11) ** 2)])
+def test_table_steps_match_dense_expm_with_numpy_interp(knots):
+    """Every step equals the dense Strang product at s = numpy.interp(u_k)."""
+    n, N, T = 6, 13, 8.0
+    inst = planted_unique_3sat(n, 33)
+    E = oracle.energy(n, inst.clauses)
+    grid = np.linspace(0.0, 1.0, len(knots))
+    rng = np.random.default_rng(34)
+    psi = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    psi /= np.linalg.norm(psi)
+    for k in range(N):
+        s = float(np.interp((k + 0.5) / N, grid, knots))
+        expect = _dense_step_at(n, E, T / N, s) @ psi
+        got = psi.copy()
+        oracle.evolve(n, inst.clauses, got, T=T, N=N, k0=k, k1=k + 1, knots=knots)
+        assert np.max(np.abs(got - expect)) < 1e-13, k
+        psi = expect
+
+
+def test_ramp_table_decomposes_into_driver_linear_sweep_and_phase():
+    """Knots {0, 0, 1, 1} with N = 3q: the first third has s = 0 (pure
+    driver, exp(-i T/3 H_B) exactly), the middle third is the linear sweep
+    over time T/3 in q steps, the last third has s = 1 (pure phase
+    exp(-i T/3 H_P) exactly).  From a basis state the driver part is the
+    closed form a^{n-d} b^d."""
+    n, q, T, z0 = 6, 11, 9.0, 0b101101
+    inst = planted_unique_3sat(n, 35)
+    E = oracle.energy(n, inst.clauses)
+    th = T / 3.0
+    a = (1 + np.exp(-1j * th)) / 2
+    b = (1 - np.exp(-1j * th)) / 2
+    d = np.array([bin(z ^ z0).count("1") for z in range(1 << n)])
+    expect = a ** (n - d) * b ** d
+    oracle.evolve(n, inst.clauses, expect, T=T / 3.0, N=q)
+    expect = expect * np.exp(-1j * th * E)
+    got = _basis(n, z0)
+    oracle.evolve(n, inst.clauses, got, T=T, N=3 * q, knots=[0.0, 0.0, 1.0, 1.0])
+    assert np.max(np.abs(got - expect)) < 1e-13
+
+
+@pytest.mark.parametrize("knots", [[0.0, 0.8, 1.0], [0.1, 0.6, 0.2, 0.9, 1.0]])
+def test_table_driver_only_closed_form(knots):
+    """m = 0 from |z0>: the driver angles add up to Theta = sum_k dt (1 - s_k).
+    With N a multiple of the segment count, the midpoints of each segment are
+    placed symmetrically in it, so the sum of s over them is exact:
+    Theta = T (1 - mean over segments of (v_j + v_{j+1})/2)."""
+    n, z0, T = 5, 0b01101, 3.3
+    segs = len(knots) - 1
+    N = 7 * segs
+    v = np.asarray(knots)
+    th = T * (1.0 - np.mean((v[:-1] + v[1:]) / 2.0))
+    a = (1 + np.exp(-1j * th)) / 2
+    b = (1 - np.exp(-1j * th)) / 2
+    d = np.array([bin(z ^ z0).count("1") for z in range(1 << n)])
+    psi = _basis(n, z0)
+    oracle.evolve(n, np.zeros((0, 3), np.int32), psi, T=T, N=N, knots=knots)
+    assert np.max(np.abs(psi - a ** (n - d) * b ** d)) < 1e-13
+
+
+def test_table_second_order_convergence():
+    """With steps that never straddle a knot, a table schedule keeps the
+    dt^2 global error (reference: fine exponential-midpoint substeps of
+    H(s(t)) with s from numpy.interp)."""
+    n = 5
+    inst = planted_unique_3sat(n, 36)
+    E = oracle.energy(n, inst.clauses)
+    knots = [0.0, 0.5, 0.6, 0.7, 1.0]
+    grid = np.linspace(0.0, 1.0, len(knots))
+    T, nsub = 4.0, 4096
+    hb, hp = oracle.dense_h_b(n), np.diag(E.astype(float))
+    ref = np.full(1 << n, 2 ** (-n / 2), dtype=np.complex128)
+    for j in range(nsub):
+        s = float(np.interp((j + 0.5) / nsub, grid, knots))
+        ref = expm(-1j * (T / nsub) * ((1 - s) * hb + s * hp)) @ ref
+    errs = []
+    for N in (8, 16, 32):
+        psi = oracle.init_uniform(n)
+        oracle.evolve(n, inst.clauses, psi, T=T, N=N, knots=knots)
+        errs.append(np.linalg.norm(psi - ref))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.5 < r1 < 4.6 and 3.5 < r2 < 4.6, (errs, r1, r2)
+
+
+@pytest.mark.parametrize("knots", [[0.5], [0.0, 1.2], [0.0, float("nan"), 1.0]])
+def test_oracle_rejects_bad_tables(knots):
+    psi = oracle.init_uniform(4)
+    with pytest.raises(ValueError):
+        oracle.evolve(4, [[1, 2, 3]], psi, T=1.0, N=3, knots=knots)
