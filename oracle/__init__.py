@@ -22,6 +22,10 @@ of the paper it follows:
 * observables      -- norm, <H_P>, and the success probability: the weight on
                       the ground manifold of H_P (Sec. 2.1), i.e. on all z with
                       E(z) = E_min.
+* levels           -- the lowest distinct eigenvalues of H(s) = (1-s) H_B + s H_P
+                      (eq. 1): the spectrum whose lowest gap sets how slowly
+                      the sweep must go (Sec. 2.1).  Dense ``eigvalsh`` for
+                      n <= 11, else scipy ``eigsh`` on a matrix-free H(s).
 * dense_h_b / dense_strang_step -- small-n dense matrices used only to pin
                       the oracle (scipy ``expm``).
 """
@@ -193,3 +197,51 @@ def dense_strang_step(n: int, e_diag: np.ndarray, T: float, N: int, k: int) -> n
     half = expm(-1j * (dt / 2.0) * s * hp)
     drive = expm(-1j * dt * (1.0 - s) * dense_h_b(n))
     return half @ drive @ half
+
+
+def _flip(x: np.ndarray, q: int) -> np.ndarray:
+    """x(z xor 2^q) for all z: swap the halves of every block of 2^(q+1)."""
+    return x.reshape(-1, 2, 1 << q)[:, ::-1, :].reshape(-1)
+
+
+def levels(n: int, clauses, s: float, k: int, merge: float = 1e-8) -> np.ndarray:
+    """The k lowest distinct eigenvalues of H(s) = (1-s) H_B + s H_P (eq. 1).
+
+    Eigenvalues closer than `merge` count as one level.  n <= 11: dense
+    matrix (H_B from Kronecker products) and numpy ``eigvalsh``, any s and
+    any clause list.  Larger n: scipy ``eigsh`` (ARPACK) with H(s) applied
+    matrix-free, (H x)(z) = ((1-s) n/2 + s E(z)) x(z) - (1-s)/2 sum_q x(z xor 2^q),
+    for 0 < s < 1 and at least one clause only: at s = 0, s = 1 or without
+    clauses the start vector's Krylov space has only as many dimensions as
+    H(s) has levels (n + 1, or the number of distinct energies), which
+    ARPACK's restarted iteration does not handle (those cases have closed
+    forms instead).
+    """
+    E = energy(n, clauses).astype(np.float64)
+    if n <= 11:
+        h = (1.0 - s) * dense_h_b(n) + s * np.diag(E)
+        w = np.linalg.eigvalsh(h)
+    else:
+        if not (0.0 < s < 1.0) or len(_lits(clauses)) == 0:
+            raise ValueError("levels: n > 11 needs 0 < s < 1 and at least one clause")
+        from scipy.sparse.linalg import LinearOperator, eigsh
+        dim = 1 << n
+        diag = (1.0 - s) * 0.5 * n + s * E
+
+        def mv(x):
+            x = np.asarray(x, dtype=np.float64).reshape(-1)
+            y = diag * x
+            for q in range(n):
+                y -= 0.5 * (1.0 - s) * _flip(x, q)
+            return y
+
+        op = LinearOperator((dim, dim), matvec=mv, dtype=np.float64)
+        start = np.cos(np.arange(dim) * 0.7071) + 1.5      # fixed, not an eigenvector
+        w = np.sort(eigsh(op, k=k + 2, which="SA", tol=1e-14, v0=start, return_eigenvectors=False))
+    out = []
+    for x in w:
+        if not out or x - out[-1] > merge:
+            out.append(float(x))
+        if len(out) == k:
+            break
+    return np.asarray(out)

@@ -416,3 +416,84 @@ def test_oracle_rejects_bad_tables(knots):
     psi = oracle.init_uniform(4)
     with pytest.raises(ValueError):
         oracle.evolve(4, [[1, 2, 3]], psi, T=1.0, N=3, knots=knots)
+
+
+# --------------------------------------------------------------------------
+# Spectrum of H(s) (eq. 1): closed forms at the ends, the two independent
+# constructions (dense Kronecker products / matrix-free flips) against each
+# other, variational bounds and first-order perturbation theory.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [6, 11])
+def test_levels_at_s0_are_the_driver_spectrum(n):
+    """H(0) = H_B has levels 0, 1, 2, ... (Hamming weight of the X basis)."""
+    inst = planted_unique_3sat(n, 41)
+    assert np.allclose(oracle.levels(n, inst.clauses, 0.0, 3), [0.0, 1.0, 2.0], atol=1e-9)
+
+
+@pytest.mark.parametrize("n", [7, 11])
+def test_levels_at_s1_are_the_sorted_energies(n):
+    inst = planted_unique_3sat(n, 42)
+    E = np.unique(oracle.energy(n, inst.clauses))
+    assert np.allclose(oracle.levels(n, inst.clauses, 1.0, 3), E[:3], atol=1e-9)
+
+
+@pytest.mark.parametrize("n,s", [(6, 0.3), (10, 0.55)])
+def test_levels_without_clauses_scale_with_one_minus_s(n, s):
+    assert np.allclose(oracle.levels(n, np.zeros((0, 3), np.int32), s, 3), (1 - s) * np.arange(3), atol=1e-9)
+
+
+def test_dense_and_matrix_free_levels_agree():
+    """The dense construction (n <= 11) against ARPACK on the matrix-free
+    flips written out again here, at n = 11."""
+    from scipy.sparse.linalg import LinearOperator, eigsh
+    n = 11
+    inst = planted_unique_3sat(n, 43)
+    for s in (0.2, 0.5, 0.8):
+        dense = oracle.levels(n, inst.clauses, s, 3)
+        E = oracle.energy(n, inst.clauses).astype(float)
+        diag = (1 - s) * n / 2 + s * E
+        op = LinearOperator((1 << n, 1 << n), dtype=float,
+                            matvec=lambda x: diag * x.ravel() - 0.5 * (1 - s) * sum(
+                                oracle._flip(x.ravel(), q) for q in range(n)))
+        w = np.sort(eigsh(op, k=3, which="SA", tol=1e-13, return_eigenvectors=False))
+        assert np.allclose(dense, w, atol=1e-9)
+
+
+@pytest.mark.parametrize("n", [10, 13])
+def test_ground_level_bounds(n):
+    """0 < E0(s) < <uniform|H(s)|uniform> = s m/8 for 0 < s < 1: both terms are
+    positive semidefinite with different kernels (uniform state, planted z*),
+    and the uniform state is a trial vector."""
+    inst = planted_unique_3sat(n, 44)
+    for s in (0.1, 0.4, 0.7, 0.95):
+        e0 = oracle.levels(n, inst.clauses, s, 1)[0]
+        assert 0.0 < e0 < s * inst.m / 8.0
+
+
+def test_ground_level_first_order_at_both_ends():
+    """E0(h) = h m/8 + O(h^2) (perturbing the uniform ground state of H_B by
+    H_P - H_B) and E0(1-h) = h n/2 + O(h^2) (perturbing |z*> by H_B - H_P)."""
+    n, h = 9, 1e-5
+    inst = planted_unique_3sat(n, 45)
+    assert abs(oracle.levels(n, inst.clauses, h, 1)[0] / h - inst.m / 8.0) < 1e-2 * inst.m / 8.0
+    assert abs(oracle.levels(n, inst.clauses, 1 - h, 1)[0] / h - n / 2.0) < 1e-2 * n / 2.0
+
+
+@pytest.mark.parametrize("s", [0.3, 0.6])
+def test_matrix_free_levels_continue_the_dense_ones(s):
+    """n = 12 (ARPACK path) against dense eigvalsh of the same matrix."""
+    n = 12
+    inst = planted_unique_3sat(n, 46)
+    E = oracle.energy(n, inst.clauses).astype(float)
+    w = np.linalg.eigvalsh((1 - s) * oracle.dense_h_b(n) + s * np.diag(E))
+    assert np.allclose(oracle.levels(n, inst.clauses, s, 3), w[:3], atol=1e-9)
+
+
+def test_matrix_free_levels_refuse_degenerate_cases():
+    inst = planted_unique_3sat(12, 47)
+    for s in (0.0, 1.0):
+        with pytest.raises(ValueError):
+            oracle.levels(12, inst.clauses, s, 2)
+    with pytest.raises(ValueError):
+        oracle.levels(12, np.zeros((0, 3), np.int32), 0.5, 2)
