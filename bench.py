@@ -44,8 +44,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
 # WRITE_SIZE runs, scaled by the same counters' reading for a plain copy of
 # known size).  Valid only for the kernel source it was taken on.
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "775dc9c5552bc44ad70dfcc2c8b1911c83e752c655e0af71dac79e730c1e1b06",
-    "bytes_per_launch": 4.521175e+09,
+    "kernel_source_sha256": "5106c482075e3fc5954c6e331de98997755271ed74ac46bb624c3dd6142ff444",
+    "bytes_per_launch": 4.521119e+09,
 }
 
 
@@ -59,7 +59,16 @@ def kernel_source_sha():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def cpu_baseline(inst, n, T, N, sample_steps):
+def schedule_table(count):
+    """None for the linear schedule, else `count` knots of
+    s(u) = u + 0.9 sin(2 pi u) / (2 pi) (monotone, slowest at u = 1/2)."""
+    if count == 0:
+        return None
+    u = [j / (count - 1) for j in range(count)]
+    return [min(1.0, max(0.0, x + 0.9 * math.sin(2 * math.pi * x) / (2 * math.pi))) for x in u]
+
+
+def cpu_baseline(inst, n, T, N, sample_steps, knots=None):
     """Oracle on the host cores: energy table once, then `sample_steps` steps;
     the per-step rate is extrapolated to the full N-step job."""
     import numpy as np  # noqa: F401
@@ -70,7 +79,7 @@ def cpu_baseline(inst, n, T, N, sample_steps):
     t_e = time.perf_counter() - t0
     psi = oracle.init_uniform(n)
     t0 = time.perf_counter()
-    oracle.evolve(n, inst.clauses, psi, T, N, 0, sample_steps)    # recomputes E inside
+    oracle.evolve(n, inst.clauses, psi, T, N, 0, sample_steps, knots=knots)    # recomputes E inside
     t_ev = time.perf_counter() - t0
     t_step = max(1e-9, (t_ev - t_e) / sample_steps)
     per_step_job = t_step + t_e / N
@@ -144,6 +153,30 @@ def run_batch(qaa, torch, count, seed, loop_sample):
     }
 
 
+def run_spectrum(qaa, torch, n, points, iters, seed):
+    """Lowest two levels of H(s) on an even grid of `points` values of s in
+    [0, 1] for one planted instance (qaa_spectrum, Lanczos on the device):
+    the minimum gap along the path and the time it takes."""
+    import numpy as np
+    from qaa_inputs import planted_unique_3sat
+    inst_in = planted_unique_3sat(n, seed)
+    inst = qaa.Instance(n, inst_in.literals())
+    table = inst.energy_table()
+    v0 = torch.from_numpy(np.random.default_rng(seed).standard_normal(1 << n)).cuda()
+    svals = [i / (points - 1) for i in range(points)]
+    inst.spectrum(table, svals[:1], v0, iters=min(iters, 20), k=2)     # warm-up (allocator, code objects)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev = inst.spectrum(table, svals, v0, iters=iters, k=2)
+    secs = time.perf_counter() - t0
+    gaps = ev[:, 1] - ev[:, 0]
+    i = int(np.argmin(gaps))
+    inst.close()
+    return {"n": n, "m": inst_in.m, "seed": seed, "points": points, "lanczos_steps": iters, "seconds": secs,
+            "ms_per_point": secs / points * 1e3, "lanczos_steps_per_s": points * iters / secs,
+            "min_gap": float(gaps[i]), "s_at_min_gap": svals[i], "e0_at_min_gap": float(ev[i, 0])}
+
+
 def run_serving(qaa, count, rates, n_lo, n_hi, t_lo, t_hi, slots, budget):
     """Open-loop serving: Poisson arrivals at each rate (requests/s), each a
     planted 3-SAT solve; reports latency percentiles and completed solves/s."""
@@ -187,6 +220,9 @@ def main():
     ap.add_argument("--n", type=int, default=28)
     ap.add_argument("--T", type=float, default=50.0, help="total evolution time of the schedule")
     ap.add_argument("--schedule-steps", type=int, default=5000, help="second-order steps of the whole schedule")
+    ap.add_argument("--schedule-knots", type=int, default=0, metavar="K",
+                    help="0: the linear schedule s = t/T; K >= 2: a K-knot schedule table sampling "
+                         "s(u) = u + 0.9 sin(2 pi u)/(2 pi), which slows the sweep around s = 1/2")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=2)
@@ -204,6 +240,9 @@ def main():
     ap.add_argument("--serve-t", type=str, default="10,50", help="T range lo,hi of served requests")
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--spectrum", type=str, default="20,21,150", metavar="N,POINTS,ITERS",
+                    help="lowest two levels of H(s) for an n-qubit instance on POINTS values of s with ITERS "
+                         "Lanczos steps each (qaa_spectrum); empty: skip")
     ap.add_argument("--autotune", action="store_true",
                     help="run the plan autotuner for this n before the timed region (qaa_autotune)")
     ap.add_argument("--precision", action="store_true",
@@ -221,6 +260,10 @@ def main():
     from qaa_inputs import planted_unique_3sat
 
     n, T, N = args.n, args.T, args.schedule_steps
+    if args.schedule_knots == 1 or args.schedule_knots > 256:
+        print("--schedule-knots must be 0 or in [2, 256]", file=sys.stderr)
+        sys.exit(2)
+    knots = schedule_table(args.schedule_knots)
     K, W = args.steps, args.warmup
     if not (1 <= K <= N) or not (0 <= W <= N):
         print("--steps must be in [1, %d] and --warmup in [0, %d]" % (N, N), file=sys.stderr)
@@ -256,7 +299,7 @@ def main():
         log("autotune: %s" % tuned)
     qaa.qaa_state_init_uniform(st)
     if W:
-        qaa.qaa_evolve_range(st, T, N, 0, W)
+        qaa.qaa_evolve_range(st, T, N, 0, W, knots=knots)
     qaa.qaa_observables(st)
     torch.cuda.synchronize()
     h.close()
@@ -270,7 +313,7 @@ def main():
     qaa.qaa_energy_table(h.handle, table, qaa.QAA_E_U8)
     st = qaa.make_state(h.handle, amp, table, qaa.QAA_E_U8)
     qaa.qaa_state_init_uniform(st)
-    qaa.qaa_evolve_range(st, T, N, 0, K)
+    qaa.qaa_evolve_range(st, T, N, 0, K, knots=knots)
     obs = qaa.qaa_observables(st)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -301,11 +344,11 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, %d steps sample)" % args.cpu_sample_steps)
-        cpu = cpu_baseline(inst_in, n, T, N, args.cpu_sample_steps)
+        cpu = cpu_baseline(inst_in, n, T, N, args.cpu_sample_steps, knots)
 
     extras = {}
     if args.no_extras:
-        args.batch, args.serve = 0, ""
+        args.batch, args.serve, args.spectrum = 0, "", ""
     if args.precision:
         log("precision study: complex128 run of the same %d steps" % K)
         ref = torch.empty(1 << n, dtype=torch.complex128, device=dev)
@@ -313,7 +356,7 @@ def main():
         qaa.qaa_energy_table(h2.handle, table, qaa.QAA_E_U8)
         st2 = qaa.make_state(h2.handle, ref, table, qaa.QAA_E_U8)
         qaa.qaa_state_init_uniform(st2)
-        qaa.qaa_evolve_range(st2, T, N, 0, K)
+        qaa.qaa_evolve_range(st2, T, N, 0, K, knots=knots)
         obs2 = qaa.qaa_observables(st2)
         l2 = float(torch.linalg.vector_norm(amp.to(torch.complex128) - ref).item())
         extras["precision"] = {
@@ -332,6 +375,12 @@ def main():
         log("batch: %.2f solves/s, %.3e amp-steps/s (loop %.3e)" % (
             extras["batch"]["solves_per_s"], extras["batch"]["amp_steps_per_s"],
             extras["batch"]["loop"]["amp_steps_per_s"]))
+    if args.spectrum:
+        sn, sp, si = (int(x) for x in args.spectrum.split(","))
+        log("spectrum: n=%d, %d values of s, %d Lanczos steps each" % (sn, sp, si))
+        extras["spectrum"] = run_spectrum(qaa, torch, sn, sp, si, 7)
+        log("spectrum: %.3f s, min gap %.4f at s=%.2f" % (extras["spectrum"]["seconds"], extras["spectrum"]["min_gap"],
+                                                       extras["spectrum"]["s_at_min_gap"]))
     if args.serve:
         rates = [float(x) for x in args.serve.split(",") if x]
         nlo, nhi = (int(x) for x in args.serve_n.split(","))
@@ -354,10 +403,12 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "planted unique-solution 3-SAT, n=%d qubits (m=%d clauses, seed %d), linear schedule "
+            "workload": "planted unique-solution 3-SAT, n=%d qubits (m=%d clauses, seed %d), %s schedule "
                         "T=%g with %d second-order steps, complex64 state + uint8 energy table, uniform start"
-                        % (n, inst_in.m, args.seed, T, N),
+                        % (n, inst_in.m, args.seed,
+                           "linear" if knots is None else "%d-knot table" % len(knots), T, N),
             "n": n, "m": inst_in.m, "T": T, "schedule_steps": N,
+            "schedule": "linear" if knots is None else {"knots": len(knots)},
             "plan": plan,
             "plan_choice": qaa.qaa_plan_get(n, qaa.QAA_C64),
         },

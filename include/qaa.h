@@ -9,8 +9,10 @@
  *                                                         (Sec. 4.3)
  *
  * with N second-order split steps: step k (0 <= k < N) evaluates the
- * schedule at the midpoint s_k = (k + 1/2)/N, dt = T/N, and applies
+ * schedule at the midpoint s_k = s((k + 1/2)/N), dt = T/N, and applies
  *     exp(-i dt/2 s_k H_P) exp(-i dt (1 - s_k) H_B) exp(-i dt/2 s_k H_P).
+ * The schedule s(u), u = t/T, is the paper's linear s = u or a
+ * caller-given piecewise-linear table (qaa_schedule).
  * The paper does not name its integrator; this splitting is the build's
  * reading and is what the test oracle computes.
  *
@@ -138,21 +140,45 @@ qaa_status qaa_state_init_basis(const qaa_state *st, uint64_t z0, void *stream);
  * Evolution.
  * ------------------------------------------------------------------- */
 
+/*
+ * The interpolation schedule s(u) of H(s), u = t/T in [0, 1].
+ *   QAA_SCHED_LINEAR: s(u) = u, the schedule of Sec. 2.1, eq. 1.
+ *   QAA_SCHED_TABLE : s(u) is the piecewise-linear interpolant of
+ *       count knots values[0..count) placed at u_j = j/(count - 1):
+ *       with x = u (count - 1), j = min(floor(x), count - 2),
+ *       s(u) = values[j] + (x - j) (values[j+1] - values[j]).
+ *       A table lets the evolution slow down where the gap of H(s) is
+ *       small (the paper only asks that s change slowly enough, Sec. 2.1);
+ *       {0, 1} is the linear schedule, to the bit.
+ *   count  : 2 <= count <= QAA_SCHED_MAX_KNOTS (TABLE only).
+ *   values : host array of count knots, each finite and in [0, 1]; read
+ *            during the call only (the library keeps its own copy).
+ * A NULL qaa_schedule pointer means QAA_SCHED_LINEAR.  Step k evaluates
+ * s at the step's midpoint u_k = (k + 1/2)/N.  QAA_ERR_INVALID_ARG for an
+ * unknown kind, a count out of range, a NULL values array or a knot
+ * outside [0, 1].
+ */
 typedef enum qaa_schedule_kind {
-    QAA_SCHED_LINEAR = 0       /* s = t/T (Sec. 2.1, eq. 1) */
+    QAA_SCHED_LINEAR = 0,
+    QAA_SCHED_TABLE = 1
 } qaa_schedule_kind;
+
+#define QAA_SCHED_MAX_KNOTS 256
 
 typedef struct qaa_schedule {
     int32_t kind;              /* qaa_schedule_kind */
+    int32_t count;             /* TABLE: number of knots */
+    const double *values;      /* TABLE: knot values s(u_j) */
 } qaa_schedule;
 
 /*
  * Apply all `steps` second-order steps of total time T to st->amp in place
  * (equivalent to qaa_evolve_range with k0 = 0, k1 = steps).
- *   sched : NULL or {QAA_SCHED_LINEAR}.
+ *   sched : NULL (linear) or a qaa_schedule as described above.
  * steps == 0 is a no-op.  QAA_ERR_INVALID_ARG for T < 0, steps < 0, a NaN
- * T, or a state without amp/table/inst.  QAA_ERR_UNSUPPORTED if the
- * instance's E_max exceeds what the table type allows.  Asynchronous.
+ * T, a bad schedule, or a state without amp/table/inst.
+ * QAA_ERR_UNSUPPORTED if the instance's E_max exceeds what the table type
+ * allows.  Asynchronous.
  */
 qaa_status qaa_evolve(const qaa_state *st, const qaa_schedule *sched, double T,
                       int64_t steps, void *stream);
@@ -170,6 +196,8 @@ qaa_status qaa_evolve_range(const qaa_state *st, const qaa_schedule *sched, doub
 /*
  * Evolve `count` independent states together.  states[i], T[i] and
  * steps[i] (host arrays) as in qaa_evolve; the states may have different n.
+ * scheds: NULL (every state linear) or a host array of `count` schedules,
+ * scheds[i] for states[i], each as in qaa_evolve.
  * States whose whole vector fits one workgroup tile (n <= 13 for complex64,
  * 12 for complex128) run in one launch, one workgroup each; the others run
  * in lock step, one launch per pass covering every state still running,
@@ -179,8 +207,48 @@ qaa_status qaa_evolve_range(const qaa_state *st, const qaa_schedule *sched, doub
  * so for work already queued on the stream); the evolution itself is
  * asynchronous on the stream.
  */
-qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, const double *T,
-                            const int64_t *steps, void *stream);
+qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, const qaa_schedule *scheds,
+                            const double *T, const int64_t *steps, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Spectrum of H(s).  How slowly the sweep must go is set by the gap
+ * between the two lowest levels of H(s) along the path (Sec. 2.1); this
+ * computes the lowest levels at given s.
+ * ------------------------------------------------------------------- */
+
+#define QAA_SPECTRUM_MAX_ITERS 1024
+
+/*
+ * The k lowest eigenvalues of H(s) = (1 - s) H_B + s H_P at each of `count`
+ * values of s, by Lanczos with full reorthogonalisation (two classical
+ * Gram-Schmidt sweeps per step) in FP64 on the device; the Ritz values of
+ * the tridiagonal matrix come from Sturm-sequence bisection on the host.
+ *   inst, table, etype : an instance and its energy table (qaa_energy_table
+ *                        must have run for it; table is device memory)
+ *   s_values           : host array of count values, each in [0, 1]
+ *   v0                 : device array of 2^n doubles, the start vector (not
+ *                        modified).  A random vector reaches every level
+ *                        with probability 1; a level whose eigenvectors
+ *                        are orthogonal to v0 is never seen.
+ *   iters              : Lanczos steps, 1 <= iters <= QAA_SPECTRUM_MAX_ITERS
+ *                        (at most 2^n are taken)
+ *   k                  : values per s, 1 <= k <= iters
+ *   evals              : host array [count][k]: row i holds the k lowest
+ *                        levels (distinct eigenvalues) at s_values[i],
+ *                        ascending: Ritz values closer than 1e-10 of the
+ *                        matrix scale (max_j |alpha_j| + 2 beta_j, about
+ *                        the spectral radius) count as one level.  NaN
+ *                        where the run found fewer than k levels.
+ * The accuracy of the Ritz values grows with iters (the lowest converge
+ * first).  SYNCHRONOUS.  Takes about (iters + 2) * 2^n * 8 bytes of device
+ * memory from the stream-ordered allocator for the call:
+ * QAA_ERR_OUT_OF_MEMORY if that fails.  QAA_ERR_INVALID_ARG for bad
+ * arguments or a zero / non-finite v0 (detected after the run);
+ * QAA_ERR_NOT_READY if the instance has no energy table yet.
+ */
+qaa_status qaa_spectrum(const qaa_instance *inst, const void *table, qaa_etype etype, int32_t count,
+                        const double *s_values, const double *v0, int32_t iters, int32_t k, double *evals,
+                        void *stream);
 
 /* ---------------------------------------------------------------------
  * Observables (Sec. 2.1: the result is read from the weight on the ground
@@ -305,16 +373,17 @@ qaa_status qaa_autotune(const qaa_state *scratch, int64_t steps, qaa_plan_choice
 
 /*
  * Diagnostic: the pass descriptors qaa_evolve_range would launch for an
- * n-qubit state (energies up to emax) over steps k0..k1-1 of `steps`.
+ * n-qubit state (energies up to emax) over steps k0..k1-1 of `steps`
+ * under schedule `sched` (NULL: linear).
  * Writes up to `capacity` descriptors of *desc_bytes bytes each into the
  * host buffer `out` (may be NULL to query the count) and the total number
  * into *count (0 when the whole state is one workgroup tile).  The record
  * layout is the library's internal pass descriptor and may change between
  * versions; it exists so that host-side tests can replay the index maps.
  */
-qaa_status qaa_debug_pass_descs(int32_t n, qaa_dtype dtype, int32_t emax, double T, int64_t steps,
-                                int64_t k0, int64_t k1, void *out, int32_t capacity, int32_t *count,
-                                int32_t *desc_bytes);
+qaa_status qaa_debug_pass_descs(int32_t n, qaa_dtype dtype, int32_t emax, const qaa_schedule *sched, double T,
+                                int64_t steps, int64_t k0, int64_t k1, void *out, int32_t capacity,
+                                int32_t *count, int32_t *desc_bytes);
 
 /* ---------------------------------------------------------------------
  * Kernel timing (tracing).

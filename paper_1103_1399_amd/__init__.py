@@ -48,6 +48,9 @@ QAA_C128 = 1
 QAA_E_U8 = 0
 QAA_E_U16 = 1
 QAA_SCHED_LINEAR = 0
+QAA_SCHED_TABLE = 1
+QAA_SCHED_MAX_KNOTS = 256
+QAA_SPECTRUM_MAX_ITERS = 1024
 QAA_MAX_QUBITS = 34
 
 
@@ -63,7 +66,22 @@ class qaa_state(ctypes.Structure):
 
 
 class qaa_schedule(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32)]
+    _fields_ = [("kind", ctypes.c_int32), ("count", ctypes.c_int32), ("values", ctypes.POINTER(ctypes.c_double))]
+
+
+def make_schedule(knots=None):
+    """A qaa_schedule for `knots` (None: the linear schedule s = t/T).
+
+    knots are the values of s at u = j/(len(knots) - 1), u = t/T; the
+    returned structure keeps the knot array alive as an attribute.
+    """
+    if knots is None:
+        return qaa_schedule(QAA_SCHED_LINEAR, 0, None)
+    vals = [float(v) for v in knots]
+    arr = (ctypes.c_double * max(1, len(vals)))(*vals)
+    sched = qaa_schedule(QAA_SCHED_TABLE, len(vals), ctypes.cast(arr, ctypes.POINTER(ctypes.c_double)))
+    sched._keep = arr
+    return sched
 
 
 class qaa_obs(ctypes.Structure):
@@ -101,11 +119,15 @@ _SIGS = {
                          ctypes.c_int64, _vp]),
     "qaa_evolve_range": (_st, [ctypes.POINTER(qaa_state), ctypes.POINTER(qaa_schedule), ctypes.c_double,
                                ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _vp]),
-    "qaa_evolve_batch": (_st, [ctypes.c_int32, ctypes.POINTER(qaa_state), _f64p, _i64p, _vp]),
+    "qaa_evolve_batch": (_st, [ctypes.c_int32, ctypes.POINTER(qaa_state), ctypes.POINTER(qaa_schedule), _f64p,
+                               _i64p, _vp]),
     "qaa_observables": (_st, [ctypes.POINTER(qaa_state), ctypes.POINTER(qaa_obs), _vp]),
+    "qaa_spectrum": (_st, [_vp, _vp, ctypes.c_int, ctypes.c_int32, _f64p, _vp, ctypes.c_int32, ctypes.c_int32,
+                           _f64p, _vp]),
     "qaa_plan_info": (_st, [ctypes.c_int32, ctypes.c_int, _i32p, _i32p, _i32p]),
-    "qaa_debug_pass_descs": (_st, [ctypes.c_int32, ctypes.c_int, ctypes.c_int32, ctypes.c_double, ctypes.c_int64,
-                                   ctypes.c_int64, ctypes.c_int64, _vp, ctypes.c_int32, _i32p, _i32p]),
+    "qaa_debug_pass_descs": (_st, [ctypes.c_int32, ctypes.c_int, ctypes.c_int32, ctypes.POINTER(qaa_schedule),
+                                   ctypes.c_double, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _vp,
+                                   ctypes.c_int32, _i32p, _i32p]),
     "qaa_profile_enable": (_st, [ctypes.c_int32]),
     "qaa_profile_read": (_st, [ctypes.c_void_p, ctypes.c_int32]),
     "qaa_server_create": (_st, [ctypes.POINTER(qaa_server_config), ctypes.POINTER(_vp)]),
@@ -202,24 +224,33 @@ def qaa_state_init_basis(state: qaa_state, z0: int, stream=None) -> None:
     _check(_lib.qaa_state_init_basis(ctypes.byref(state), int(z0), _stream_ptr(stream)), "qaa_state_init_basis")
 
 
-def qaa_evolve(state: qaa_state, T: float, steps: int, stream=None) -> None:
-    sched = qaa_schedule(QAA_SCHED_LINEAR)
+def qaa_evolve(state: qaa_state, T: float, steps: int, stream=None, knots=None) -> None:
+    """Evolve in place; knots: None (linear schedule) or a schedule table."""
+    sched = make_schedule(knots)
     _check(_lib.qaa_evolve(ctypes.byref(state), ctypes.byref(sched), float(T), int(steps), _stream_ptr(stream)),
            "qaa_evolve")
 
 
-def qaa_evolve_range(state: qaa_state, T: float, steps: int, k0: int, k1: int, stream=None) -> None:
-    sched = qaa_schedule(QAA_SCHED_LINEAR)
+def qaa_evolve_range(state: qaa_state, T: float, steps: int, k0: int, k1: int, stream=None, knots=None) -> None:
+    sched = make_schedule(knots)
     _check(_lib.qaa_evolve_range(ctypes.byref(state), ctypes.byref(sched), float(T), int(steps), int(k0), int(k1),
                                  _stream_ptr(stream)), "qaa_evolve_range")
 
 
-def qaa_evolve_batch(states, Ts, steps, stream=None) -> None:
+def qaa_evolve_batch(states, Ts, steps, stream=None, knots=None) -> None:
+    """Evolve states together; knots: None (all linear) or one entry per
+    state, each None (linear) or a schedule table."""
     cnt = len(states)
     arr = (qaa_state * cnt)(*states)
     t_arr = (ctypes.c_double * cnt)(*[float(t) for t in Ts])
     s_arr = (ctypes.c_int64 * cnt)(*[int(s) for s in steps])
-    _check(_lib.qaa_evolve_batch(cnt, arr, t_arr, s_arr, _stream_ptr(stream)), "qaa_evolve_batch")
+    scheds = None
+    if knots is not None:
+        if len(knots) != cnt:
+            raise ValueError("qaa_evolve_batch: one schedule per state")
+        held = [make_schedule(k) for k in knots]
+        scheds = (qaa_schedule * cnt)(*held)
+    _check(_lib.qaa_evolve_batch(cnt, arr, scheds, t_arr, s_arr, _stream_ptr(stream)), "qaa_evolve_batch")
 
 
 def qaa_observables(state: qaa_state, stream=None) -> dict:
@@ -227,6 +258,22 @@ def qaa_observables(state: qaa_state, stream=None) -> dict:
     _check(_lib.qaa_observables(ctypes.byref(state), ctypes.byref(out), _stream_ptr(stream)), "qaa_observables")
     return {"norm": out.norm, "energy": out.energy, "p_success": out.p_success, "e_min": out.e_min,
             "degeneracy": out.degeneracy}
+
+
+def qaa_spectrum(handle: int, table, etype: int, s_values, v0, iters: int, k: int, stream=None):
+    """The k lowest eigenvalues of H(s) at each s (Lanczos from the device
+    vector v0, float64 of length 2^n); returns a numpy array [len(s), k]."""
+    import numpy as np
+    import torch
+    if v0.dtype != torch.float64 or not v0.is_contiguous():
+        raise TypeError("v0 must be a contiguous float64 device tensor")
+    sv = [float(x) for x in s_values]
+    cnt = len(sv)
+    s_arr = (ctypes.c_double * max(1, cnt))(*sv)
+    out = (ctypes.c_double * max(1, cnt * int(k)))()
+    _check(_lib.qaa_spectrum(handle, table.data_ptr(), int(etype), cnt, s_arr, v0.data_ptr(), int(iters), int(k),
+                             out, _stream_ptr(stream)), "qaa_spectrum")
+    return np.frombuffer(out, dtype=np.float64, count=cnt * int(k)).reshape(cnt, int(k)).copy()
 
 
 def qaa_plan_info(n: int, dtype: int = QAA_C64) -> dict:
@@ -254,14 +301,17 @@ class PassDesc(ctypes.Structure):
                 ("gpos_last", ctypes.c_uint8 * 16), ("masks", ctypes.c_uint32 * 12)]
 
 
-def qaa_debug_pass_descs(n: int, dtype: int, emax: int, T: float, steps: int, k0: int, k1: int):
+def qaa_debug_pass_descs(n: int, dtype: int, emax: int, T: float, steps: int, k0: int, k1: int, knots=None):
     count, size = ctypes.c_int32(), ctypes.c_int32()
-    _check(_lib.qaa_debug_pass_descs(n, dtype, emax, T, steps, k0, k1, None, 0, ctypes.byref(count),
+    sched = make_schedule(knots)
+    _check(_lib.qaa_debug_pass_descs(n, dtype, emax, ctypes.byref(sched), T, steps, k0, k1, None, 0,
+                                     ctypes.byref(count),
                                      ctypes.byref(size)), "qaa_debug_pass_descs")
     if size.value != ctypes.sizeof(PassDesc):
         raise RuntimeError("pass descriptor layout mismatch (%d vs %d bytes)" % (size.value, ctypes.sizeof(PassDesc)))
     arr = (PassDesc * max(1, count.value))()
-    _check(_lib.qaa_debug_pass_descs(n, dtype, emax, T, steps, k0, k1, arr, count.value, ctypes.byref(count),
+    _check(_lib.qaa_debug_pass_descs(n, dtype, emax, ctypes.byref(sched), T, steps, k0, k1, arr, count.value,
+                                     ctypes.byref(count),
                                      ctypes.byref(size)), "qaa_debug_pass_descs")
     return list(arr)[:count.value]
 
@@ -383,6 +433,12 @@ class Instance:
         qaa_energy_table(self.handle, table, etype, stream)
         return table
 
+    def spectrum(self, table, s_values, v0, iters: int, k: int, stream=None):
+        """Lowest k eigenvalues of H(s) per s (see qaa_spectrum)."""
+        import torch
+        etype = QAA_E_U8 if table.dtype == torch.uint8 else QAA_E_U16
+        return qaa_spectrum(self.handle, table, etype, s_values, v0, iters, k, stream)
+
     def close(self):
         if self.handle:
             qaa_instance_destroy(self.handle)
@@ -416,12 +472,12 @@ class State:
         qaa_state_init_basis(self.c, z0, stream)
         return self
 
-    def evolve(self, T: float, steps: int, stream=None):
-        qaa_evolve(self.c, T, steps, stream)
+    def evolve(self, T: float, steps: int, stream=None, knots=None):
+        qaa_evolve(self.c, T, steps, stream, knots)
         return self
 
-    def evolve_range(self, T: float, steps: int, k0: int, k1: int, stream=None):
-        qaa_evolve_range(self.c, T, steps, k0, k1, stream)
+    def evolve_range(self, T: float, steps: int, k0: int, k1: int, stream=None, knots=None):
+        qaa_evolve_range(self.c, T, steps, k0, k1, stream, knots)
         return self
 
     def observables(self, stream=None) -> dict:

@@ -595,13 +595,14 @@ __device__ __forceinline__ double step_gphase(int n, double theta, bool flip)
     return fmod(0.5 * (double)n * theta + (flip ? M_PI * (double)(n & 1) : 0.0), 2.0 * M_PI);
 }
 
-// Step k of N over total time T: schedule midpoint s_k = (k + 1/2)/N and the
-// rotation coefficients of theta_k = dt (1 - s_k) (same formulas as the host).
-__device__ __forceinline__ DevCoef dev_step_coef(double T, int64_t N, int64_t k)
+// Step k of N over total time T: schedule value s_k at the step midpoint
+// (knots v[0..count), count 0 = linear) and the rotation coefficients of
+// theta_k = dt (1 - s_k) (same formulas as the host).
+__device__ __forceinline__ DevCoef dev_step_coef(double T, int64_t N, int64_t k, const double *v, int count)
 {
     DevCoef c;
     const double dt = T / (double)N;
-    c.s = ((double)k + 0.5) / (double)N;
+    c.s = sched_mid(v, count, k, N);
     c.theta = dt * (1.0 - c.s);
     rot_params(c.theta, c.t, c.sn, c.flip);
     return c;
@@ -640,14 +641,14 @@ batch_pass_kernel(const BatchInst *__restrict__ insts, const uint32_t *__restric
     const uint64_t w1 = w0 + (uint64_t)chunk_tiles < ntiles ? w0 + (uint64_t)chunk_tiles : ntiles;
 
     const double dt = I.T / (double)I.N;
-    const DevCoef ck = dev_step_coef(I.T, I.N, s);
+    const DevCoef ck = dev_step_coef(I.T, I.N, s, I.sched.v, I.sched.count);
     Rot<F> kA = make_rot<F>(ck.t, ck.sn), kB = make_rot<F>(0.0, 0.0);
     double phi = 0.0, gph = 0.0;
     if (kind == 0) {
         kB = kA;
         phi = 0.5 * dt * ck.s;
     } else if (kind == r - 1 || kind == r) {
-        const DevCoef cn = dev_step_coef(I.T, I.N, s + 1);
+        const DevCoef cn = dev_step_coef(I.T, I.N, s + 1, I.sched.v, I.sched.count);
         kB = make_rot<F>(cn.t, cn.sn);
         phi = 0.5 * dt * (ck.s + cn.s);
         gph = step_gphase(I.n, ck.theta, ck.flip);
@@ -720,6 +721,11 @@ __device__ __forceinline__ void resident_body(const ResidentDesc &d)
         lj_s[g][j] = o;
     }
     if (tid < 8) gm_s[tid] = d.gmask[tid];
+    // schedule knots, read once per step below
+    __shared__ double knots_s[kMaxKnots];
+    const int kcount = d.sched.count;
+    for (int x = (int)tid; x < kcount; x += (int)blockDim.x) knots_s[x] = d.sched.v[x];
+    __syncthreads();     // every thread reads knots_s before its first barrier
 
     for (uint32_t z = tid; z < dim; z += blockDim.x) {
         tile[swz<F>(z)] = amp[z];
@@ -789,7 +795,7 @@ __device__ __forceinline__ void resident_body(const ResidentDesc &d)
     double theta_prev = 0.0, s_prev = 0.0;
     bool flip_prev = false;
     for (int64_t k = d.k0; k < d.k1; ++k) {
-        const double sk = ((double)k + 0.5) / Nd;
+        const double sk = sched_mid(knots_s, kcount, k, d.N);
         const double theta = dt * (1.0 - sk);
         double phi, gph;
         if (k == d.k0) {

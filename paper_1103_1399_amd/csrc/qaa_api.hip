@@ -520,11 +520,11 @@ struct StepCoef {
     bool flip;
 };
 
-StepCoef step_coef(double T, int64_t N, int64_t k)
+StepCoef step_coef(double T, int64_t N, int64_t k, const SchedKnots &sc)
 {
     StepCoef c;
     const double dt = T / (double)N;
-    c.s = ((double)k + 0.5) / (double)N;
+    c.s = sched_mid(sc.v, sc.count, k, N);
     c.theta = dt * (1.0 - c.s);
     double phi = std::fmod(0.5 * c.theta, 2.0 * M_PI);
     if (phi > M_PI) phi -= 2.0 * M_PI;
@@ -632,12 +632,14 @@ void fill_residencies(PassDesc &d, const SetPlan &sp, int tb, int rb, int dt, bo
     }
 }
 
-ResidentDesc make_resident_desc(const qaa_state *st, double T, int64_t N, int64_t k0, int64_t k1)
+ResidentDesc make_resident_desc(const qaa_state *st, const SchedKnots &sc, double T, int64_t N, int64_t k0,
+                                int64_t k1)
 {
     const int n = st->inst->n;
     const int dt = (int)st->dtype;
     ResidentDesc d;
     std::memset(&d, 0, sizeof d);
+    d.sched = sc;
     d.amp = st->amp;
     d.table = st->table;
     d.n = n;
@@ -662,9 +664,10 @@ ResidentDesc make_resident_desc(const qaa_state *st, double T, int64_t N, int64_
     return d;
 }
 
-qaa_status run_resident(const qaa_state *st, double T, int64_t N, int64_t k0, int64_t k1, hipStream_t s)
+qaa_status run_resident(const qaa_state *st, const SchedKnots &sc, double T, int64_t N, int64_t k0, int64_t k1,
+                        hipStream_t s)
 {
-    const ResidentDesc d = make_resident_desc(st, T, N, k0, k1);
+    const ResidentDesc d = make_resident_desc(st, sc, T, N, k0, k1);
     QAA_HIP(launch_resident(nullptr, &d, 1, (int)st->dtype, (int)st->etype, s));
     return QAA_OK;
 }
@@ -673,8 +676,8 @@ qaa_status run_resident(const qaa_state *st, double T, int64_t N, int64_t k0, in
 // visited forward on even steps (relative to k0) and backward on odd ones,
 // so the set that ends step k also starts step k+1 and one pass applies
 // both its rotations and the merged diagonal phase between them.
-std::vector<PassDesc> build_passes(const Plan &p, int n, int dty, int emax, double T, int64_t N, int64_t k0,
-                                   int64_t k1)
+std::vector<PassDesc> build_passes(const Plan &p, int n, int dty, int emax, const SchedKnots &sc, double T,
+                                   int64_t N, int64_t k0, int64_t k1)
 {
     std::vector<PassDesc> out;
     const int TB = p.tile_bits, RB = p.reg_bits;
@@ -686,7 +689,7 @@ std::vector<PassDesc> build_passes(const Plan &p, int n, int dty, int emax, doub
     base.emax = emax;
     for (int64_t k = k0; k < k1; ++k) {
         const bool fwd = ((k - k0) & 1) == 0;
-        const StepCoef ck = step_coef(T, N, k);
+        const StepCoef ck = step_coef(T, N, k, sc);
         for (int idx = 0; idx < r; ++idx) {
             const int set = fwd ? idx : r - 1 - idx;
             const bool first = idx == 0, last = idx == r - 1;
@@ -713,7 +716,7 @@ std::vector<PassDesc> build_passes(const Plan &p, int n, int dty, int emax, doub
                 d.sB = ck.sn;
                 fill_residencies(d, sp, TB, RB, dty, false, true, true);
             } else if (last && k + 1 < k1) {
-                const StepCoef cn = step_coef(T, N, k + 1);
+                const StepCoef cn = step_coef(T, N, k + 1, sc);
                 d.tA = ck.t;
                 d.sA = ck.sn;
                 d.phi = 0.5 * dt * (ck.s + cn.s);
@@ -852,10 +855,10 @@ hipError_t prof_drain(bool wait)
     return hipSuccess;
 }
 
-std::vector<PassDesc> plan_passes(const Plan &p, int n, int dty, int emax, double T, int64_t N, int64_t k0,
-                                  int64_t k1)
+std::vector<PassDesc> plan_passes(const Plan &p, int n, int dty, int emax, const SchedKnots &sc, double T,
+                                  int64_t N, int64_t k0, int64_t k1)
 {
-    return schedule_passes(build_passes(p, n, dty, emax, T, N, k0, k1), p, n, dty == 0 ? 3 : 4);
+    return schedule_passes(build_passes(p, n, dty, emax, sc, T, N, k0, k1), p, n, dty == 0 ? 3 : 4);
 }
 
 // Norm control (see PassDesc) is on unless QAA_NORM_CONTROL=0 is set in
@@ -869,10 +872,11 @@ bool norm_control_enabled()
     return on;
 }
 
-qaa_status run_passes(const qaa_state *st, const Plan &p, double T, int64_t N, int64_t k0, int64_t k1,
-                      hipStream_t s)
+qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, double T, int64_t N, int64_t k0,
+                      int64_t k1, hipStream_t s)
 {
-    const std::vector<PassDesc> ps = plan_passes(p, st->inst->n, (int)st->dtype, st->inst->e_max, T, N, k0, k1);
+    const std::vector<PassDesc> ps =
+        plan_passes(p, st->inst->n, (int)st->dtype, st->inst->e_max, sc, T, N, k0, k1);
     unsigned long long *acc = nullptr;
     if (norm_control_enabled()) {
         QAA_HIP(hipMallocAsync(reinterpret_cast<void **>(&acc), 3 * sizeof(unsigned long long), s));
@@ -936,13 +940,36 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, double T, int64_t N, i
 
 int lut_limit(qaa_etype e) { return e == QAA_E_U8 ? kLutMaxU8 : kLutMax; }
 
+// Validates a caller's schedule and copies it into the form the planner and
+// the kernels read (NULL and QAA_SCHED_LINEAR: count 0).
+qaa_status to_knots(const qaa_schedule *sched, SchedKnots *out, const char *who)
+{
+    std::memset(out, 0, sizeof *out);
+    if (!sched || sched->kind == QAA_SCHED_LINEAR) return QAA_OK;
+    if (sched->kind != QAA_SCHED_TABLE)
+        return fail(QAA_ERR_INVALID_ARG, "%s: unknown schedule kind %d", who, sched->kind);
+    if (sched->count < 2 || sched->count > kMaxKnots)
+        return fail(QAA_ERR_INVALID_ARG, "%s: schedule table needs 2..%d knots, got %d", who, kMaxKnots,
+                    sched->count);
+    if (!sched->values) return fail(QAA_ERR_INVALID_ARG, "%s: schedule table values is NULL", who);
+    for (int j = 0; j < sched->count; ++j) {
+        const double v = sched->values[j];
+        if (!(v >= 0.0 && v <= 1.0))
+            return fail(QAA_ERR_INVALID_ARG, "%s: schedule knot %d is not in [0, 1]", who, j);
+        out->v[j] = v;
+    }
+    out->count = sched->count;
+    return QAA_OK;
+}
+
 qaa_status evolve_common(const qaa_state *st, const qaa_schedule *sched, double T, int64_t steps, int64_t k0,
                          int64_t k1, void *stream, const char *who)
 {
-    qaa_status r = check_state_table(st, who);
+    SchedKnots sc;
+    qaa_status r = to_knots(sched, &sc, who);
     if (r != QAA_OK) return r;
-    if (sched && sched->kind != QAA_SCHED_LINEAR)
-        return fail(QAA_ERR_UNSUPPORTED, "%s: schedule kind %d not supported", who, sched->kind);
+    r = check_state_table(st, who);
+    if (r != QAA_OK) return r;
     if (!(T >= 0.0) || !std::isfinite(T)) return fail(QAA_ERR_INVALID_ARG, "%s: T must be finite and >= 0", who);
     if (steps < 0) return fail(QAA_ERR_INVALID_ARG, "%s: steps < 0", who);
     if (k0 < 0 || k1 < k0 || k1 > steps)
@@ -953,7 +980,7 @@ qaa_status evolve_common(const qaa_state *st, const qaa_schedule *sched, double 
     if (k0 == k1) return ok();
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const Plan p = make_plan(st->inst->n, (int)st->dtype);
-    r = p.resident ? run_resident(st, T, steps, k0, k1, s) : run_passes(st, p, T, steps, k0, k1, s);
+    r = p.resident ? run_resident(st, sc, T, steps, k0, k1, s) : run_passes(st, p, sc, T, steps, k0, k1, s);
     if (r != QAA_OK) return r;
     return ok();
 }
@@ -1035,8 +1062,8 @@ qaa_status upload(const std::vector<T> &host, T **dev, hipStream_t s)
 // (one workgroup each).
 constexpr int kBatchChunkTiles = 8;
 
-qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states, const double *T,
-                            const int64_t *steps, hipStream_t s)
+qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states, const SchedKnots *scs,
+                            const double *T, const int64_t *steps, hipStream_t s)
 {
     if (idx.empty()) return QAA_OK;
     const int dty = (int)states[idx[0]].dtype, ety = (int)states[idx[0]].etype;
@@ -1085,6 +1112,7 @@ qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states
             b.emax = states[i].inst->e_max;
             b.r = g.r;
             b.struct_base = base_of_n[n];
+            b.sched = scs[i];
             const uint64_t chunks = ((1ull << (n - TB)) + kBatchChunkTiles - 1) / kBatchChunkTiles;
             for (uint64_t c = 0; c < chunks; ++c) chunk_inst.push_back((uint32_t)(insts.size() - g.inst_base));
             g.chunk_prefix.push_back(g.chunk_prefix.back() + chunks);
@@ -1141,14 +1169,17 @@ qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states
 
 }  // namespace
 
-extern "C" qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, const double *T,
-                                       const int64_t *steps, void *stream)
+extern "C" qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, const qaa_schedule *scheds,
+                                       const double *T, const int64_t *steps, void *stream)
 {
     if (count < 0) return fail(QAA_ERR_INVALID_ARG, "qaa_evolve_batch: count < 0");
     if (count == 0) return ok();
     if (!states || !T || !steps) return fail(QAA_ERR_INVALID_ARG, "qaa_evolve_batch: NULL array");
+    std::vector<SchedKnots> scs((size_t)count);
     for (int i = 0; i < count; ++i) {
-        qaa_status r = check_state_table(&states[i], "qaa_evolve_batch");
+        qaa_status r = to_knots(scheds ? &scheds[i] : nullptr, &scs[i], "qaa_evolve_batch");
+        if (r != QAA_OK) return r;
+        r = check_state_table(&states[i], "qaa_evolve_batch");
         if (r != QAA_OK) return r;
         if (!(T[i] >= 0.0) || !std::isfinite(T[i]) || steps[i] < 0)
             return fail(QAA_ERR_INVALID_ARG, "qaa_evolve_batch: state %d has a bad T or step count", i);
@@ -1167,7 +1198,7 @@ extern "C" qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, c
         if (steps[i] == 0) continue;
         const int dt = (int)states[i].dtype, et = (int)states[i].etype;
         if (make_plan(states[i].inst->n, dt).resident)
-            small[dt][et].push_back(make_resident_desc(&states[i], T[i], steps[i], 0, steps[i]));
+            small[dt][et].push_back(make_resident_desc(&states[i], scs[i], T[i], steps[i], 0, steps[i]));
         else
             large[dt][et].push_back(i);
     }
@@ -1207,13 +1238,42 @@ extern "C" qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, c
     if (r == QAA_OK && he != hipSuccess)
         r = fail(QAA_ERR_DEVICE, "qaa_evolve_batch: resident launch failed: %s", hipGetErrorString(he));
     for (int dt = 0; dt < 2 && r == QAA_OK; ++dt)
-        for (int et = 0; et < 2 && r == QAA_OK; ++et) r = run_batch_passes(large[dt][et], states, T, steps, s);
+        for (int et = 0; et < 2 && r == QAA_OK; ++et) r = run_batch_passes(large[dt][et], states, scs.data(), T, steps, s);
     // the caller's stream waits for the side stream's work of this call on
     // every path, so none of it outlives the caller's stream unordered
     he = joined ? hipStreamWaitEvent(s, join, 0) : hipErrorUnknown;
     if (r != QAA_OK) return done(r);
     if (he != hipSuccess) return done(fail(QAA_ERR_DEVICE, "qaa_evolve_batch: join failed"));
     return done(ok());
+}
+
+// ---------------------------------------------------------------------------
+// Spectrum of H(s)
+// ---------------------------------------------------------------------------
+extern "C" qaa_status qaa_spectrum(const qaa_instance *inst, const void *table, qaa_etype etype, int32_t count,
+                                   const double *s_values, const double *v0, int32_t iters, int32_t k,
+                                   double *evals, void *stream)
+{
+    const char *who = "qaa_spectrum";
+    if (!inst) return fail(QAA_ERR_INVALID_ARG, "%s: instance is NULL", who);
+    if (!table || !v0) return fail(QAA_ERR_INVALID_ARG, "%s: table or v0 is NULL", who);
+    if (etype != QAA_E_U8 && etype != QAA_E_U16) return fail(QAA_ERR_INVALID_ARG, "%s: bad etype %d", who, (int)etype);
+    if (count < 0) return fail(QAA_ERR_INVALID_ARG, "%s: count < 0", who);
+    if (count > 0 && (!s_values || !evals)) return fail(QAA_ERR_INVALID_ARG, "%s: NULL s_values or evals", who);
+    if (iters < 1 || iters > QAA_SPECTRUM_MAX_ITERS)
+        return fail(QAA_ERR_INVALID_ARG, "%s: iters must be in 1..%d", who, QAA_SPECTRUM_MAX_ITERS);
+    if (k < 1 || k > iters) return fail(QAA_ERR_INVALID_ARG, "%s: k must be in 1..iters", who);
+    for (int i = 0; i < count; ++i)
+        if (!(s_values[i] >= 0.0 && s_values[i] <= 1.0))
+            return fail(QAA_ERR_INVALID_ARG, "%s: s_values[%d] is not in [0, 1]", who, i);
+    if (reinterpret_cast<uintptr_t>(v0) % 8) return fail(QAA_ERR_INVALID_ARG, "%s: v0 must be 8-byte aligned", who);
+    if (inst->e_max < 0) return fail(QAA_ERR_NOT_READY, "%s: qaa_energy_table has not run for this instance", who);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    for (int i = 0; i < count; ++i) {
+        qaa_status r = lanczos_lowest(inst->n, table, (int)etype, s_values[i], v0, iters, k, evals + (size_t)i * k, s);
+        if (r != QAA_OK) return r;
+    }
+    return ok();
 }
 
 // ---------------------------------------------------------------------------
@@ -1337,21 +1397,24 @@ extern "C" qaa_status qaa_plan_info(int32_t n, qaa_dtype dtype, int32_t *tile_bi
     return ok();
 }
 
-extern "C" qaa_status qaa_debug_pass_descs(int32_t n, qaa_dtype dtype, int32_t emax, double T, int64_t steps,
-                                           int64_t k0, int64_t k1, void *out, int32_t capacity, int32_t *count,
-                                           int32_t *desc_bytes)
+extern "C" qaa_status qaa_debug_pass_descs(int32_t n, qaa_dtype dtype, int32_t emax, const qaa_schedule *sched,
+                                           double T, int64_t steps, int64_t k0, int64_t k1, void *out,
+                                           int32_t capacity, int32_t *count, int32_t *desc_bytes)
 {
     if (n < 1 || n > QAA_MAX_QUBITS) return fail(QAA_ERR_INVALID_ARG, "qaa_debug_pass_descs: n out of range");
     if (dtype != QAA_C64 && dtype != QAA_C128) return fail(QAA_ERR_INVALID_ARG, "qaa_debug_pass_descs: bad dtype");
     if (steps < 0 || k0 < 0 || k1 < k0 || k1 > steps || !count)
         return fail(QAA_ERR_INVALID_ARG, "qaa_debug_pass_descs: bad step range");
     if (desc_bytes) *desc_bytes = (int32_t)sizeof(PassDesc);
+    SchedKnots sc;
+    qaa_status r = to_knots(sched, &sc, "qaa_debug_pass_descs");
+    if (r != QAA_OK) return r;
     const Plan p = make_plan(n, (int)dtype);
     if (p.resident || k0 == k1) {
         *count = 0;
         return ok();
     }
-    const std::vector<PassDesc> ps = plan_passes(p, n, (int)dtype, emax, T, steps, k0, k1);
+    const std::vector<PassDesc> ps = plan_passes(p, n, (int)dtype, emax, sc, T, steps, k0, k1);
     *count = (int32_t)ps.size();
     if (out && capacity > 0)
         std::memcpy(out, ps.data(), sizeof(PassDesc) * std::min<size_t>(ps.size(), (size_t)capacity));

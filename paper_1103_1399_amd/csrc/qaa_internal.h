@@ -15,6 +15,30 @@ constexpr int kMaxRes = 12;
 constexpr int kLutMax = 1024;
 constexpr int kLutMaxU8 = 256;
 
+// Interpolation schedule as the kernels and the host planner consume it:
+// count == 0 is the linear s(u) = u; otherwise v[0..count) are the knots of
+// a piecewise-linear s(u) at u_j = j/(count - 1) (see qaa_schedule).
+constexpr int kMaxKnots = QAA_SCHED_MAX_KNOTS;
+struct SchedKnots {
+    int32_t count;
+    int32_t pad_;
+    double v[kMaxKnots];
+};
+
+// s at the midpoint u_k = (k + 1/2)/N of step k.  Host and device evaluate
+// this same expression (the product and the quotient are correctly rounded
+// and the interpolation is one explicit fma), so a state gets the same s_k
+// whether its coefficients are made on the host or on the device.  With
+// the knots {0, 1} it returns exactly (k + 1/2)/N, the linear schedule.
+__host__ __device__ inline double sched_mid(const double *v, int count, int64_t k, int64_t N)
+{
+    if (count < 2) return ((double)k + 0.5) / (double)N;
+    const double x = ((double)k + 0.5) * (double)(count - 1) / (double)N;
+    int j = (int)x;                      // x >= 0: truncation is floor
+    if (j > count - 2) j = count - 2;
+    return fma(x - (double)j, v[j + 1] - v[j], v[j]);
+}
+
 // One clause in the form the energy kernel consumes.  A clause over three
 // distinct variables is violated by z iff (z & mask) == pat, where mask has
 // the clause's three variable bits and pat has the bits of the negated
@@ -118,6 +142,7 @@ struct ResidentDesc {
     uint8_t gbits[8][8];       // group g: state bit of register bit i
     uint8_t tpos[8][16];       // group g: state bit of thread-index bit k
     uint8_t gmask[8];          // register bits of group g that rotate
+    SchedKnots sched;
 };
 
 // One state of a batched evolution run pass by pass (n above the resident
@@ -129,7 +154,7 @@ struct ResidentDesc {
 //   kind r-1 / r: turn pass over set r-1 / set 0,
 //   kind r+1 / r+2: last pass over set r-1 / set 0,
 // and the rotation and phase coefficients are computed on the device from
-// (T, N, s) exactly as the host computes them for a single state.
+// (T, N, schedule, s) exactly as the host computes them for a single state.
 struct BatchInst {
     void *amp;
     const void *table;
@@ -138,6 +163,7 @@ struct BatchInst {
     int64_t N;
     uint64_t chunk_offset;     // first workgroup chunk of this state in its launch group
     int32_t n, emax, r, struct_base;
+    SchedKnots sched;
 };
 
 // Kernel launch helpers (defined in the .hip files).
@@ -174,6 +200,15 @@ hipError_t launch_observables(const void *amp, int dtype, const void *table, int
                               int emin, double *partials, int nblocks, double *out,
                               hipStream_t s);
 int observables_blocks(int n);
+
+// y = H(s) x for real FP64 vectors of 2^n entries (spectrum.hip).
+hipError_t launch_hmv_product(const double *x, const void *table, int etype, double *y, int n, double s,
+                              hipStream_t st);
+// The k lowest Ritz values of H(s) after `iters` Lanczos steps from v0
+// (device), into the host array evals (NaN past the Krylov dimension).
+// Synchronous on st.
+qaa_status lanczos_lowest(int n, const void *table, int etype, double s, const double *v0, int iters, int k,
+                          double *evals, hipStream_t st);
 
 // Sets the calling thread's qaa_last_error() message (cleared for QAA_OK)
 // and returns st.

@@ -1,0 +1,307 @@
+// spectrum.hip -- lowest eigenvalues of H(s) = (1 - s) H_B + s H_P
+// (Sec. 2.1, eq. 1) by Lanczos with full reorthogonalisation, FP64.
+//
+// H(s) is real and symmetric in the computational basis:
+//     (H x)(z) = ((1 - s) n/2 + s E(z)) x(z) - (1 - s)/2 sum_q x(z xor 2^q),
+// since H_B = sum_q (1 - sigma^x_q)/2 and sigma^x_q flips bit q of z.
+// The device runs the whole Lanczos recurrence (matrix-vector product,
+// two classical Gram-Schmidt sweeps against every earlier Lanczos vector,
+// normalisation) without a host round trip; the host reads the
+// tridiagonal coefficients once at the end and finds the lowest Ritz
+// values by Sturm-sequence bisection (Barth, Martin and Wilkinson, 1967).
+#include "qaa_internal.h"
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <string>
+#include <vector>
+
+namespace qaa {
+namespace {
+
+// Tile of the matrix-vector product: 2^kHmvTile consecutive z per
+// workgroup, staged in LDS so the flips of the low qubits read LDS; the
+// flips of the high qubits read the partner tile from memory, which for a
+// fixed qubit is itself contiguous (coalesced).
+constexpr int kHmvTile = 10;
+constexpr int kThreads = 256;
+// Partial sums per vector in the dot products: fixed, so the order of
+// every FP64 sum is fixed (deterministic results).
+constexpr int kDotBlocks = 2048;
+constexpr int kDotWaves = kThreads / 64;
+constexpr int kDotGroup = 8;      // vectors per sweep over w
+
+template <typename ET>
+__global__ void __launch_bounds__(kThreads)
+hmv_kernel(const double *__restrict__ x, const ET *__restrict__ E, double *__restrict__ y, int n, int tb,
+           double diag_b, double off, double s)
+{
+    __shared__ double xs[1 << kHmvTile];
+    const uint32_t tsize = 1u << tb;
+    const uint64_t base = (uint64_t)blockIdx.x << tb;
+    for (uint32_t l = threadIdx.x; l < tsize; l += blockDim.x) xs[l] = x[base + l];
+    __syncthreads();
+    for (uint32_t l = threadIdx.x; l < tsize; l += blockDim.x) {
+        const uint64_t z = base + l;
+        double acc = 0.0;
+        for (int q = 0; q < tb; ++q) acc += xs[l ^ (1u << q)];
+        for (int q = tb; q < n; ++q) acc += x[z ^ (1ull << q)];
+        y[z] = fma(fma(s, (double)E[z], diag_b), xs[l], off * acc);
+    }
+}
+
+// partials[(j * gridDim.x + block) * kDotWaves + wave] = this wave's part
+// of V_j . w, for j < k (V_j = V + j * dim).
+__global__ void __launch_bounds__(kThreads)
+dots_kernel(const double *__restrict__ V, int k, const double *__restrict__ w, uint64_t dim,
+            double *__restrict__ partials)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t e0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    for (int j0 = 0; j0 < k; j0 += kDotGroup) {
+        const int g = min(kDotGroup, k - j0);
+        double p[kDotGroup];
+#pragma unroll
+        for (int i = 0; i < kDotGroup; ++i) p[i] = 0.0;
+        for (uint64_t e = e0; e < dim; e += stride) {
+            const double we = w[e];
+#pragma unroll
+            for (int i = 0; i < kDotGroup; ++i)
+                if (i < g) p[i] = fma(V[(uint64_t)(j0 + i) * dim + e], we, p[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < kDotGroup; ++i) {
+            if (i >= g) break;
+            double t = p[i];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+            if (lane == 0) partials[((uint64_t)(j0 + i) * gridDim.x + blockIdx.x) * kDotWaves + wave] = t;
+        }
+    }
+}
+
+// out[j] = sum of the np partials of vector j, in a fixed order (block j).
+__global__ void __launch_bounds__(kThreads)
+sum_partials_kernel(const double *__restrict__ partials, int np, double *__restrict__ out)
+{
+    const int j = (int)blockIdx.x;
+    double t = 0.0;
+    for (int p = (int)threadIdx.x; p < np; p += (int)blockDim.x) t += partials[(uint64_t)j * np + p];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    __shared__ double red[kThreads / 64];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double total = 0.0;
+        for (int i = 0; i < kThreads / 64; ++i) total += red[i];
+        out[j] = total;
+    }
+}
+
+// w -= sum_{j < k} c[j] V_j.
+__global__ void __launch_bounds__(kThreads)
+update_kernel(double *__restrict__ w, const double *__restrict__ V, int k, const double *__restrict__ c,
+              uint64_t dim)
+{
+    extern __shared__ double cs[];
+    for (int j = (int)threadIdx.x; j < k; j += (int)blockDim.x) cs[j] = c[j];
+    __syncthreads();
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < dim; e += stride) {
+        double acc = 0.0;
+        for (int j = 0; j < k; ++j) acc = fma(cs[j], V[(uint64_t)j * dim + e], acc);
+        w[e] -= acc;
+    }
+}
+
+// v = w / sqrt(*nrm2) (v = 0 if the norm is exactly 0).  Block 0 also
+// records alpha[j] = ca[j] + cb[j] (the two Gram-Schmidt coefficients of
+// the newest vector; ca == nullptr: none) and beta[j] = sqrt(*nrm2).
+__global__ void __launch_bounds__(kThreads)
+normalize_kernel(const double *__restrict__ w, double *__restrict__ v, const double *__restrict__ nrm2,
+                 uint64_t dim, const double *__restrict__ ca, const double *__restrict__ cb, int j,
+                 double *__restrict__ alpha, double *__restrict__ beta)
+{
+    const double b = sqrt(*nrm2);
+    const double inv = b > 0.0 ? 1.0 / b : 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < dim; e += stride) v[e] = w[e] * inv;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (ca) alpha[j] = ca[j] + cb[j];
+        if (beta) beta[j] = b;
+    }
+}
+
+unsigned grid_for(uint64_t dim)
+{
+    const uint64_t b = (dim + kThreads - 1) / kThreads;
+    return (unsigned)std::min<uint64_t>(b, 4096);
+}
+
+// The number of eigenvalues of the symmetric tridiagonal matrix
+// (diagonal a[0..m), off-diagonal b[0..m-1)) that are smaller than x:
+// the count of negative pivots of the LDL^T factorisation of T - x I.
+int sturm_count(const std::vector<double> &a, const std::vector<double> &b, int m, double x, double pivmin)
+{
+    int cnt = 0;
+    double q = 1.0;
+    for (int i = 0; i < m; ++i) {
+        q = (a[i] - x) - (i > 0 ? b[i - 1] * b[i - 1] / q : 0.0);
+        if (std::fabs(q) < pivmin) q = -pivmin;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+// The i-th smallest eigenvalue (i = 0, 1, ...) of the tridiagonal matrix,
+// by bisection inside the Gershgorin interval.
+double tridiag_eig(const std::vector<double> &a, const std::vector<double> &b, int m, int i)
+{
+    double lo = a[0], hi = a[0], scale = 0.0;
+    for (int r = 0; r < m; ++r) {
+        const double rad = (r > 0 ? std::fabs(b[r - 1]) : 0.0) + (r + 1 < m ? std::fabs(b[r]) : 0.0);
+        lo = std::min(lo, a[r] - rad);
+        hi = std::max(hi, a[r] + rad);
+        scale = std::max(scale, std::fabs(a[r]) + rad);
+    }
+    const double pivmin = DBL_MIN * std::max(1.0, scale * scale);
+    lo -= DBL_EPSILON * scale + pivmin;
+    hi += DBL_EPSILON * scale + pivmin;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (sturm_count(a, b, m, mid, pivmin) > i)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+template <typename ET>
+hipError_t launch_hmv(const double *x, const void *table, double *y, int n, double s, hipStream_t st)
+{
+    const int tb = std::min(n, kHmvTile);
+    const unsigned blocks = (unsigned)(1ull << (n - tb));
+    hipLaunchKernelGGL((hmv_kernel<ET>), dim3(blocks), dim3(kThreads), 0, st, x, reinterpret_cast<const ET *>(table),
+                       y, n, tb, (1.0 - s) * 0.5 * (double)n, -0.5 * (1.0 - s), s);
+    return hipGetLastError();
+}
+
+// c[0..k) = V[0..k)^T w, through `partials` (k * kDotBlocks * kDotWaves).
+hipError_t project(const double *V, int k, const double *w, uint64_t dim, double *partials, double *c,
+                   hipStream_t st)
+{
+    const unsigned nb = (unsigned)std::min<uint64_t>(kDotBlocks, (dim + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(dots_kernel, dim3(nb), dim3(kThreads), 0, st, V, k, w, dim, partials);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3((unsigned)k), dim3(kThreads), 0, st, partials,
+                       (int)(nb * kDotWaves), c);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_hmv_product(const double *x, const void *table, int etype, double *y, int n, double s,
+                              hipStream_t st)
+{
+    return etype == 0 ? launch_hmv<uint8_t>(x, table, y, n, s, st) : launch_hmv<uint16_t>(x, table, y, n, s, st);
+}
+
+qaa_status lanczos_lowest(int n, const void *table, int etype, double s, const double *v0, int iters, int k,
+                          double *evals, hipStream_t st)
+{
+    const uint64_t dim = 1ull << n;
+    iters = (int)std::min<uint64_t>((uint64_t)iters, dim);
+    // device memory: V (iters + 1 vectors), w, the dot partials and the
+    // small coefficient arrays
+    const size_t vec = sizeof(double) * dim;
+    const size_t nparts = (size_t)(iters + 1) * kDotBlocks * kDotWaves;
+    const size_t small = sizeof(double) * (4 * (size_t)(iters + 1) + 2);
+    char *mem = nullptr;
+    const size_t bytes = vec * (size_t)(iters + 2) + sizeof(double) * nparts + small;
+    if (hipMallocAsync(reinterpret_cast<void **>(&mem), bytes, st) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(QAA_ERR_OUT_OF_MEMORY, "qaa_spectrum: Lanczos workspace allocation failed");
+    }
+    double *V = reinterpret_cast<double *>(mem);
+    double *w = V + dim * (uint64_t)(iters + 1);
+    double *partials = w + dim;
+    double *ca = partials + nparts;            // first Gram-Schmidt coefficients (iters + 1)
+    double *cb = ca + (iters + 1);             // second sweep (iters + 1)
+    double *alpha = cb + (iters + 1);
+    double *beta = alpha + (iters + 1);
+    double *nrm2 = beta + (iters + 1);
+    double *n0 = nrm2 + 1;                     // |v0|^2
+    const unsigned g = grid_for(dim);
+    hipError_t e = hipSuccess;
+    auto ok = [&]() { return (e = hipGetLastError()) == hipSuccess; };
+    // v_0 = v0 / |v0|
+    e = project(v0, 1, v0, dim, partials, n0, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(normalize_kernel, dim3(g), dim3(kThreads), 0, st, v0, V, (const double *)n0, dim,
+                           (const double *)nullptr, (const double *)nullptr, 0, (double *)nullptr,
+                           (double *)nullptr);
+        ok();
+    }
+    for (int j = 0; j < iters && e == hipSuccess; ++j) {
+        double *vj = V + dim * (uint64_t)j;
+        e = launch_hmv_product(vj, table, etype, w, n, s, st);
+        // two classical Gram-Schmidt sweeps against v_0 .. v_j
+        if (e == hipSuccess) e = project(V, j + 1, w, dim, partials, ca, st);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(update_kernel, dim3(g), dim3(kThreads), sizeof(double) * (j + 1), st, w,
+                               (const double *)V, j + 1, (const double *)ca, dim);
+            ok();
+        }
+        if (e == hipSuccess) e = project(V, j + 1, w, dim, partials, cb, st);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(update_kernel, dim3(g), dim3(kThreads), sizeof(double) * (j + 1), st, w,
+                               (const double *)V, j + 1, (const double *)cb, dim);
+            ok();
+        }
+        if (e == hipSuccess) e = project(w, 1, w, dim, partials, nrm2, st);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(normalize_kernel, dim3(g), dim3(kThreads), 0, st, (const double *)w,
+                               V + dim * (uint64_t)(j + 1), (const double *)nrm2, dim, (const double *)ca,
+                               (const double *)cb, j, alpha, beta);
+            ok();
+        }
+    }
+    std::vector<double> a((size_t)iters), b((size_t)iters);
+    double v0_norm2 = 0.0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&v0_norm2, n0, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(a.data(), alpha, sizeof(double) * iters, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.data(), beta, sizeof(double) * iters, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFreeAsync(mem, st);
+    if (e != hipSuccess) return set_error(QAA_ERR_DEVICE, (std::string("qaa_spectrum: ") + hipGetErrorString(e)).c_str());
+    if (!(v0_norm2 > 0.0) || !std::isfinite(v0_norm2))
+        return set_error(QAA_ERR_INVALID_ARG, "qaa_spectrum: the start vector v0 is zero or not finite");
+    // The Krylov space closes at the first negligible beta: T splits there
+    // and only its leading block belongs to the start vector's space.
+    double scale = 0.0;
+    for (int j = 0; j < iters; ++j) scale = std::max(scale, std::fabs(a[j]) + 2.0 * b[j]);
+    int m = iters;
+    for (int j = 0; j + 1 < iters; ++j)
+        if (!(b[j] > 1e-12 * std::max(scale, 1.0))) {
+            m = j + 1;
+            break;
+        }
+    // Levels, not Ritz values: once the start vector's Krylov space is used
+    // up, rounding feeds in directions outside it and a degenerate level can
+    // show up again (a genuine second eigenvector); values closer than
+    // 1e-10 of the matrix scale count as one level.
+    const double merge = 1e-10 * std::max(scale, 1.0);
+    int got = 0;
+    for (int i = 0; i < m && got < k; ++i) {
+        const double x = tridiag_eig(a, b, m, i);
+        if (got == 0 || x - evals[got - 1] > merge) evals[got++] = x;
+    }
+    for (int i = got; i < k; ++i) evals[i] = NAN;
+    return QAA_OK;
+}
+
+}  // namespace qaa

@@ -96,8 +96,59 @@ def test_evolve_rejects_before_any_device_call():
         assert lib.qaa_observables(ctypes.byref(st), ctypes.byref(out), None) == qaa.QAA_ERR_NOT_READY
         assert lib.qaa_energy_table(h, None, 0, None) == qaa.QAA_ERR_INVALID_ARG
         assert lib.qaa_energy_table(h, 0x1000, 5, None) == qaa.QAA_ERR_INVALID_ARG
-        assert lib.qaa_evolve_batch(-1, None, None, None, None) == qaa.QAA_ERR_INVALID_ARG
-        assert lib.qaa_evolve_batch(0, None, None, None, None) == qaa.QAA_OK
+        assert lib.qaa_evolve_batch(-1, None, None, None, None, None) == qaa.QAA_ERR_INVALID_ARG
+        assert lib.qaa_evolve_batch(0, None, None, None, None, None) == qaa.QAA_OK
+    finally:
+        qaa.qaa_instance_destroy(h)
+
+
+@pytest.mark.parametrize("sched,msg", [
+    (dict(kind=7), "unknown schedule kind"),
+    (dict(kind=1, count=1, values=[0.0]), "2..256 knots"),
+    (dict(kind=1, count=257, values=[0.5] * 257), "2..256 knots"),
+    (dict(kind=1, count=3, values=None), "values is NULL"),
+    (dict(kind=1, count=3, values=[0.0, float("nan"), 1.0]), "knot 1"),
+    (dict(kind=1, count=3, values=[0.0, 0.5, 1.5]), "knot 2"),
+    (dict(kind=1, count=2, values=[-0.25, 1.0]), "knot 0"),
+])
+def test_bad_schedules_are_rejected(sched, msg):
+    """Schedule tables are checked before anything touches the device, in
+    every call that takes one."""
+    vals = sched.get("values")
+    arr = None if vals is None else (ctypes.c_double * len(vals))(*vals)
+    sc = qaa.qaa_schedule(sched["kind"], sched.get("count", 0),
+                          None if arr is None else ctypes.cast(arr, ctypes.POINTER(ctypes.c_double)))
+    h = qaa.qaa_instance_create(5, [1, 2, 3])
+    try:
+        st = qaa.qaa_state(h, 0x1000, qaa.QAA_C64, 0x2000, qaa.QAA_E_U8)
+        lib = qaa._lib
+        assert lib.qaa_evolve(ctypes.byref(st), ctypes.byref(sc), 1.0, 10, None) == qaa.QAA_ERR_INVALID_ARG
+        assert msg in qaa.qaa_last_error()
+        assert lib.qaa_evolve_range(ctypes.byref(st), ctypes.byref(sc), 1.0, 10, 0, 5, None) == \
+            qaa.QAA_ERR_INVALID_ARG
+        states = (qaa.qaa_state * 1)(st)
+        scheds = (qaa.qaa_schedule * 1)(sc)
+        t_arr = (ctypes.c_double * 1)(1.0)
+        n_arr = (ctypes.c_int64 * 1)(10)
+        assert lib.qaa_evolve_batch(1, states, scheds, t_arr, n_arr, None) == qaa.QAA_ERR_INVALID_ARG
+        assert msg in qaa.qaa_last_error()
+        cnt, size = ctypes.c_int32(), ctypes.c_int32()
+        assert lib.qaa_debug_pass_descs(20, 0, 10, ctypes.byref(sc), 1.0, 10, 0, 10, None, 0, ctypes.byref(cnt),
+                                        ctypes.byref(size)) == qaa.QAA_ERR_INVALID_ARG
+    finally:
+        qaa.qaa_instance_destroy(h)
+
+
+def test_good_schedule_passes_to_the_state_checks():
+    """A valid table gets past the schedule check (the missing energy table
+    is what stops it), and the linear kind ignores count and values."""
+    h = qaa.qaa_instance_create(5, [1, 2, 3])
+    try:
+        st = qaa.qaa_state(h, 0x1000, qaa.QAA_C64, 0x2000, qaa.QAA_E_U8)
+        lib = qaa._lib
+        for sc in (qaa.make_schedule([0.0, 0.3, 1.0]), qaa.make_schedule([1.0] * 256),
+                   qaa.qaa_schedule(qaa.QAA_SCHED_LINEAR, 99, None)):
+            assert lib.qaa_evolve(ctypes.byref(st), ctypes.byref(sc), 1.0, 10, None) == qaa.QAA_ERR_NOT_READY
     finally:
         qaa.qaa_instance_destroy(h)
 
@@ -175,3 +226,32 @@ def test_plan_choice_defaults_set_and_reset():
     assert lib.qaa_plan_set(35, 0, None) == qaa.QAA_ERR_INVALID_ARG
     assert lib.qaa_plan_get(28, 0, None) == qaa.QAA_ERR_INVALID_ARG
     assert lib.qaa_autotune(None, 10, None, None, None) == qaa.QAA_ERR_INVALID_ARG
+
+
+def test_spectrum_rejects_before_any_device_call():
+    h = qaa.qaa_instance_create(5, [1, 2, 3])
+    lib = qaa._lib
+    s_ok = (ctypes.c_double * 2)(0.2, 0.8)
+    out = (ctypes.c_double * 8)()
+    try:
+        def call(inst=h, table=0x1000, etype=0, count=2, svals=s_ok, v0=0x2000, iters=10, k=2, ev=out):
+            return lib.qaa_spectrum(inst, table, etype, count, svals, v0, iters, k, ev, None)
+        assert call(inst=None) == qaa.QAA_ERR_INVALID_ARG
+        assert call(table=None) == qaa.QAA_ERR_INVALID_ARG
+        assert call(v0=None) == qaa.QAA_ERR_INVALID_ARG
+        assert call(etype=4) == qaa.QAA_ERR_INVALID_ARG
+        assert call(count=-1) == qaa.QAA_ERR_INVALID_ARG
+        assert call(svals=None) == qaa.QAA_ERR_INVALID_ARG
+        assert call(iters=0) == qaa.QAA_ERR_INVALID_ARG
+        assert call(iters=qaa.QAA_SPECTRUM_MAX_ITERS + 1) == qaa.QAA_ERR_INVALID_ARG
+        assert call(k=0) == qaa.QAA_ERR_INVALID_ARG
+        assert call(k=11) == qaa.QAA_ERR_INVALID_ARG
+        bad = (ctypes.c_double * 2)(0.2, 1.5)
+        assert call(svals=bad) == qaa.QAA_ERR_INVALID_ARG
+        assert "s_values[1]" in qaa.qaa_last_error()
+        assert call(v0=0x2004) == qaa.QAA_ERR_INVALID_ARG
+        # everything valid but no energy table yet
+        assert call() == qaa.QAA_ERR_NOT_READY
+        assert call(count=0) == qaa.QAA_ERR_NOT_READY
+    finally:
+        qaa.qaa_instance_destroy(h)

@@ -31,14 +31,14 @@ def _pad(l, dtype):
     return l + (2 * (l >> 5) if dtype == 0 else (l >> 4))
 
 
-def _replay(n, dtype, E, psi, T, N, k0, k1):
+def _replay(n, dtype, E, psi, T, N, k0, k1, knots=None):
     plan = qaa.qaa_plan_info(n, dtype)
     TB = plan["tile_bits"]
     RB = 5 if dtype == qaa.QAA_C64 else 4
     WB = TB - RB
     R, WG = 1 << RB, 1 << WB
     TSP = _pad(1 << TB, dtype)
-    descs = qaa.qaa_debug_pass_descs(n, dtype, int(E.max()), T, N, k0, k1)
+    descs = qaa.qaa_debug_pass_descs(n, dtype, int(E.max()), T, N, k0, k1, knots)
     tid = np.arange(WG, dtype=np.int64)
     reg = np.arange(R, dtype=np.int64)
     for d in descs:
@@ -185,3 +185,55 @@ def test_pass_plan_range_replay():
 def test_pass_descs_for_whole_tile_states_are_empty():
     assert qaa.qaa_debug_pass_descs(13, 0, 10, 5.0, 10, 0, 10) == []
     assert qaa.qaa_debug_pass_descs(20, 0, 10, 5.0, 10, 3, 3) == []
+
+
+def _tables():
+    rng = np.random.default_rng(11)
+    return {
+        "3 knots": [0.0, 0.7, 1.0],
+        "17 knots, slow middle": list(0.5 + 0.5 * np.sin(np.linspace(-np.pi / 2, np.pi / 2, 17)) ** 3),
+        "256 random knots": list(np.sort(rng.random(256))),
+        "non-monotone": [0.0, 0.9, 0.2, 1.0],
+    }
+
+
+@pytest.mark.parametrize("name,n,dtype,T,N",
+                         [(name, n, dt, T, N) for name in _tables() for (n, dt, T, N) in ((16, 0, 6.0, 5),
+                                                                                          (15, 1, 7.0, 4))]
+                         + [("256 random knots", 22, 0, 5.0, 3)])      # three qubit sets
+def test_table_schedule_replays_the_oracle(name, n, dtype, T, N):
+    """The host planner's coefficients for a schedule table (every pass kind,
+    merged phases between steps of different s) give the oracle's result."""
+    knots = _tables()[name]
+    inst = planted_unique_3sat(n, 800 + n)
+    E = oracle.energy(n, inst.clauses).astype(np.int64)
+    psi = np.full(1 << n, 2.0 ** (-n / 2), np.complex128)
+    got, _ = _replay(n, dtype, E, psi, T, N, 0, N, knots)
+    ref = oracle.init_uniform(n)
+    oracle.evolve(n, inst.clauses, ref, T, N, knots=knots)
+    assert np.max(np.abs(got - ref)) < 1e-12
+    # and the table really changes the result
+    lin = oracle.init_uniform(n)
+    oracle.evolve(n, inst.clauses, lin, T, N)
+    assert np.max(np.abs(lin - ref)) > 1e-4
+
+
+def test_table_schedule_range_replay():
+    n, T, N = 17, 5.0, 9
+    knots = [0.0, 0.2, 0.25, 0.3, 1.0]
+    inst = planted_unique_3sat(n, 9)
+    E = oracle.energy(n, inst.clauses).astype(np.int64)
+    psi = np.full(1 << n, 2.0 ** (-n / 2), np.complex128)
+    psi, _ = _replay(n, 0, E, psi, T, N, 0, 5, knots)
+    psi, _ = _replay(n, 0, E, psi, T, N, 5, N, knots)
+    ref = oracle.init_uniform(n)
+    oracle.evolve(n, inst.clauses, ref, T, N, knots=knots)
+    assert np.max(np.abs(psi - ref)) < 1e-12
+
+
+def test_two_knot_table_is_the_linear_schedule_to_the_bit():
+    a = qaa.qaa_debug_pass_descs(20, 0, 30, 9.0, 7, 0, 7)
+    b = qaa.qaa_debug_pass_descs(20, 0, 30, 9.0, 7, 0, 7, [0.0, 1.0])
+    assert len(a) == len(b) > 0
+    for x, y in zip(a, b):
+        assert bytes(x) == bytes(y)
