@@ -1268,11 +1268,10 @@ extern "C" qaa_status qaa_spectrum(const qaa_instance *inst, const void *table, 
             return fail(QAA_ERR_INVALID_ARG, "%s: s_values[%d] is not in [0, 1]", who, i);
     if (reinterpret_cast<uintptr_t>(v0) % 8) return fail(QAA_ERR_INVALID_ARG, "%s: v0 must be 8-byte aligned", who);
     if (inst->e_max < 0) return fail(QAA_ERR_NOT_READY, "%s: qaa_energy_table has not run for this instance", who);
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    for (int i = 0; i < count; ++i) {
-        qaa_status r = lanczos_lowest(inst->n, table, (int)etype, s_values[i], v0, iters, k, evals + (size_t)i * k, s);
-        if (r != QAA_OK) return r;
-    }
+    if (count == 0) return ok();
+    qaa_status r = lanczos_lowest(inst->n, table, (int)etype, count, s_values, v0, iters, k, evals,
+                                  reinterpret_cast<hipStream_t>(stream));
+    if (r != QAA_OK) return r;
     return ok();
 }
 

@@ -204,11 +204,11 @@ int observables_blocks(int n);
 // y = H(s) x for real FP64 vectors of 2^n entries (spectrum.hip).
 hipError_t launch_hmv_product(const double *x, const void *table, int etype, double *y, int n, double s,
                               hipStream_t st);
-// The k lowest Ritz values of H(s) after `iters` Lanczos steps from v0
-// (device), into the host array evals (NaN past the Krylov dimension).
-// Synchronous on st.
-qaa_status lanczos_lowest(int n, const void *table, int etype, double s, const double *v0, int iters, int k,
-                          double *evals, hipStream_t st);
+// The k lowest levels of H(s) after `iters` Lanczos steps from v0
+// (device) for each of the count values s_values[i], into the host array
+// evals[i * k ..] (NaN where fewer were found).  Synchronous on st.
+qaa_status lanczos_lowest(int n, const void *table, int etype, int count, const double *s_values, const double *v0,
+                          int iters, int k, double *evals, hipStream_t st);
 
 // Sets the calling thread's qaa_last_error() message (cleared for QAA_OK)
 // and returns st.

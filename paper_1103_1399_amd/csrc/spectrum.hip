@@ -210,76 +210,13 @@ hipError_t launch_hmv_product(const double *x, const void *table, int etype, dou
     return etype == 0 ? launch_hmv<uint8_t>(x, table, y, n, s, st) : launch_hmv<uint16_t>(x, table, y, n, s, st);
 }
 
-qaa_status lanczos_lowest(int n, const void *table, int etype, double s, const double *v0, int iters, int k,
-                          double *evals, hipStream_t st)
+namespace {
+
+// The lowest k levels of the tridiagonal matrix (alpha a, beta b) that a
+// Lanczos run produced, into evals (NaN where fewer were found).
+void levels_from_tridiag(const std::vector<double> &a, const std::vector<double> &b, int iters, int k,
+                         double *evals)
 {
-    const uint64_t dim = 1ull << n;
-    iters = (int)std::min<uint64_t>((uint64_t)iters, dim);
-    // device memory: V (iters + 1 vectors), w, the dot partials and the
-    // small coefficient arrays
-    const size_t vec = sizeof(double) * dim;
-    const size_t nparts = (size_t)(iters + 1) * kDotBlocks * kDotWaves;
-    const size_t small = sizeof(double) * (4 * (size_t)(iters + 1) + 2);
-    char *mem = nullptr;
-    const size_t bytes = vec * (size_t)(iters + 2) + sizeof(double) * nparts + small;
-    if (hipMallocAsync(reinterpret_cast<void **>(&mem), bytes, st) != hipSuccess) {
-        (void)hipGetLastError();
-        return set_error(QAA_ERR_OUT_OF_MEMORY, "qaa_spectrum: Lanczos workspace allocation failed");
-    }
-    double *V = reinterpret_cast<double *>(mem);
-    double *w = V + dim * (uint64_t)(iters + 1);
-    double *partials = w + dim;
-    double *ca = partials + nparts;            // first Gram-Schmidt coefficients (iters + 1)
-    double *cb = ca + (iters + 1);             // second sweep (iters + 1)
-    double *alpha = cb + (iters + 1);
-    double *beta = alpha + (iters + 1);
-    double *nrm2 = beta + (iters + 1);
-    double *n0 = nrm2 + 1;                     // |v0|^2
-    const unsigned g = grid_for(dim);
-    hipError_t e = hipSuccess;
-    auto ok = [&]() { return (e = hipGetLastError()) == hipSuccess; };
-    // v_0 = v0 / |v0|
-    e = project(v0, 1, v0, dim, partials, n0, st);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(normalize_kernel, dim3(g), dim3(kThreads), 0, st, v0, V, (const double *)n0, dim,
-                           (const double *)nullptr, (const double *)nullptr, 0, (double *)nullptr,
-                           (double *)nullptr);
-        ok();
-    }
-    for (int j = 0; j < iters && e == hipSuccess; ++j) {
-        double *vj = V + dim * (uint64_t)j;
-        e = launch_hmv_product(vj, table, etype, w, n, s, st);
-        // two classical Gram-Schmidt sweeps against v_0 .. v_j
-        if (e == hipSuccess) e = project(V, j + 1, w, dim, partials, ca, st);
-        if (e == hipSuccess) {
-            hipLaunchKernelGGL(update_kernel, dim3(g), dim3(kThreads), sizeof(double) * (j + 1), st, w,
-                               (const double *)V, j + 1, (const double *)ca, dim);
-            ok();
-        }
-        if (e == hipSuccess) e = project(V, j + 1, w, dim, partials, cb, st);
-        if (e == hipSuccess) {
-            hipLaunchKernelGGL(update_kernel, dim3(g), dim3(kThreads), sizeof(double) * (j + 1), st, w,
-                               (const double *)V, j + 1, (const double *)cb, dim);
-            ok();
-        }
-        if (e == hipSuccess) e = project(w, 1, w, dim, partials, nrm2, st);
-        if (e == hipSuccess) {
-            hipLaunchKernelGGL(normalize_kernel, dim3(g), dim3(kThreads), 0, st, (const double *)w,
-                               V + dim * (uint64_t)(j + 1), (const double *)nrm2, dim, (const double *)ca,
-                               (const double *)cb, j, alpha, beta);
-            ok();
-        }
-    }
-    std::vector<double> a((size_t)iters), b((size_t)iters);
-    double v0_norm2 = 0.0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&v0_norm2, n0, sizeof(double), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(a.data(), alpha, sizeof(double) * iters, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(b.data(), beta, sizeof(double) * iters, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFreeAsync(mem, st);
-    if (e != hipSuccess) return set_error(QAA_ERR_DEVICE, (std::string("qaa_spectrum: ") + hipGetErrorString(e)).c_str());
-    if (!(v0_norm2 > 0.0) || !std::isfinite(v0_norm2))
-        return set_error(QAA_ERR_INVALID_ARG, "qaa_spectrum: the start vector v0 is zero or not finite");
     // The Krylov space closes at the first negligible beta: T splits there
     // and only its leading block belongs to the start vector's space.
     double scale = 0.0;
@@ -301,6 +238,88 @@ qaa_status lanczos_lowest(int n, const void *table, int etype, double s, const d
         if (got == 0 || x - evals[got - 1] > merge) evals[got++] = x;
     }
     for (int i = got; i < k; ++i) evals[i] = NAN;
+}
+
+}  // namespace
+
+qaa_status lanczos_lowest(int n, const void *table, int etype, int count, const double *s_values, const double *v0,
+                          int iters, int k, double *evals, hipStream_t st)
+{
+    const uint64_t dim = 1ull << n;
+    iters = (int)std::min<uint64_t>((uint64_t)iters, dim);
+    // device memory, taken once for all values of s: V (iters + 1 vectors),
+    // w, the dot partials and the small coefficient arrays
+    const size_t vec = sizeof(double) * dim;
+    const size_t nparts = (size_t)(iters + 1) * kDotBlocks * kDotWaves;
+    const size_t small = sizeof(double) * (4 * (size_t)(iters + 1) + 2);
+    char *mem = nullptr;
+    const size_t bytes = vec * (size_t)(iters + 2) + sizeof(double) * nparts + small;
+    if (hipMallocAsync(reinterpret_cast<void **>(&mem), bytes, st) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(QAA_ERR_OUT_OF_MEMORY, "qaa_spectrum: Lanczos workspace allocation failed");
+    }
+    double *V = reinterpret_cast<double *>(mem);
+    double *w = V + dim * (uint64_t)(iters + 1);
+    double *partials = w + dim;
+    double *ca = partials + nparts;            // first Gram-Schmidt coefficients (iters + 1)
+    double *cb = ca + (iters + 1);             // second sweep (iters + 1)
+    double *alpha = cb + (iters + 1);
+    double *beta = alpha + (iters + 1);
+    double *nrm2 = beta + (iters + 1);
+    double *n0 = nrm2 + 1;                     // |v0|^2
+    const unsigned g = grid_for(dim);
+    hipError_t e = hipSuccess;
+    auto ok = [&]() { return (e = hipGetLastError()) == hipSuccess; };
+    std::vector<double> a((size_t)iters), b((size_t)iters);
+    double v0_norm2 = 0.0;
+    for (int si = 0; si < count && e == hipSuccess; ++si) {
+        const double s = s_values[si];
+        // v_0 = v0 / |v0|
+        e = project(v0, 1, v0, dim, partials, n0, st);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(normalize_kernel, dim3(g), dim3(kThreads), 0, st, v0, V, (const double *)n0, dim,
+                               (const double *)nullptr, (const double *)nullptr, 0, (double *)nullptr,
+                               (double *)nullptr);
+            ok();
+        }
+        for (int j = 0; j < iters && e == hipSuccess; ++j) {
+            double *vj = V + dim * (uint64_t)j;
+            e = launch_hmv_product(vj, table, etype, w, n, s, st);
+            // two classical Gram-Schmidt sweeps against v_0 .. v_j
+            if (e == hipSuccess) e = project(V, j + 1, w, dim, partials, ca, st);
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(update_kernel, dim3(g), dim3(kThreads), sizeof(double) * (j + 1), st, w,
+                                   (const double *)V, j + 1, (const double *)ca, dim);
+                ok();
+            }
+            if (e == hipSuccess) e = project(V, j + 1, w, dim, partials, cb, st);
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(update_kernel, dim3(g), dim3(kThreads), sizeof(double) * (j + 1), st, w,
+                                   (const double *)V, j + 1, (const double *)cb, dim);
+                ok();
+            }
+            if (e == hipSuccess) e = project(w, 1, w, dim, partials, nrm2, st);
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(normalize_kernel, dim3(g), dim3(kThreads), 0, st, (const double *)w,
+                                   V + dim * (uint64_t)(j + 1), (const double *)nrm2, dim, (const double *)ca,
+                                   (const double *)cb, j, alpha, beta);
+                ok();
+            }
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(&v0_norm2, n0, sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(a.data(), alpha, sizeof(double) * iters, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(b.data(), beta, sizeof(double) * iters, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) break;
+        if (!(v0_norm2 > 0.0) || !std::isfinite(v0_norm2)) {
+            (void)hipFreeAsync(mem, st);
+            return set_error(QAA_ERR_INVALID_ARG, "qaa_spectrum: the start vector v0 is zero or not finite");
+        }
+        levels_from_tridiag(a, b, iters, k, evals + (size_t)si * k);
+    }
+    (void)hipFreeAsync(mem, st);
+    if (e != hipSuccess)
+        return set_error(QAA_ERR_DEVICE, (std::string("qaa_spectrum: ") + hipGetErrorString(e)).c_str());
     return QAA_OK;
 }
 

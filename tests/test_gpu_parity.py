@@ -424,6 +424,30 @@ def test_full_size_c64_vs_c128_first_steps(qaa):
     assert abs(oa["norm"] - 1.0) < 1e-5
 
 
+def test_full_size_first_steps_vs_oracle(qaa):
+    """n = 28 seed 0, T = 50, steps 0..1 of 5000 in the benchmark's launch
+    configuration (complex64, uint8 table, the three-set pass plan), against
+    the complex128 CPU oracle over the whole state vector."""
+    n, T, N, K = 28, 50.0, 5000, 2
+    inst_in = planted_unique_3sat(n, 0)
+    inst = qaa.Instance(n, inst_in.literals())
+    table = inst.energy_table()
+    a = qaa.State(inst, table, dtype=torch.complex64).init_uniform()
+    a.evolve_range(T, N, 0, K)
+    oa = a.observables()
+    got = a.amp.cpu().numpy()
+    del a, table
+    torch.cuda.empty_cache()
+    psi = oracle.init_uniform(n)
+    oracle.evolve(n, inst_in.clauses, psi, T, N, 0, K)
+    ref = oracle.observables(n, inst_in.clauses, psi)
+    l2 = float(np.sqrt(np.sum(np.abs(got.astype(np.complex128) - psi) ** 2)))
+    assert l2 <= L2_TOL_C64, l2
+    assert abs(oa["p_success"] - ref["p_success"]) <= P_TOL_C64
+    assert abs(oa["energy"] - ref["energy"]) <= 1e-4 * max(1.0, ref["energy"])
+    del psi, got
+
+
 def test_full_size_full_job_c64_vs_c128(qaa):
     """The benchmark's job in full (n = 28 seed 0, T = 50, 5000 steps):
     complex64 against the complex128 GPU path at the workload's tolerances
