@@ -51,35 +51,56 @@ hmv_kernel(const double *__restrict__ x, const ET *__restrict__ E, double *__res
     }
 }
 
-// partials[(j * gridDim.x + block) * kDotWaves + wave] = this wave's part
-// of V_j . w, for j < k (V_j = V + j * dim).
-__global__ void __launch_bounds__(kThreads)
-dots_kernel(const double *__restrict__ V, int k, const double *__restrict__ w, uint64_t dim,
-            double *__restrict__ partials)
+// This workgroup's part of V_j . w for the G vectors j0 .. j0+G-1, into
+// partials[j * gridDim.x + block] (lanes summed by butterflies, then the
+// four waves in order through LDS).  G is a compile-time
+// count so that the G loads of an element are issued back to back (a
+// run-time guard per load would make each one wait for the previous).
+template <int G>
+__device__ __forceinline__ void dots_group(const double *__restrict__ V, int j0, const double *__restrict__ w,
+                                           uint64_t dim, double *__restrict__ partials)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t e0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
-    for (int j0 = 0; j0 < k; j0 += kDotGroup) {
-        const int g = min(kDotGroup, k - j0);
-        double p[kDotGroup];
+    double p[G];
 #pragma unroll
-        for (int i = 0; i < kDotGroup; ++i) p[i] = 0.0;
-        for (uint64_t e = e0; e < dim; e += stride) {
-            const double we = w[e];
+    for (int i = 0; i < G; ++i) p[i] = 0.0;
+    for (uint64_t e = e0; e < dim; e += stride) {
+        const double we = w[e];
+        double v[G];
 #pragma unroll
-            for (int i = 0; i < kDotGroup; ++i)
-                if (i < g) p[i] = fma(V[(uint64_t)(j0 + i) * dim + e], we, p[i]);
-        }
+        for (int i = 0; i < G; ++i) v[i] = V[(uint64_t)(j0 + i) * dim + e];
 #pragma unroll
-        for (int i = 0; i < kDotGroup; ++i) {
-            if (i >= g) break;
-            double t = p[i];
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-            if (lane == 0) partials[((uint64_t)(j0 + i) * gridDim.x + blockIdx.x) * kDotWaves + wave] = t;
-        }
+        for (int i = 0; i < G; ++i) p[i] = fma(v[i], we, p[i]);
     }
+    __shared__ double red[kDotGroup][kDotWaves];
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+        double t = p[i];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+        if (lane == 0) red[i][wave] = t;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < G) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < kDotWaves; ++q) t += red[threadIdx.x][q];
+        partials[(uint64_t)(j0 + (int)threadIdx.x) * gridDim.x + blockIdx.x] = t;
+    }
+    __syncthreads();      // red is rewritten by the next group
+}
+
+// Partial dot products V_j . w for j < k (V_j = V + j * dim): groups of
+// kDotGroup vectors per sweep over w, then the remaining ones one by one.
+__global__ void __launch_bounds__(kThreads)
+dots_kernel(const double *__restrict__ V, int k, const double *__restrict__ w, uint64_t dim,
+            double *__restrict__ partials)
+{
+    int j0 = 0;
+    for (; j0 + kDotGroup <= k; j0 += kDotGroup) dots_group<kDotGroup>(V, j0, w, dim, partials);
+    for (; j0 < k; ++j0) dots_group<1>(V, j0, w, dim, partials);
 }
 
 // out[j] = sum of the np partials of vector j, in a fixed order (block j).
@@ -191,14 +212,13 @@ hipError_t launch_hmv(const double *x, const void *table, double *y, int n, doub
     return hipGetLastError();
 }
 
-// c[0..k) = V[0..k)^T w, through `partials` (k * kDotBlocks * kDotWaves).
+// c[0..k) = V[0..k)^T w, through `partials` (k * kDotBlocks).
 hipError_t project(const double *V, int k, const double *w, uint64_t dim, double *partials, double *c,
                    hipStream_t st)
 {
     const unsigned nb = (unsigned)std::min<uint64_t>(kDotBlocks, (dim + kThreads - 1) / kThreads);
     hipLaunchKernelGGL(dots_kernel, dim3(nb), dim3(kThreads), 0, st, V, k, w, dim, partials);
-    hipLaunchKernelGGL(sum_partials_kernel, dim3((unsigned)k), dim3(kThreads), 0, st, partials,
-                       (int)(nb * kDotWaves), c);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3((unsigned)k), dim3(kThreads), 0, st, partials, (int)nb, c);
     return hipGetLastError();
 }
 
@@ -250,7 +270,7 @@ qaa_status lanczos_lowest(int n, const void *table, int etype, int count, const 
     // device memory, taken once for all values of s: V (iters + 1 vectors),
     // w, the dot partials and the small coefficient arrays
     const size_t vec = sizeof(double) * dim;
-    const size_t nparts = (size_t)(iters + 1) * kDotBlocks * kDotWaves;
+    const size_t nparts = (size_t)(iters + 1) * kDotBlocks;
     const size_t small = sizeof(double) * (4 * (size_t)(iters + 1) + 2);
     char *mem = nullptr;
     const size_t bytes = vec * (size_t)(iters + 2) + sizeof(double) * nparts + small;

@@ -107,3 +107,13 @@ def test_zero_start_vector_is_reported(qaa):
     with pytest.raises(qaa.QaaError) as ei:
         inst.spectrum(table, [0.5], torch.zeros(1 << n, dtype=torch.float64, device="cuda"), iters=10, k=1)
     assert ei.value.status == qaa.QAA_ERR_INVALID_ARG
+
+
+def test_uint16_table_gives_the_same_levels(qaa):
+    n = 13
+    cl, inst, table = _setup(qaa, n, 1304)
+    t16 = inst.energy_table(etype=qaa.QAA_E_U16)
+    v0 = _v0(n, 6)
+    a = inst.spectrum(table, [0.45], v0, iters=100, k=2)
+    b = inst.spectrum(t16, [0.45], v0, iters=100, k=2)
+    assert np.array_equal(a, b)
