@@ -193,7 +193,22 @@ def qaa_instance_info(handle: int) -> dict:
     return {"n": n.value, "m": m.value, "e_min": emin.value, "e_max": emax.value, "degeneracy": deg.value}
 
 
+def _check_buffer(t, n: int, elem_bytes: int, what: str) -> None:
+    """The C ABI takes bare device pointers and cannot see buffer sizes: a
+    tensor handed to it must be a contiguous device tensor holding at least
+    2^n elements of the expected width."""
+    if not getattr(t, "is_cuda", False):
+        raise TypeError("%s must be a device tensor" % what)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    if t.element_size() != elem_bytes:
+        raise TypeError("%s must have %d-byte elements" % (what, elem_bytes))
+    if t.numel() < (1 << n):
+        raise ValueError("%s holds %d elements, needs 2^%d" % (what, t.numel(), n))
+
+
 def qaa_energy_table(handle: int, table, etype: int, stream=None) -> None:
+    _check_buffer(table, qaa_instance_info(handle)["n"], 1 if int(etype) == QAA_E_U8 else 2, "energy table")
     _check(_lib.qaa_energy_table(handle, table.data_ptr(), int(etype), _stream_ptr(stream)), "qaa_energy_table")
 
 
@@ -205,11 +220,12 @@ def make_state(handle: int, amp, table=None, etype: int | None = None) -> qaa_st
         dt = QAA_C128
     else:
         raise TypeError("amplitudes must be complex64 or complex128")
-    if not amp.is_contiguous():
-        raise ValueError("amplitudes must be contiguous")
+    n = qaa_instance_info(handle)["n"]
+    _check_buffer(amp, n, amp.element_size(), "amplitudes")
     if table is not None:
         if etype is None:
             etype = QAA_E_U8 if table.dtype == torch.uint8 else QAA_E_U16
+        _check_buffer(table, n, 1 if etype == QAA_E_U8 else 2, "energy table")
         tp = table.data_ptr()
     else:
         tp, etype = None, QAA_E_U8
@@ -265,8 +281,11 @@ def qaa_spectrum(handle: int, table, etype: int, s_values, v0, iters: int, k: in
     vector v0, float64 of length 2^n); returns a numpy array [len(s), k]."""
     import numpy as np
     import torch
-    if v0.dtype != torch.float64 or not v0.is_contiguous():
-        raise TypeError("v0 must be a contiguous float64 device tensor")
+    if v0.dtype != torch.float64:
+        raise TypeError("v0 must be a float64 device tensor")
+    n = qaa_instance_info(handle)["n"]
+    _check_buffer(v0, n, 8, "v0")
+    _check_buffer(table, n, 1 if int(etype) == QAA_E_U8 else 2, "energy table")
     sv = [float(x) for x in s_values]
     cnt = len(sv)
     s_arr = (ctypes.c_double * max(1, cnt))(*sv)

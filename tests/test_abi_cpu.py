@@ -255,3 +255,23 @@ def test_spectrum_rejects_before_any_device_call():
         assert call(count=0) == qaa.QAA_ERR_NOT_READY
     finally:
         qaa.qaa_instance_destroy(h)
+
+
+def test_binding_checks_buffers_before_handing_pointers_over():
+    """The C ABI sees bare pointers; the binding refuses host tensors and
+    buffers too small for 2^n elements instead of passing them on."""
+    import torch
+    h = qaa.qaa_instance_create(6, [1, 2, 3])
+    try:
+        with pytest.raises(TypeError, match="device tensor"):
+            qaa.make_state(h, torch.zeros(64, dtype=torch.complex64))
+        with pytest.raises(TypeError, match="device tensor"):
+            qaa.qaa_energy_table(h, torch.zeros(64, dtype=torch.uint8), qaa.QAA_E_U8)
+        with pytest.raises(TypeError, match="device tensor"):
+            qaa.qaa_spectrum(h, torch.zeros(64, dtype=torch.uint8), qaa.QAA_E_U8, [0.5],
+                             torch.zeros(64, dtype=torch.float64), 10, 1)
+        with pytest.raises(TypeError, match="float64"):
+            qaa.qaa_spectrum(h, torch.zeros(64, dtype=torch.uint8), qaa.QAA_E_U8, [0.5],
+                             torch.zeros(64, dtype=torch.float32), 10, 1)
+    finally:
+        qaa.qaa_instance_destroy(h)

@@ -550,3 +550,14 @@ def test_n20_T100_10k_steps_vs_stored_oracle(qaa, rec):
     exp = np.array([complex(a, b) for a, b in rec["sample_amp"]])
     # per-amplitude error budget: a state-L2 of 1e-4 spread over 2^20 entries
     assert np.max(np.abs(got - exp)) <= 1e-4
+
+
+def test_binding_refuses_undersized_device_buffers(qaa):
+    inst = qaa.Instance(12, planted_unique_3sat(12, 5).literals())
+    small = torch.zeros(1 << 11, dtype=torch.complex64, device="cuda")
+    with pytest.raises(ValueError, match="needs 2\\^12"):
+        qaa.make_state(inst.handle, small)
+    with pytest.raises(ValueError, match="needs 2\\^12"):
+        qaa.qaa_energy_table(inst.handle, torch.zeros(1 << 11, dtype=torch.uint8, device="cuda"), qaa.QAA_E_U8)
+    with pytest.raises(TypeError, match="2-byte"):
+        qaa.qaa_energy_table(inst.handle, torch.zeros(1 << 12, dtype=torch.uint8, device="cuda"), qaa.QAA_E_U16)
