@@ -299,12 +299,13 @@ typedef struct qaa_server_result {
 qaa_status qaa_server_create(const qaa_server_config *cfg, qaa_server **out);
 
 /* Queue a solve of the instance (n, m, lits; as qaa_instance_create) for
- * total time T and `steps` steps; *ticket identifies it.  Copies lits.
- * QAA_ERR_OUT_OF_MEMORY if its footprint exceeds the whole budget (it could
- * never be admitted); QAA_ERR_INVALID_ARG for malformed arguments (clause
- * errors are reported through the result). */
-qaa_status qaa_server_submit(qaa_server *sv, int32_t n, int32_t m, const int32_t *lits, double T,
-                             int64_t steps, int64_t *ticket);
+ * total time T and `steps` steps under schedule `sched` (NULL: linear; as
+ * in qaa_evolve); *ticket identifies it.  Copies lits and the schedule's
+ * knots.  QAA_ERR_OUT_OF_MEMORY if its footprint exceeds the whole budget
+ * (it could never be admitted); QAA_ERR_INVALID_ARG for malformed arguments
+ * or a bad schedule (clause errors are reported through the result). */
+qaa_status qaa_server_submit(qaa_server *sv, int32_t n, int32_t m, const int32_t *lits,
+                             const qaa_schedule *sched, double T, int64_t steps, int64_t *ticket);
 
 /* Non-blocking status of a ticket.  A finished request's record (its
  * status, observables and times, about 100 bytes) is kept until destroy. */

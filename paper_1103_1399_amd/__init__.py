@@ -131,8 +131,8 @@ _SIGS = {
     "qaa_profile_enable": (_st, [ctypes.c_int32]),
     "qaa_profile_read": (_st, [ctypes.c_void_p, ctypes.c_int32]),
     "qaa_server_create": (_st, [ctypes.POINTER(qaa_server_config), ctypes.POINTER(_vp)]),
-    "qaa_server_submit": (_st, [_vp, ctypes.c_int32, ctypes.c_int32, _i32p, ctypes.c_double, ctypes.c_int64,
-                                _i64p]),
+    "qaa_server_submit": (_st, [_vp, ctypes.c_int32, ctypes.c_int32, _i32p, ctypes.POINTER(qaa_schedule),
+                                ctypes.c_double, ctypes.c_int64, _i64p]),
     "qaa_server_poll": (_st, [_vp, ctypes.c_int64, ctypes.POINTER(qaa_server_result)]),
     "qaa_server_wait": (_st, [_vp, ctypes.c_int64, ctypes.POINTER(qaa_server_result)]),
     "qaa_server_stats": (_st, [_vp, _i64p, _i64p, ctypes.POINTER(ctypes.c_uint64)]),
@@ -388,12 +388,13 @@ def qaa_server_create(hbm_budget_bytes: int, slots: int) -> int:
     return out.value
 
 
-def qaa_server_submit(server: int, n: int, lits, T: float, steps: int) -> int:
+def qaa_server_submit(server: int, n: int, lits, T: float, steps: int, knots=None) -> int:
     import numpy as np
     arr = np.ascontiguousarray(np.asarray(lits, dtype=np.int32).reshape(-1))
+    sched = make_schedule(knots)
     t = ctypes.c_int64()
-    _check(_lib.qaa_server_submit(server, int(n), arr.size // 3, arr.ctypes.data_as(_i32p), float(T), int(steps),
-                                  ctypes.byref(t)), "qaa_server_submit")
+    _check(_lib.qaa_server_submit(server, int(n), arr.size // 3, arr.ctypes.data_as(_i32p), ctypes.byref(sched),
+                                  float(T), int(steps), ctypes.byref(t)), "qaa_server_submit")
     return t.value
 
 

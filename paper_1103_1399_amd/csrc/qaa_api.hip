@@ -940,9 +940,11 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, 
 
 int lut_limit(qaa_etype e) { return e == QAA_E_U8 ? kLutMaxU8 : kLutMax; }
 
+}  // namespace
+
 // Validates a caller's schedule and copies it into the form the planner and
 // the kernels read (NULL and QAA_SCHED_LINEAR: count 0).
-qaa_status to_knots(const qaa_schedule *sched, SchedKnots *out, const char *who)
+qaa_status qaa::to_knots(const qaa_schedule *sched, SchedKnots *out, const char *who)
 {
     std::memset(out, 0, sizeof *out);
     if (!sched || sched->kind == QAA_SCHED_LINEAR) return QAA_OK;
@@ -961,6 +963,8 @@ qaa_status to_knots(const qaa_schedule *sched, SchedKnots *out, const char *who)
     out->count = sched->count;
     return QAA_OK;
 }
+
+namespace {
 
 qaa_status evolve_common(const qaa_state *st, const qaa_schedule *sched, double T, int64_t steps, int64_t k0,
                          int64_t k1, void *stream, const char *who)

@@ -210,6 +210,10 @@ hipError_t launch_hmv_product(const double *x, const void *table, int etype, dou
 qaa_status lanczos_lowest(int n, const void *table, int etype, int count, const double *s_values, const double *v0,
                           int iters, int k, double *evals, hipStream_t st);
 
+// Checks a caller's schedule (NULL: linear) and copies it into *out; sets
+// the thread's error message on failure.
+qaa_status to_knots(const qaa_schedule *sched, SchedKnots *out, const char *who);
+
 // Sets the calling thread's qaa_last_error() message (cleared for QAA_OK)
 // and returns st.
 qaa_status set_error(qaa_status st, const char *msg);

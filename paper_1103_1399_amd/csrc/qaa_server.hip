@@ -34,6 +34,7 @@ struct Request {
     int64_t id = 0;
     int32_t n = 0;
     std::vector<int32_t> lits;
+    std::vector<double> knots;   // schedule table (empty: linear)
     double T = 0.0;
     int64_t steps = 0;
     size_t footprint = 0;
@@ -95,7 +96,9 @@ qaa_status solve(Request &rq, hipStream_t s, std::string &err)
     if (st == QAA_OK) {
         qaa_state state{inst, amp, QAA_C64, table, et};
         st = qaa_state_init_uniform(&state, s);
-        if (st == QAA_OK) st = qaa_evolve(&state, nullptr, rq.T, rq.steps, s);
+        const qaa_schedule sched{rq.knots.empty() ? QAA_SCHED_LINEAR : QAA_SCHED_TABLE, (int32_t)rq.knots.size(),
+                                 rq.knots.empty() ? nullptr : rq.knots.data()};
+        if (st == QAA_OK) st = qaa_evolve(&state, &sched, rq.T, rq.steps, s);
         if (st == QAA_OK) st = qaa_observables(&state, &rq.obs, s);
     }
     if (st != QAA_OK) err = qaa_last_error();
@@ -140,6 +143,7 @@ void worker_main(qaa_server *sv)
         done.t_done = now_s();
         done.state = st == QAA_OK ? 2 : 3;
         std::vector<int32_t>().swap(done.lits);    // finished records keep only their results
+        std::vector<double>().swap(done.knots);
         sv->in_use -= done.footprint;
         sv->cv_work.notify_all();
         sv->cv_done.notify_all();
@@ -173,12 +177,14 @@ extern "C" qaa_status qaa_server_create(const qaa_server_config *cfg, qaa_server
     return qaa::set_error(QAA_OK, nullptr);
 }
 
-extern "C" qaa_status qaa_server_submit(qaa_server *sv, int32_t n, int32_t m, const int32_t *lits, double T,
-                                        int64_t steps, int64_t *ticket)
+extern "C" qaa_status qaa_server_submit(qaa_server *sv, int32_t n, int32_t m, const int32_t *lits,
+                                        const qaa_schedule *sched, double T, int64_t steps, int64_t *ticket)
 {
     if (!sv || !ticket) return qaa::set_error(QAA_ERR_INVALID_ARG, "qaa_server_submit: NULL argument");
     if (n < 1 || n > QAA_MAX_QUBITS || m < 0 || (m > 0 && !lits) || !(T >= 0.0) || steps < 0)
         return qaa::set_error(QAA_ERR_INVALID_ARG, "qaa_server_submit: malformed request");
+    qaa::SchedKnots sc;
+    if (qaa::to_knots(sched, &sc, "qaa_server_submit") != QAA_OK) return QAA_ERR_INVALID_ARG;
     const size_t fp = footprint_of(n);
     if (fp > sv->cfg.hbm_budget_bytes)    // could never be admitted
         return qaa::set_error(QAA_ERR_OUT_OF_MEMORY, "qaa_server_submit: footprint exceeds the HBM budget");
@@ -187,6 +193,7 @@ extern "C" qaa_status qaa_server_submit(qaa_server *sv, int32_t n, int32_t m, co
     rq.id = sv->next_id++;
     rq.n = n;
     rq.lits.assign(lits, lits + 3 * (size_t)m);
+    rq.knots.assign(sc.v, sc.v + sc.count);
     rq.T = T;
     rq.steps = steps;
     rq.footprint = fp;

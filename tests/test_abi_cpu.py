@@ -193,7 +193,7 @@ def test_server_create_rejects_bad_config():
     # calls on a NULL server are rejected, destroy ignores it
     t = ctypes.c_int64()
     lits = (ctypes.c_int32 * 3)(1, 2, 3)
-    assert lib.qaa_server_submit(None, 3, 1, lits, 1.0, 10, ctypes.byref(t)) == qaa.QAA_ERR_INVALID_ARG
+    assert lib.qaa_server_submit(None, 3, 1, lits, None, 1.0, 10, ctypes.byref(t)) == qaa.QAA_ERR_INVALID_ARG
     r = qaa.qaa_server_result()
     assert lib.qaa_server_poll(None, 1, ctypes.byref(r)) == qaa.QAA_ERR_INVALID_ARG
     assert lib.qaa_server_wait(None, 1, ctypes.byref(r)) == qaa.QAA_ERR_INVALID_ARG

@@ -19,12 +19,12 @@ def qaa():
     return m
 
 
-def _solo(qaa, n, lits, T, steps):
+def _solo(qaa, n, lits, T, steps, knots=None):
     inst = qaa.Instance(n, lits)
     table = inst.energy_table()
     st = qaa.State(inst, table)
     st.init_uniform()
-    st.evolve(T, steps)
+    st.evolve(T, steps, knots=knots)
     obs = st.observables()
     torch.cuda.synchronize()
     inst.close()
@@ -100,3 +100,27 @@ def test_server_admission_respects_budget(qaa):
         assert r["done"] and r["status"] == qaa.QAA_ERR_INVALID_ARG
     finally:
         qaa.qaa_server_destroy(sv)
+
+
+def test_server_requests_with_schedule_tables(qaa):
+    """Each request may carry its own schedule; results equal the solo runs
+    with the same table, and a bad table is refused at submit."""
+    tabs = [[0.0, 0.4, 0.5, 0.6, 1.0], None, [0.0, 0.9, 0.2, 1.0], list(np.linspace(0, 1, 256) ** 2)]
+    reqs = [(n, planted_unique_3sat(n, 400 + n).literals(), 5.0, 30) for n in (10, 14, 17, 12)]
+    sv = qaa.qaa_server_create(hbm_budget_bytes=1 << 30, slots=2)
+    try:
+        with pytest.raises(qaa.QaaError) as ei:
+            qaa.qaa_server_submit(sv, 10, reqs[0][1], 5.0, 30, knots=[0.0, 1.5])
+        assert ei.value.status == qaa.QAA_ERR_INVALID_ARG
+        tickets = [qaa.qaa_server_submit(sv, n, lits, T, steps, knots=k) for (n, lits, T, steps), k in zip(reqs, tabs)]
+        results = [qaa.qaa_server_wait(sv, t) for t in tickets]
+    finally:
+        qaa.qaa_server_destroy(sv)
+    for (n, lits, T, steps), k, r in zip(reqs, tabs, results):
+        assert r["done"] and r["status"] == qaa.QAA_OK, (n, r)
+        solo = _solo(qaa, n, lits, T, steps, knots=k)
+        for key in ("norm", "energy", "p_success"):
+            assert r[key] == solo[key], (n, key, r[key], solo[key])
+    # the tables took effect: the first request differs from its linear run
+    lin = _solo(qaa, *reqs[0])
+    assert lin["p_success"] != results[0]["p_success"]
