@@ -220,8 +220,9 @@ qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, const qaa_sc
 
 /*
  * The k lowest eigenvalues of H(s) = (1 - s) H_B + s H_P at each of `count`
- * values of s, by Lanczos with full reorthogonalisation (two classical
- * Gram-Schmidt sweeps per step) in FP64 on the device; the Ritz values of
+ * values of s, by Lanczos with full reorthogonalisation (the three-term
+ * recurrence, then one classical Gram-Schmidt sweep against every earlier
+ * vector) in FP64 on the device; the Ritz values of
  * the tridiagonal matrix come from Sturm-sequence bisection on the host.
  *   inst, table, etype : an instance and its energy table (qaa_energy_table
  *                        must have run for it; table is device memory)

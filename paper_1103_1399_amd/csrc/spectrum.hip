@@ -5,10 +5,11 @@
 //     (H x)(z) = ((1 - s) n/2 + s E(z)) x(z) - (1 - s)/2 sum_q x(z xor 2^q),
 // since H_B = sum_q (1 - sigma^x_q)/2 and sigma^x_q flips bit q of z.
 // The device runs the whole Lanczos recurrence (matrix-vector product,
-// two classical Gram-Schmidt sweeps against every earlier Lanczos vector,
-// normalisation) without a host round trip; the host reads the
-// tridiagonal coefficients once at the end and finds the lowest Ritz
-// values by Sturm-sequence bisection (Barth, Martin and Wilkinson, 1967).
+// three-term recurrence, one classical Gram-Schmidt sweep against every
+// earlier Lanczos vector, normalisation) without a host round trip; the
+// host reads the tridiagonal coefficients once at the end and finds the
+// lowest Ritz values by Sturm-sequence bisection (Barth, Martin and
+// Wilkinson, 1967).
 #include "qaa_internal.h"
 
 #include <algorithm>
@@ -139,8 +140,9 @@ update_kernel(double *__restrict__ w, const double *__restrict__ V, int k, const
 }
 
 // v = w / sqrt(*nrm2) (v = 0 if the norm is exactly 0).  Block 0 also
-// records alpha[j] = ca[j] + cb[j] (the two Gram-Schmidt coefficients of
-// the newest vector; ca == nullptr: none) and beta[j] = sqrt(*nrm2).
+// records alpha[j] = ca[j] + cb[j] (the recurrence's coefficient of the
+// newest vector and its correction from the sweep; ca == nullptr: none)
+// and beta[j] = sqrt(*nrm2).
 __global__ void __launch_bounds__(kThreads)
 normalize_kernel(const double *__restrict__ w, double *__restrict__ v, const double *__restrict__ nrm2,
                  uint64_t dim, const double *__restrict__ ca, const double *__restrict__ cb, int j,
@@ -281,8 +283,8 @@ qaa_status lanczos_lowest(int n, const void *table, int etype, int count, const 
     double *V = reinterpret_cast<double *>(mem);
     double *w = V + dim * (uint64_t)(iters + 1);
     double *partials = w + dim;
-    double *ca = partials + nparts;            // first Gram-Schmidt coefficients (iters + 1)
-    double *cb = ca + (iters + 1);             // second sweep (iters + 1)
+    double *ca = partials + nparts;            // alpha_j of the three-term recurrence (iters + 1)
+    double *cb = ca + (iters + 1);             // coefficients of the reorthogonalisation sweep (iters + 1)
     double *alpha = cb + (iters + 1);
     double *beta = alpha + (iters + 1);
     double *nrm2 = beta + (iters + 1);
@@ -305,13 +307,21 @@ qaa_status lanczos_lowest(int n, const void *table, int etype, int count, const 
         for (int j = 0; j < iters && e == hipSuccess; ++j) {
             double *vj = V + dim * (uint64_t)j;
             e = launch_hmv_product(vj, table, etype, w, n, s, st);
-            // two classical Gram-Schmidt sweeps against v_0 .. v_j
-            if (e == hipSuccess) e = project(V, j + 1, w, dim, partials, ca, st);
-            if (e == hipSuccess) {
-                hipLaunchKernelGGL(update_kernel, dim3(g), dim3(kThreads), sizeof(double) * (j + 1), st, w,
-                                   (const double *)V, j + 1, (const double *)ca, dim);
+            // three-term recurrence: w -= beta_{j-1} v_{j-1}; alpha_j = v_j . w; w -= alpha_j v_j
+            if (e == hipSuccess && j > 0) {
+                hipLaunchKernelGGL(update_kernel, dim3(g), dim3(kThreads), sizeof(double), st, w,
+                                   (const double *)(vj - dim), 1, (const double *)(beta + (j - 1)), dim);
                 ok();
             }
+            if (e == hipSuccess) e = project(vj, 1, w, dim, partials, ca + j, st);
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(update_kernel, dim3(g), dim3(kThreads), sizeof(double), st, w, (const double *)vj,
+                                   1, (const double *)(ca + j), dim);
+                ok();
+            }
+            // then one classical Gram-Schmidt sweep against v_0 .. v_j: the
+            // recurrence already removed the large components, so the sweep
+            // only takes out what rounding left (full reorthogonalisation)
             if (e == hipSuccess) e = project(V, j + 1, w, dim, partials, cb, st);
             if (e == hipSuccess) {
                 hipLaunchKernelGGL(update_kernel, dim3(g), dim3(kThreads), sizeof(double) * (j + 1), st, w,
