@@ -143,3 +143,30 @@ def test_full_size_table_driver_only_closed_form(qaa):
     expect = a ** (n - d) * b ** d
     assert np.max(np.abs(got - expect)) < 2e-6
     assert abs(obs["norm"] - 1.0) < 1e-6
+
+
+def test_batch_mixed_dtypes_and_table_types_vs_oracle(qaa):
+    """One batched call over complex64 and complex128 states with uint8 and
+    uint16 energy tables, one-workgroup and pass-plan sizes, linear and
+    table schedules: every launch group of the batch against the oracle."""
+    cases = [(9, torch.complex128, qaa.QAA_E_U8, None), (12, torch.complex128, qaa.QAA_E_U16, TABLES["slow middle"]),
+             (14, torch.complex128, qaa.QAA_E_U8, TABLES["non-monotone"]), (15, torch.complex128, qaa.QAA_E_U16, None),
+             (10, torch.complex64, qaa.QAA_E_U16, TABLES["256 knots"]), (16, torch.complex64, qaa.QAA_E_U16,
+                                                                        TABLES["slow middle"])]
+    states, ins, Ts, Ns, knots = [], [], [], [], []
+    for i, (n, dt, et, kn) in enumerate(cases):
+        inst_in = planted_unique_3sat(n, 1100 + i)
+        inst = qaa.Instance(n, inst_in.literals())
+        table = inst.energy_table(etype=et)
+        states.append(qaa.State(inst, table, dtype=dt).init_uniform())
+        ins.append(inst_in)
+        Ts.append(4.0 + i)
+        Ns.append(20 + 5 * i)
+        knots.append(kn)
+    qaa.qaa_evolve_batch([st.c for st in states], Ts, Ns, knots=knots)
+    torch.cuda.synchronize()
+    for (n, dt, et, kn), st, inst_in, T, N in zip(cases, states, ins, Ts, Ns):
+        psi = oracle.init_uniform(n)
+        oracle.evolve(n, inst_in.clauses, psi, T, N, knots=kn)
+        tol = L2_TOL_C128 if dt == torch.complex128 else L2_TOL_C64
+        _check(st, psi, inst_in.clauses, n, tol, tol if dt == torch.complex128 else P_TOL_C64)
