@@ -167,14 +167,15 @@ def run_spectrum(qaa, torch, n, points, iters, seed):
     inst.spectrum(table, svals[:1], v0, iters=min(iters, 20), k=2)     # warm-up (allocator, code objects)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev = inst.spectrum(table, svals, v0, iters=iters, k=2)
+    ev, bd = inst.spectrum(table, svals, v0, iters=iters, k=2, bounds=True)
     secs = time.perf_counter() - t0
     gaps = ev[:, 1] - ev[:, 0]
     i = int(np.argmin(gaps))
     inst.close()
     return {"n": n, "m": inst_in.m, "seed": seed, "points": points, "lanczos_steps": iters, "seconds": secs,
             "ms_per_point": secs / points * 1e3, "lanczos_steps_per_s": points * iters / secs,
-            "min_gap": float(gaps[i]), "s_at_min_gap": svals[i], "e0_at_min_gap": float(ev[i, 0])}
+            "min_gap": float(gaps[i]), "s_at_min_gap": svals[i], "e0_at_min_gap": float(ev[i, 0]),
+            "max_residual_bound": float(np.nanmax(bd))}
 
 
 def run_serving(qaa, count, rates, n_lo, n_hi, t_lo, t_hi, slots, budget):

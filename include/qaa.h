@@ -240,6 +240,12 @@ qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, const qaa_sc
  *                        matrix scale (max_j |alpha_j| + 2 beta_j, about
  *                        the spectral radius) count as one level.  NaN
  *                        where the run found fewer than k levels.
+ *   bounds             : NULL, or a host array [count][k] that receives
+ *                        the residual norm |beta_m y_m| of each returned
+ *                        Ritz value (y the unit eigenvector of the m x m
+ *                        tridiagonal matrix): H(s) has an eigenvalue
+ *                        within that distance of it.  Small bounds on the
+ *                        two lowest levels mean the gap is resolved.
  * The accuracy of the Ritz values grows with iters (the lowest converge
  * first).  SYNCHRONOUS.  Takes about (iters + 2) * 2^n * 8 bytes of device
  * memory from the stream-ordered allocator for the call:
@@ -249,7 +255,7 @@ qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, const qaa_sc
  */
 qaa_status qaa_spectrum(const qaa_instance *inst, const void *table, qaa_etype etype, int32_t count,
                         const double *s_values, const double *v0, int32_t iters, int32_t k, double *evals,
-                        void *stream);
+                        double *bounds, void *stream);
 
 /* ---------------------------------------------------------------------
  * Observables (Sec. 2.1: the result is read from the weight on the ground
@@ -383,6 +389,17 @@ qaa_status qaa_autotune(const qaa_state *scratch, int64_t steps, qaa_plan_choice
  * layout is the library's internal pass descriptor and may change between
  * versions; it exists so that host-side tests can replay the index maps.
  */
+/*
+ * Diagnostic: the host half of qaa_spectrum on a given tridiagonal matrix
+ * (diagonal alpha[0..m), off-diagonal beta[0..m-1), and beta[m-1] the
+ * residual coefficient of the last Lanczos step): the k lowest levels and,
+ * if bounds is not NULL, their residual norms, exactly as qaa_spectrum
+ * returns them.  Host memory only; exists so that host-side tests can
+ * check the eigenvalue and merging logic without a device.
+ */
+qaa_status qaa_debug_tridiag_levels(const double *alpha, const double *beta, int32_t m, int32_t k, double *evals,
+                                    double *bounds);
+
 qaa_status qaa_debug_pass_descs(int32_t n, qaa_dtype dtype, int32_t emax, const qaa_schedule *sched, double T,
                                 int64_t steps, int64_t k0, int64_t k1, void *out, int32_t capacity,
                                 int32_t *count, int32_t *desc_bytes);

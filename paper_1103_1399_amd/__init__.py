@@ -123,7 +123,8 @@ _SIGS = {
                                _i64p, _vp]),
     "qaa_observables": (_st, [ctypes.POINTER(qaa_state), ctypes.POINTER(qaa_obs), _vp]),
     "qaa_spectrum": (_st, [_vp, _vp, ctypes.c_int, ctypes.c_int32, _f64p, _vp, ctypes.c_int32, ctypes.c_int32,
-                           _f64p, _vp]),
+                           _f64p, _f64p, _vp]),
+    "qaa_debug_tridiag_levels": (_st, [_f64p, _f64p, ctypes.c_int32, ctypes.c_int32, _f64p, _f64p]),
     "qaa_plan_info": (_st, [ctypes.c_int32, ctypes.c_int, _i32p, _i32p, _i32p]),
     "qaa_debug_pass_descs": (_st, [ctypes.c_int32, ctypes.c_int, ctypes.c_int32, ctypes.POINTER(qaa_schedule),
                                    ctypes.c_double, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _vp,
@@ -276,9 +277,10 @@ def qaa_observables(state: qaa_state, stream=None) -> dict:
             "degeneracy": out.degeneracy}
 
 
-def qaa_spectrum(handle: int, table, etype: int, s_values, v0, iters: int, k: int, stream=None):
-    """The k lowest eigenvalues of H(s) at each s (Lanczos from the device
-    vector v0, float64 of length 2^n); returns a numpy array [len(s), k]."""
+def qaa_spectrum(handle: int, table, etype: int, s_values, v0, iters: int, k: int, stream=None, bounds=False):
+    """The k lowest levels of H(s) at each s (Lanczos from the device
+    vector v0, float64 of length 2^n): a numpy array [len(s), k], or with
+    bounds=True the pair (levels, residual norms)."""
     import numpy as np
     import torch
     if v0.dtype != torch.float64:
@@ -290,9 +292,29 @@ def qaa_spectrum(handle: int, table, etype: int, s_values, v0, iters: int, k: in
     cnt = len(sv)
     s_arr = (ctypes.c_double * max(1, cnt))(*sv)
     out = (ctypes.c_double * max(1, cnt * int(k)))()
+    bnd = (ctypes.c_double * max(1, cnt * int(k)))() if bounds else None
     _check(_lib.qaa_spectrum(handle, table.data_ptr(), int(etype), cnt, s_arr, v0.data_ptr(), int(iters), int(k),
-                             out, _stream_ptr(stream)), "qaa_spectrum")
-    return np.frombuffer(out, dtype=np.float64, count=cnt * int(k)).reshape(cnt, int(k)).copy()
+                             out, bnd, _stream_ptr(stream)), "qaa_spectrum")
+    ev = np.frombuffer(out, dtype=np.float64, count=cnt * int(k)).reshape(cnt, int(k)).copy()
+    if not bounds:
+        return ev
+    return ev, np.frombuffer(bnd, dtype=np.float64, count=cnt * int(k)).reshape(cnt, int(k)).copy()
+
+
+def qaa_debug_tridiag_levels(alpha, beta, k: int):
+    """Levels and residual norms qaa_spectrum would report for the
+    tridiagonal matrix (alpha, beta); host only."""
+    import numpy as np
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    if a.shape != b.shape:
+        raise ValueError("alpha and beta must have the same length (beta[m-1] is the last residual)")
+    ev = np.empty(int(k))
+    bd = np.empty(int(k))
+    _check(_lib.qaa_debug_tridiag_levels(a.ctypes.data_as(_f64p), b.ctypes.data_as(_f64p), a.size, int(k),
+                                         ev.ctypes.data_as(_f64p), bd.ctypes.data_as(_f64p)),
+           "qaa_debug_tridiag_levels")
+    return ev, bd
 
 
 def qaa_plan_info(n: int, dtype: int = QAA_C64) -> dict:
@@ -453,11 +475,11 @@ class Instance:
         qaa_energy_table(self.handle, table, etype, stream)
         return table
 
-    def spectrum(self, table, s_values, v0, iters: int, k: int, stream=None):
-        """Lowest k eigenvalues of H(s) per s (see qaa_spectrum)."""
+    def spectrum(self, table, s_values, v0, iters: int, k: int, stream=None, bounds=False):
+        """Lowest k levels of H(s) per s (see qaa_spectrum)."""
         import torch
         etype = QAA_E_U8 if table.dtype == torch.uint8 else QAA_E_U16
-        return qaa_spectrum(self.handle, table, etype, s_values, v0, iters, k, stream)
+        return qaa_spectrum(self.handle, table, etype, s_values, v0, iters, k, stream, bounds)
 
     def close(self):
         if self.handle:

@@ -1256,7 +1256,7 @@ extern "C" qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, c
 // ---------------------------------------------------------------------------
 extern "C" qaa_status qaa_spectrum(const qaa_instance *inst, const void *table, qaa_etype etype, int32_t count,
                                    const double *s_values, const double *v0, int32_t iters, int32_t k,
-                                   double *evals, void *stream)
+                                   double *evals, double *bounds, void *stream)
 {
     const char *who = "qaa_spectrum";
     if (!inst) return fail(QAA_ERR_INVALID_ARG, "%s: instance is NULL", who);
@@ -1273,7 +1273,7 @@ extern "C" qaa_status qaa_spectrum(const qaa_instance *inst, const void *table, 
     if (reinterpret_cast<uintptr_t>(v0) % 8) return fail(QAA_ERR_INVALID_ARG, "%s: v0 must be 8-byte aligned", who);
     if (inst->e_max < 0) return fail(QAA_ERR_NOT_READY, "%s: qaa_energy_table has not run for this instance", who);
     if (count == 0) return ok();
-    qaa_status r = lanczos_lowest(inst->n, table, (int)etype, count, s_values, v0, iters, k, evals,
+    qaa_status r = lanczos_lowest(inst->n, table, (int)etype, count, s_values, v0, iters, k, evals, bounds,
                                   reinterpret_cast<hipStream_t>(stream));
     if (r != QAA_OK) return r;
     return ok();

@@ -206,9 +206,10 @@ hipError_t launch_hmv_product(const double *x, const void *table, int etype, dou
                               hipStream_t st);
 // The k lowest levels of H(s) after `iters` Lanczos steps from v0
 // (device) for each of the count values s_values[i], into the host array
-// evals[i * k ..] (NaN where fewer were found).  Synchronous on st.
+// evals[i * k ..] (NaN where fewer were found), and their residual norms
+// into bounds[i * k ..] when bounds is not null.  Synchronous on st.
 qaa_status lanczos_lowest(int n, const void *table, int etype, int count, const double *s_values, const double *v0,
-                          int iters, int k, double *evals, hipStream_t st);
+                          int iters, int k, double *evals, double *bounds, hipStream_t st);
 
 // Checks a caller's schedule (NULL: linear) and copies it into *out; sets
 // the thread's error message on failure.

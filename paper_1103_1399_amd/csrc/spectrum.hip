@@ -234,10 +234,70 @@ hipError_t launch_hmv_product(const double *x, const void *table, int etype, dou
 
 namespace {
 
+// Residual norm of the Ritz pair at theta: |beta_m| |y[m-1]|, with y the
+// unit eigenvector of the leading m x m block of T at theta.  Since H is
+// symmetric, some eigenvalue of H lies within this distance of theta.  y
+// comes from inverse iteration with (T - theta I), factored by Gaussian
+// elimination with partial pivoting for tridiagonal matrices (the scheme
+// of LAPACK's dgttrf / dgtts2).
+double ritz_residual(const std::vector<double> &a, const std::vector<double> &b, int m, double theta,
+                     double beta_m, double pivmin)
+{
+    std::vector<double> dl(m), d(m), du(m), du2(m, 0.0), x(m, 1.0);
+    std::vector<char> swap(m, 0);
+    for (int i = 0; i < m; ++i) {
+        d[i] = a[i] - theta;
+        if (i + 1 < m) dl[i] = du[i] = b[i];
+    }
+    for (int i = 0; i + 1 < m; ++i) {
+        if (std::fabs(d[i]) >= std::fabs(dl[i])) {
+            if (std::fabs(d[i]) < pivmin) d[i] = pivmin;
+            const double f = dl[i] / d[i];
+            dl[i] = f;
+            d[i + 1] -= f * du[i];
+        } else {                              // interchange rows i and i + 1
+            const double f = d[i] / dl[i];
+            d[i] = dl[i];
+            dl[i] = f;
+            const double t = du[i];
+            du[i] = d[i + 1];
+            d[i + 1] = t - f * d[i + 1];
+            if (i + 2 < m) {
+                du2[i] = du[i + 1];
+                du[i + 1] = -f * du[i + 1];
+            }
+            swap[i] = 1;
+        }
+    }
+    if (std::fabs(d[m - 1]) < pivmin) d[m - 1] = pivmin;
+    for (int it = 0; it < 3; ++it) {
+        for (int i = 0; i + 1 < m; ++i) {     // L z = P x
+            if (swap[i]) {
+                const double t = x[i];
+                x[i] = x[i + 1];
+                x[i + 1] = t - dl[i] * x[i];
+            } else {
+                x[i + 1] -= dl[i] * x[i];
+            }
+        }
+        x[m - 1] /= d[m - 1];                 // U x = z
+        if (m > 1) x[m - 2] = (x[m - 2] - du[m - 2] * x[m - 1]) / d[m - 2];
+        for (int i = m - 3; i >= 0; --i) x[i] = (x[i] - du[i] * x[i + 1] - du2[i] * x[i + 2]) / d[i];
+        double nrm = 0.0;
+        for (int i = 0; i < m; ++i) nrm = std::max(nrm, std::fabs(x[i]));
+        for (int i = 0; i < m; ++i) x[i] /= nrm;
+    }
+    double nrm2 = 0.0;
+    for (int i = 0; i < m; ++i) nrm2 += x[i] * x[i];
+    return std::fabs(beta_m) * std::fabs(x[m - 1]) / std::sqrt(nrm2);
+}
+
 // The lowest k levels of the tridiagonal matrix (alpha a, beta b) that a
-// Lanczos run produced, into evals (NaN where fewer were found).
+// Lanczos run produced, into evals (NaN where fewer were found), and, if
+// bounds is not null, the residual norm of each (a distance within which
+// H has an eigenvalue).
 void levels_from_tridiag(const std::vector<double> &a, const std::vector<double> &b, int iters, int k,
-                         double *evals)
+                         double *evals, double *bounds)
 {
     // The Krylov space closes at the first negligible beta: T splits there
     // and only its leading block belongs to the start vector's space.
@@ -254,18 +314,35 @@ void levels_from_tridiag(const std::vector<double> &a, const std::vector<double>
     // show up again (a genuine second eigenvector); values closer than
     // 1e-10 of the matrix scale count as one level.
     const double merge = 1e-10 * std::max(scale, 1.0);
+    const double pivmin = DBL_MIN * std::max(1.0, scale * scale);
     int got = 0;
     for (int i = 0; i < m && got < k; ++i) {
         const double x = tridiag_eig(a, b, m, i);
-        if (got == 0 || x - evals[got - 1] > merge) evals[got++] = x;
+        if (got == 0 || x - evals[got - 1] > merge) {
+            if (bounds) bounds[got] = ritz_residual(a, b, m, x, b[m - 1], pivmin);
+            evals[got++] = x;
+        }
     }
-    for (int i = got; i < k; ++i) evals[i] = NAN;
+    for (int i = got; i < k; ++i) {
+        evals[i] = NAN;
+        if (bounds) bounds[i] = NAN;
+    }
 }
 
 }  // namespace
 
+extern "C" qaa_status qaa_debug_tridiag_levels(const double *alpha, const double *beta, int32_t m, int32_t k,
+                                               double *evals, double *bounds)
+{
+    if (!alpha || !beta || !evals || m < 1 || k < 1)
+        return set_error(QAA_ERR_INVALID_ARG, "qaa_debug_tridiag_levels: bad arguments");
+    const std::vector<double> a(alpha, alpha + m), b(beta, beta + m);
+    levels_from_tridiag(a, b, m, k, evals, bounds);
+    return set_error(QAA_OK, nullptr);
+}
+
 qaa_status lanczos_lowest(int n, const void *table, int etype, int count, const double *s_values, const double *v0,
-                          int iters, int k, double *evals, hipStream_t st)
+                          int iters, int k, double *evals, double *bounds, hipStream_t st)
 {
     const uint64_t dim = 1ull << n;
     iters = (int)std::min<uint64_t>((uint64_t)iters, dim);
@@ -345,7 +422,7 @@ qaa_status lanczos_lowest(int n, const void *table, int etype, int count, const 
             (void)hipFreeAsync(mem, st);
             return set_error(QAA_ERR_INVALID_ARG, "qaa_spectrum: the start vector v0 is zero or not finite");
         }
-        levels_from_tridiag(a, b, iters, k, evals + (size_t)si * k);
+        levels_from_tridiag(a, b, iters, k, evals + (size_t)si * k, bounds ? bounds + (size_t)si * k : nullptr);
     }
     (void)hipFreeAsync(mem, st);
     if (e != hipSuccess)

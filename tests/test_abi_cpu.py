@@ -235,7 +235,7 @@ def test_spectrum_rejects_before_any_device_call():
     out = (ctypes.c_double * 8)()
     try:
         def call(inst=h, table=0x1000, etype=0, count=2, svals=s_ok, v0=0x2000, iters=10, k=2, ev=out):
-            return lib.qaa_spectrum(inst, table, etype, count, svals, v0, iters, k, ev, None)
+            return lib.qaa_spectrum(inst, table, etype, count, svals, v0, iters, k, ev, None, None)
         assert call(inst=None) == qaa.QAA_ERR_INVALID_ARG
         assert call(table=None) == qaa.QAA_ERR_INVALID_ARG
         assert call(v0=None) == qaa.QAA_ERR_INVALID_ARG

@@ -117,3 +117,27 @@ def test_uint16_table_gives_the_same_levels(qaa):
     a = inst.spectrum(table, [0.45], v0, iters=100, k=2)
     b = inst.spectrum(t16, [0.45], v0, iters=100, k=2)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("iters", [6, 12, 40])
+def test_residual_bounds_hold(qaa, iters):
+    """Each returned Ritz value has an eigenvalue of H(s) within its bound
+    (all eigenvalues from dense eigvalsh at n = 8), also far from
+    convergence."""
+    n = 8
+    cl, inst, table = _setup(qaa, n, 1305)
+    E = oracle.energy(n, cl).astype(float)
+    svals = [0.3, 0.6]
+    ev, bd = inst.spectrum(table, svals, _v0(n, 7), iters=iters, k=3, bounds=True)
+    for i, s in enumerate(svals):
+        w = np.linalg.eigvalsh((1 - s) * oracle.dense_h_b(n) + s * np.diag(E))
+        for x, b in zip(ev[i], bd[i]):
+            assert np.min(np.abs(w - x)) <= b * (1 + 1e-9) + 1e-12, (s, x, b)
+
+
+def test_residual_bounds_are_small_once_converged(qaa):
+    n = 14
+    cl, inst, table = _setup(qaa, n, 1214)
+    ev, bd = inst.spectrum(table, [0.3, 0.5, 0.7], _v0(n, n + 1), iters=300, k=2, bounds=True)
+    assert np.all(bd < 1e-8), bd
+    assert np.allclose(ev, inst.spectrum(table, [0.3, 0.5, 0.7], _v0(n, n + 1), iters=300, k=2), atol=0, rtol=0)
