@@ -1062,15 +1062,25 @@ qaa_status upload(const std::vector<T> &host, T **dev, hipStream_t s)
 // size.  States are grouped by their number of qubit sets r (a group runs
 // r - 1 passes per step, r in the first); inside a group they are sorted by
 // step count, longest first, so the states still running at step k are a
-// prefix, and each state's tiles are cut into chunks of kBatchChunkTiles
+// prefix, and each state's tiles are cut into chunks of batch_chunk_tiles()
 // (one workgroup each).
-constexpr int kBatchChunkTiles = 8;
+// Tiles per workgroup chunk: QAA_BATCH_CHUNK_TILES (1..64, read once), else 8.
+int batch_chunk_tiles()
+{
+    static const int v = [] {
+        const char *e = std::getenv("QAA_BATCH_CHUNK_TILES");
+        const int x = e ? std::atoi(e) : 0;
+        return x >= 1 && x <= 64 ? x : 8;
+    }();
+    return v;
+}
 
 qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states, const SchedKnots *scs,
                             const double *T, const int64_t *steps, hipStream_t s)
 {
     if (idx.empty()) return QAA_OK;
     const int dty = (int)states[idx[0]].dtype, ety = (int)states[idx[0]].etype;
+    const int chunk_tiles = batch_chunk_tiles();
     struct GroupPlan {
         int r = 0;
         std::vector<int> order;              // state indices, longest first
@@ -1117,7 +1127,7 @@ qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states
             b.r = g.r;
             b.struct_base = base_of_n[n];
             b.sched = scs[i];
-            const uint64_t chunks = ((1ull << (n - TB)) + kBatchChunkTiles - 1) / kBatchChunkTiles;
+            const uint64_t chunks = ((1ull << (n - TB)) + chunk_tiles - 1) / chunk_tiles;
             for (uint64_t c = 0; c < chunks; ++c) chunk_inst.push_back((uint32_t)(insts.size() - g.inst_base));
             g.chunk_prefix.push_back(g.chunk_prefix.back() + chunks);
             insts.push_back(b);
@@ -1159,7 +1169,7 @@ qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states
             const int jn = k == 0 ? g.r : g.r - 1;
             for (int j = 0; j < jn; ++j) {
                 hipError_t e = launch_batch_pass(d_insts + g.inst_base, d_chunks + g.chunk_base, g.chunk_prefix[a],
-                                                 d_structs, k, j, kBatchChunkTiles, dty, ety, TB, RB, s);
+                                                 d_structs, k, j, chunk_tiles, dty, ety, TB, RB, s);
                 if (e != hipSuccess) {
                     release();
                     return fail(QAA_ERR_DEVICE, "batched pass launch failed: %s", hipGetErrorString(e));
