@@ -141,3 +141,18 @@ def test_residual_bounds_are_small_once_converged(qaa):
     ev, bd = inst.spectrum(table, [0.3, 0.5, 0.7], _v0(n, n + 1), iters=300, k=2, bounds=True)
     assert np.all(bd < 1e-8), bd
     assert np.allclose(ev, inst.spectrum(table, [0.3, 0.5, 0.7], _v0(n, n + 1), iters=300, k=2), atol=0, rtol=0)
+
+
+def test_workspace_too_large_is_reported(qaa):
+    """n = 30 with 1024 Lanczos steps needs ~8.8 TB of workspace: refused
+    with QAA_ERR_OUT_OF_MEMORY before any kernel runs (v0 and the table
+    are full size, so nothing could read past them either way)."""
+    n = 30
+    inst = qaa.Instance(n, [])
+    table = inst.energy_table()
+    v0 = torch.ones(1 << n, dtype=torch.float64, device="cuda")
+    with pytest.raises(qaa.QaaError) as ei:
+        inst.spectrum(table, [0.5], v0, iters=1024, k=2)
+    assert ei.value.status == qaa.QAA_ERR_OUT_OF_MEMORY
+    del v0, table
+    torch.cuda.empty_cache()
