@@ -960,21 +960,19 @@ hipError_t launch_pass_t(void *amp, const void *table, const PassDesc &d, hipStr
     return launch_pass_v<F, ET, TB, RB, false>(amp, table, d, s);
 }
 
-template <typename F, typename ET, int RB, int WB>
+template <typename F, typename ET, int RB, int WB, bool ONE>
 hipError_t launch_resident_t(const ResidentDesc *descs_dev, const ResidentDesc *one, int count, hipStream_t s)
 {
     using F2 = typename V2<F>::T;
     const size_t lds = sizeof(F2) * ((size_t(1) << (RB + WB)) + lut_cap<ET>()) + sizeof(ET) * (size_t(1) << (RB + WB));
-    static const hipError_t attr = [&] {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&resident_one_kernel<F, ET, RB, WB>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&resident_batch_kernel<F, ET, RB, WB>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        return e;
-    }();
+    const void *fn;
+    if constexpr (ONE)
+        fn = reinterpret_cast<const void *>(&resident_one_kernel<F, ET, RB, WB>);
+    else
+        fn = reinterpret_cast<const void *>(&resident_batch_kernel<F, ET, RB, WB>);
+    static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (attr != hipSuccess) return attr;
-    if (one)
+    if constexpr (ONE)
         hipLaunchKernelGGL((resident_one_kernel<F, ET, RB, WB>), dim3(1), dim3(1u << WB), lds, s, *one);
     else
         hipLaunchKernelGGL((resident_batch_kernel<F, ET, RB, WB>), dim3(count), dim3(1u << WB), lds, s, descs_dev);
@@ -1034,15 +1032,35 @@ hipError_t launch_batch_pass(const BatchInst *insts, const uint32_t *chunk_inst,
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_resident(const ResidentDesc *descs_dev, const ResidentDesc *one, int count, int dtype, int etype,
-                           hipStream_t s)
+// Single-state shapes (see resident_shape): 2^(rb + wb) amplitudes.
+template <typename F, typename ET>
+hipError_t launch_resident_one(const ResidentDesc *one, int rb, int wb, hipStream_t s)
 {
-    if (dtype == 0) {
-        if (etype == 0) return launch_resident_t<float, uint8_t, 5, 8>(descs_dev, one, count, s);
-        return launch_resident_t<float, uint16_t, 5, 8>(descs_dev, one, count, s);
+    if (rb == 2 && wb == 8) return launch_resident_t<F, ET, 2, 8, true>(nullptr, one, 1, s);
+    if (rb == 2 && wb == 9) return launch_resident_t<F, ET, 2, 9, true>(nullptr, one, 1, s);
+    if (rb == 2 && wb == 10) return launch_resident_t<F, ET, 2, 10, true>(nullptr, one, 1, s);
+    if constexpr (sizeof(F) == 4)
+        if (rb == 3 && wb == 10) return launch_resident_t<F, ET, 3, 10, true>(nullptr, one, 1, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_resident(const ResidentDesc *descs_dev, const ResidentDesc *one, int count, int dtype, int etype,
+                           int rb, int wb, hipStream_t s)
+{
+    if (one) {
+        if (dtype == 0)
+            return etype == 0 ? launch_resident_one<float, uint8_t>(one, rb, wb, s)
+                              : launch_resident_one<float, uint16_t>(one, rb, wb, s);
+        return etype == 0 ? launch_resident_one<double, uint8_t>(one, rb, wb, s)
+                          : launch_resident_one<double, uint16_t>(one, rb, wb, s);
     }
-    if (etype == 0) return launch_resident_t<double, uint8_t, 4, 8>(descs_dev, one, count, s);
-    return launch_resident_t<double, uint16_t, 4, 8>(descs_dev, one, count, s);
+    if (rb != kResRegBits[dtype] || wb != kResThrBits) return hipErrorInvalidValue;
+    if (dtype == 0) {
+        if (etype == 0) return launch_resident_t<float, uint8_t, 5, 8, false>(descs_dev, nullptr, count, s);
+        return launch_resident_t<float, uint16_t, 5, 8, false>(descs_dev, nullptr, count, s);
+    }
+    if (etype == 0) return launch_resident_t<double, uint8_t, 4, 8, false>(descs_dev, nullptr, count, s);
+    return launch_resident_t<double, uint16_t, 4, 8, false>(descs_dev, nullptr, count, s);
 }
 
 hipError_t launch_energy(const ClauseRec *cl, int m, int n, void *table, int etype, uint32_t *stats, hipStream_t s)

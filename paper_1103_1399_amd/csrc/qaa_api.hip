@@ -633,10 +633,9 @@ void fill_residencies(PassDesc &d, const SetPlan &sp, int tb, int rb, int dt, bo
 }
 
 ResidentDesc make_resident_desc(const qaa_state *st, const SchedKnots &sc, double T, int64_t N, int64_t k0,
-                                int64_t k1)
+                                int64_t k1, int rb)
 {
     const int n = st->inst->n;
-    const int dt = (int)st->dtype;
     ResidentDesc d;
     std::memset(&d, 0, sizeof d);
     d.sched = sc;
@@ -648,7 +647,7 @@ ResidentDesc make_resident_desc(const qaa_state *st, const SchedKnots &sc, doubl
     d.N = N;
     d.k0 = k0;
     d.k1 = k1;
-    d.reg_bits = std::min(kResRegBits[dt], n);
+    d.reg_bits = std::min(rb, n);
     d.thr_bits = n - d.reg_bits;
     std::vector<int> rot;
     for (int b = 0; b < n; ++b) rot.push_back(b);
@@ -667,8 +666,10 @@ ResidentDesc make_resident_desc(const qaa_state *st, const SchedKnots &sc, doubl
 qaa_status run_resident(const qaa_state *st, const SchedKnots &sc, double T, int64_t N, int64_t k0, int64_t k1,
                         hipStream_t s)
 {
-    const ResidentDesc d = make_resident_desc(st, sc, T, N, k0, k1);
-    QAA_HIP(launch_resident(nullptr, &d, 1, (int)st->dtype, (int)st->etype, s));
+    int rb = 0, wb = 0;
+    resident_shape(st->inst->n, &rb, &wb);
+    const ResidentDesc d = make_resident_desc(st, sc, T, N, k0, k1, rb);
+    QAA_HIP(launch_resident(nullptr, &d, 1, (int)st->dtype, (int)st->etype, rb, wb, s));
     return QAA_OK;
 }
 
@@ -1212,7 +1213,7 @@ extern "C" qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, c
         if (steps[i] == 0) continue;
         const int dt = (int)states[i].dtype, et = (int)states[i].etype;
         if (make_plan(states[i].inst->n, dt).resident)
-            small[dt][et].push_back(make_resident_desc(&states[i], scs[i], T[i], steps[i], 0, steps[i]));
+            small[dt][et].push_back(make_resident_desc(&states[i], scs[i], T[i], steps[i], 0, steps[i], kResRegBits[dt]));
         else
             large[dt][et].push_back(i);
     }
@@ -1244,7 +1245,8 @@ extern "C" qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, c
                 ResidentDesc *d = nullptr;
                 r = upload(small[dt][et], &d, ctx->side);
                 if (r != QAA_OK) break;
-                he = launch_resident(d, nullptr, (int)small[dt][et].size(), dt, et, ctx->side);
+                he = launch_resident(d, nullptr, (int)small[dt][et].size(), dt, et, kResRegBits[dt], kResThrBits,
+                                     ctx->side);
                 (void)hipFreeAsync(d, ctx->side);
             }
         joined = hipEventRecord(join, ctx->side) == hipSuccess;

@@ -184,12 +184,26 @@ hipError_t launch_batch_pass(const BatchInst *insts, const uint32_t *chunk_inst,
                              const PassDesc *structs, int64_t s, int j, int chunk_tiles, int dtype, int etype,
                              int tile_bits, int reg_bits, hipStream_t st);
 // Resident evolution: one state (one != nullptr, descriptor by value) or a
-// batch of `count` states whose descriptors are in device memory.
+// batch of `count` states whose descriptors are in device memory.  rb / wb
+// are the kernel's register bits and thread-index bits: resident_shape()
+// for one state, kResRegBits[dtype] / kResThrBits for a batch.
 hipError_t launch_resident(const ResidentDesc *descs_dev, const ResidentDesc *one, int count, int dtype,
-                           int etype, hipStream_t s);
-// Register/thread split of the resident kernels: complex64 5+8, complex128 4+8.
+                           int etype, int rb, int wb, hipStream_t s);
+// Register/thread split of the batched resident kernel: complex64 5+8,
+// complex128 4+8 bits (2^13 / 2^12 amplitudes in one 256-thread workgroup).
 constexpr int kResRegBits[2] = {5, 4};
 constexpr int kResThrBits = 8;
+// A single state runs in one workgroup whose threads hold few amplitudes
+// each: 256 threads up to n = 10, then 512 (n = 11) and 1024 (n = 12, 13),
+// with 2 register bits (3 at n = 13).  Each step's serial chain per
+// thread (loads, rotations, phase) then stays short; a state of 2^10
+// amplitudes runs as 256 threads x 4 instead of 32 threads x 32.  Batches
+// keep the 256-thread split: many workgroups fill the device anyway.
+inline void resident_shape(int n, int *rb, int *wb)
+{
+    *wb = n <= 10 ? 8 : (n == 11 ? 9 : 10);
+    *rb = n <= 12 ? 2 : 3;
+}
 // Pass tile shapes: complex64 2^13 (5 register bits), complex128 2^12 (4).
 constexpr int kPassTileBits[2] = {13, 12};
 constexpr int kPassRegBits[2] = {5, 4};
