@@ -32,9 +32,10 @@
  *    Calls are asynchronous on it unless stated otherwise.
  *  - Library-owned device memory: a per-device block of reduction scratch
  *    (created on first use, kept until the process ends), a device copy of
- *    each instance's clause list, and small per-call buffers (norm
- *    accumulators, batch descriptors) taken from the stream-ordered
- *    allocator and released in stream order by the call that took them.
+ *    each instance's clause list, and per-call buffers (norm accumulators,
+ *    batch descriptors, qaa_spectrum's Lanczos vectors) taken from the
+ *    stream-ordered allocator and released in stream order by the call
+ *    that took them.
  *  - Calls that read back results (qaa_energy_table, qaa_observables) are
  *    serialised per device; evolution calls on different streams run
  *    concurrently.
