@@ -22,7 +22,10 @@ Also reported on the same JSON line:
                   one qaa_evolve call per instance on a sample.
   serving      -- Poisson request streams through the request server: p50/p99
                   latency and solves/s per arrival rate.
-(--no-extras skips the last two; they run after the timed region.)
+  spectrum     -- the two lowest levels of H(s) on a grid of s for one
+                  planted instance (qaa_spectrum): minimum gap and time.
+(--no-extras skips the last three; they run after the timed region.
+--schedule-knots K runs the headline job under a K-knot schedule table.)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
