@@ -328,7 +328,7 @@ class PassDesc(ctypes.Structure):
     """Mirror of the library's internal pass descriptor (diagnostics only)."""
     _fields_ = [("n", ctypes.c_int32), ("n_rest", ctypes.c_int32), ("n_res", ctypes.c_int32),
                 ("phase_at", ctypes.c_int32), ("emax", ctypes.c_int32), ("set_id", ctypes.c_int32),
-                ("reverse", ctypes.c_int32),
+                ("reverse", ctypes.c_int32), ("persist", ctypes.c_int32),
                 ("tA", ctypes.c_double), ("sA", ctypes.c_double), ("tB", ctypes.c_double),
                 ("sB", ctypes.c_double),
                 ("phi", ctypes.c_double), ("gphase", ctypes.c_double),

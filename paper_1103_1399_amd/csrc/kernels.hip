@@ -935,13 +935,15 @@ hipError_t launch_pass_p(void *amp, const void *table, const PassDesc &d, hipStr
     return hipGetLastError();
 }
 
-// Kernel variant (tuning switch, QAA_PASS_VARIANT): 2 (default) persistent
-// grid with the next tile's loads in flight, 0 one workgroup per tile.
+// Kernel variant: the persistent grid with the next tile's loads in
+// flight, or one workgroup per tile, as the planner chose for the pass
+// (PassDesc::persist).  Tuning switch QAA_PASS_VARIANT: 2 forces the
+// persistent grid everywhere, 0 one workgroup per tile everywhere.
 inline int pass_variant()
 {
     static const int v = [] {
         const char *e = std::getenv("QAA_PASS_VARIANT");
-        return e ? (std::atoi(e) & 2) : 2;
+        return e ? (std::atoi(e) & 2) : -1;
     }();
     return v;
 }
@@ -949,7 +951,8 @@ inline int pass_variant()
 template <typename F, typename ET, int TB, int RB, bool PHASE>
 hipError_t launch_pass_v(void *amp, const void *table, const PassDesc &d, hipStream_t s)
 {
-    if (pass_variant() == 0) return launch_pass_p<F, ET, TB, RB, PHASE, false>(amp, table, d, s);
+    const int v = pass_variant();
+    if (v == 0 || (v < 0 && !d.persist)) return launch_pass_p<F, ET, TB, RB, PHASE, false>(amp, table, d, s);
     return launch_pass_p<F, ET, TB, RB, PHASE, true>(amp, table, d, s);
 }
 

@@ -98,6 +98,7 @@ struct PassDesc {
     int32_t emax;              // largest E value the LUT must cover
     int32_t set_id;            // qubit set of this pass (host bookkeeping)
     int32_t reverse;           // visit the tiles in descending order
+    int32_t persist;           // 1: persistent pipelined grid, 0: one workgroup per tile
     double tA, sA, tB, sB;     // tan(theta/4), sin(theta/2) of the rotations before (A) / after (B) the phase
     double phi, gphase;
     uint64_t tile_begin;       // this launch handles tiles [tile_begin, tile_begin + tile_count)
