@@ -907,10 +907,11 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, 
         // 256-byte runs spread over the whole state and its table reads come
         // in 64-byte runs: only the persistent grid, with the next tile's
         // loads in flight, streams them well (one workgroup per tile: 5.6x
-        // slower).  Every other pass streams faster with one workgroup per
-        // tile (n = 28: middle passes 0.89 -> 0.82 ms, set-0 turns 0.84 ->
-        // 0.81 ms).
-        d.persist = (d.set_id == top || top < 2) ? 1 : 0;
+        // slower).  Every other pass, and every pass of a two-set plan,
+        // streams faster with one workgroup per tile (n = 28: middle passes
+        // 0.89 -> 0.82 ms, set-0 turns 0.84 -> 0.81 ms; n = 16..21: 6-8 %
+        // per step).
+        d.persist = (top >= 2 && d.set_id == top) ? 1 : 0;
         prev_low = low;
         prev_rev = d.reverse != 0;
         // Norm control rides on the passes over the top qubit set: each one
