@@ -80,6 +80,8 @@ def _load():
             lib.oracle_observables.restype = ctypes.c_int
             lib.oracle_num_threads.argtypes = []
             lib.oracle_num_threads.restype = ctypes.c_int
+            lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+            lib.oracle_set_num_threads.restype = None
             _lib = lib
     return _lib
 
@@ -95,6 +97,11 @@ def _ptr(a, t):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(t: int) -> None:
+    """Threads the oracle's OpenMP loops use from now on (timing only)."""
+    _load().oracle_set_num_threads(int(t))
 
 
 def energy(n: int, clauses) -> np.ndarray:

@@ -220,10 +220,13 @@ int oracle_observables(int n, int m, const int32_t *lits, const double *psi_ri,
     return 0;
 }
 
-/* Thread count OpenMP will use (reported beside CPU timings). */
+/* Thread count OpenMP will use (reported beside CPU timings), and a way to
+ * change it for timing runs (it does not change any result). */
 #ifdef _OPENMP
 #include <omp.h>
 int oracle_num_threads(void) { return omp_get_max_threads(); }
+void oracle_set_num_threads(int t) { if (t > 0) omp_set_num_threads(t); }
 #else
 int oracle_num_threads(void) { return 1; }
+void oracle_set_num_threads(int t) { (void)t; }
 #endif

@@ -103,6 +103,44 @@ def test_energy_per_clause_indicator():
     assert set(np.unique(E).tolist()) == {0, 1}
 
 
+def _energy_by_proposition(clauses, z):
+    """Count the clauses the assignment z falsifies, reading each literal
+    from the bits of z directly (Sec. 2.2: x_i is bit i-1 of z)."""
+    x = [(z >> i) & 1 for i in range(64)]
+    return sum(0 if _satisfies_all([c], x) else 1 for c in clauses)
+
+
+@pytest.mark.parametrize("n,seed", [(5, 31), (12, 32), (17, 33)])
+def test_energy_at_matches_the_full_table(n, seed):
+    """energy_at (the sampled checker used at full size) agrees with the
+    whole table on random z and on both corners z = 0 and z = 2^n - 1."""
+    inst = planted_unique_3sat(n, seed)
+    E = oracle.energy(n, inst.clauses)
+    rng = np.random.default_rng(seed)
+    zs = np.concatenate([[0, (1 << n) - 1, inst.planted], rng.integers(0, 1 << n, 500)]).astype(np.uint64)
+    got = oracle.energy_at(n, inst.clauses, zs)
+    assert np.array_equal(got, E[zs.astype(np.int64)])
+
+
+@pytest.mark.parametrize("n", [28, 34])
+def test_energy_at_matches_the_proposition_at_large_n(n):
+    """Above what a full table allows, energy_at is checked against a count
+    written from the clause definition, z by z, including z with the top
+    bits set (a truncated index would lose them)."""
+    rng = np.random.default_rng(n)
+    cl = []
+    for _ in range(60):
+        v = rng.choice(n, size=3, replace=False) + 1
+        v[0] = n if len(cl) % 5 == 0 else v[0]       # some clauses on the top variable
+        if len(set(v.tolist())) < 3:
+            continue
+        cl.append([int(a) * (1 if rng.random() < 0.5 else -1) for a in v])
+    zs = np.concatenate([[0, (1 << n) - 1, 1 << (n - 1)], rng.integers(0, 1 << n, 40, dtype=np.int64)])
+    got = oracle.energy_at(n, cl, zs.astype(np.uint64))
+    want = [_energy_by_proposition(cl, int(z)) for z in zs]
+    assert got.tolist() == want
+
+
 def test_energy_rejects_out_of_range_literal():
     with pytest.raises(ValueError):
         oracle.energy(4, [[1, 2, 5]])
@@ -230,6 +268,58 @@ def test_zero_steps_gives_uniform_observables():
     assert obs["degeneracy"] == 1 and obs["e_min"] == 0
     assert abs(obs["p_success"] - 2.0 ** -n) < 1e-15
     assert abs(obs["energy"] - inst.m / 8.0) < 1e-12
+
+
+def _random_state(n, seed):
+    rng = np.random.default_rng(seed)
+    psi = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    return psi / np.linalg.norm(psi)
+
+
+def test_success_probability_without_clauses_is_the_norm():
+    """m = 0: every z has E = 0, so the ground manifold is all 2^n states
+    and P_success is the whole norm (Sec. 2.1, degeneracy 2^n)."""
+    n = 6
+    psi = _random_state(n, 1)
+    obs = oracle.observables(n, np.zeros((0, 3), np.int32), psi)
+    assert obs["e_min"] == 0 and obs["degeneracy"] == 1 << n
+    assert abs(obs["p_success"] - 1.0) < 1e-13 and abs(obs["energy"]) == 0.0
+
+
+def test_success_probability_sums_every_solution():
+    """A formula with several solutions: P_success is the weight on all of
+    them (found here by brute force over the assignments), not on one."""
+    n = 7
+    # x1 = 1 is forced by the four clauses over (1, 2, 3) without the pattern
+    # x1 = 1 falsifies; the clauses over (4, 5, 6) and (5, 6, 7) prune the rest
+    cl = [[1, 2, 3], [1, -2, 3], [1, 2, -3], [1, -2, -3],
+          [4, 5, 6], [-4, 5, 6], [4, -5, 6], [4, 5, -6], [-4, -5, 6], [-4, 5, -6], [4, -5, -6],
+          [5, 6, 7], [-5, 6, 7], [5, -6, 7], [5, 6, -7], [-5, -6, 7], [5, -6, -7]]
+    sols = [z for z in range(1 << n) if _satisfies_all(cl, [(z >> i) & 1 for i in range(n)])]
+    assert 2 <= len(sols) <= 8
+    psi = _random_state(n, 2)
+    obs = oracle.observables(n, cl, psi)
+    assert obs["e_min"] == 0 and obs["degeneracy"] == len(sols)
+    want = sum(abs(psi[z]) ** 2 for z in sols)
+    assert abs(obs["p_success"] - want) < 1e-14
+    # the largest single weight is not the answer
+    assert abs(obs["p_success"] - max(abs(psi[z]) ** 2 for z in sols)) > 1e-3
+
+
+def test_success_probability_on_an_unsatisfiable_formula():
+    """All eight sign patterns over (x1, x2, x3): every assignment falsifies
+    exactly one of them, so E_min = 1; one more clause over (x4, x5, x6)
+    lifts 1/8 of the states to E = 2.  The ground manifold is the other 7/8."""
+    n = 6
+    cl = [[a * 1, b * 2, c * 3] for a in (1, -1) for b in (1, -1) for c in (1, -1)] + [[4, -5, 6]]
+    psi = _random_state(n, 3)
+    obs = oracle.observables(n, cl, psi)
+    assert obs["e_min"] == 1 and obs["degeneracy"] == (1 << n) - (1 << (n - 3))
+    lifted = [z for z in range(1 << n) if ((z >> 3) & 1) == 0 and ((z >> 4) & 1) == 1 and ((z >> 5) & 1) == 0]
+    assert len(lifted) == 1 << (n - 3)
+    want = 1.0 - sum(abs(psi[z]) ** 2 for z in lifted)
+    assert abs(obs["p_success"] - want) < 1e-13
+    assert abs(obs["energy"] - (1.0 + (1.0 - want))) < 1e-13
 
 
 def test_step_ranges_compose():
