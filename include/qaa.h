@@ -30,15 +30,15 @@
  *    queued on the stream has finished.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Calls are asynchronous on it unless stated otherwise.
- *  - Library-owned device memory: a per-device block of reduction scratch
- *    (created on first use, kept until the process ends), a device copy of
- *    each instance's clause list, and per-call buffers (norm accumulators,
- *    batch descriptors, qaa_spectrum's Lanczos vectors) taken from the
- *    stream-ordered allocator and released in stream order by the call
- *    that took them.
- *  - Calls that read back results (qaa_energy_table, qaa_observables) are
- *    serialised per device; evolution calls on different streams run
- *    concurrently.
+ *  - Library-owned device memory: a device copy of each instance's clause
+ *    list and per-call buffers (norm
+ *    accumulators, reduction partials, batch descriptors, qaa_spectrum's
+ *    Lanczos vectors) taken from the stream-ordered allocator and released
+ *    in stream order by the call that took them.
+ *  - Calls on different streams share no library state on the device and
+ *    run concurrently, including the ones that read back results
+ *    (qaa_energy_table, qaa_observables), which wait for their own stream
+ *    only.
  *  - Errors: every call returns a qaa_status; nothing throws or aborts
  *    across the ABI.  qaa_last_error() returns a thread-local message for
  *    the last failing call of the calling thread.
@@ -381,16 +381,6 @@ qaa_status qaa_autotune(const qaa_state *scratch, int64_t steps, qaa_plan_choice
                         void *stream);
 
 /*
- * Diagnostic: the pass descriptors qaa_evolve_range would launch for an
- * n-qubit state (energies up to emax) over steps k0..k1-1 of `steps`
- * under schedule `sched` (NULL: linear).
- * Writes up to `capacity` descriptors of *desc_bytes bytes each into the
- * host buffer `out` (may be NULL to query the count) and the total number
- * into *count (0 when the whole state is one workgroup tile).  The record
- * layout is the library's internal pass descriptor and may change between
- * versions; it exists so that host-side tests can replay the index maps.
- */
-/*
  * Diagnostic: the host half of qaa_spectrum on a given tridiagonal matrix
  * (diagonal alpha[0..m), off-diagonal beta[0..m-1), and beta[m-1] the
  * residual coefficient of the last Lanczos step): the k lowest levels and,
@@ -401,9 +391,25 @@ qaa_status qaa_autotune(const qaa_state *scratch, int64_t steps, qaa_plan_choice
 qaa_status qaa_debug_tridiag_levels(const double *alpha, const double *beta, int32_t m, int32_t k, double *evals,
                                     double *bounds);
 
+/*
+ * Diagnostic: the pass descriptors qaa_evolve_range would launch for an
+ * n-qubit state (energies up to emax) over steps k0..k1-1 of `steps`
+ * under schedule `sched` (NULL: linear).
+ *   tile_bits : 0 for the library's own plan; otherwise the plan the same
+ *               planner makes for tiles of that many qubits (complex64
+ *               9..13, complex128 8..12).  Smaller tiles give plans with
+ *               three and four qubit sets already at small n, so host-side
+ *               replays can check them against a reference; no kernel runs
+ *               such tiles.  QAA_ERR_INVALID_ARG outside that range.
+ * Writes up to `capacity` descriptors of *desc_bytes bytes each into the
+ * host buffer `out` (may be NULL to query the count) and the total number
+ * into *count (0 when the whole state is one workgroup tile).  The record
+ * layout is the library's internal pass descriptor and may change between
+ * versions; it exists so that host-side tests can replay the index maps.
+ */
 qaa_status qaa_debug_pass_descs(int32_t n, qaa_dtype dtype, int32_t emax, const qaa_schedule *sched, double T,
-                                int64_t steps, int64_t k0, int64_t k1, void *out, int32_t capacity,
-                                int32_t *count, int32_t *desc_bytes);
+                                int64_t steps, int64_t k0, int64_t k1, int32_t tile_bits, void *out,
+                                int32_t capacity, int32_t *count, int32_t *desc_bytes);
 
 /* ---------------------------------------------------------------------
  * Kernel timing (tracing).

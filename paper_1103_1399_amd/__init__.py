@@ -127,8 +127,8 @@ _SIGS = {
     "qaa_debug_tridiag_levels": (_st, [_f64p, _f64p, ctypes.c_int32, ctypes.c_int32, _f64p, _f64p]),
     "qaa_plan_info": (_st, [ctypes.c_int32, ctypes.c_int, _i32p, _i32p, _i32p]),
     "qaa_debug_pass_descs": (_st, [ctypes.c_int32, ctypes.c_int, ctypes.c_int32, ctypes.POINTER(qaa_schedule),
-                                   ctypes.c_double, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _vp,
-                                   ctypes.c_int32, _i32p, _i32p]),
+                                   ctypes.c_double, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                   _vp, ctypes.c_int32, _i32p, _i32p]),
     "qaa_profile_enable": (_st, [ctypes.c_int32]),
     "qaa_profile_read": (_st, [ctypes.c_void_p, ctypes.c_int32]),
     "qaa_server_create": (_st, [ctypes.POINTER(qaa_server_config), ctypes.POINTER(_vp)]),
@@ -342,18 +342,19 @@ class PassDesc(ctypes.Structure):
                 ("gpos_last", ctypes.c_uint8 * 16), ("masks", ctypes.c_uint32 * 12)]
 
 
-def qaa_debug_pass_descs(n: int, dtype: int, emax: int, T: float, steps: int, k0: int, k1: int, knots=None):
+def qaa_debug_pass_descs(n: int, dtype: int, emax: int, T: float, steps: int, k0: int, k1: int, knots=None,
+                         tile_bits: int = 0):
+    """Pass descriptors of the plan (tile_bits 0) or of the same planner's
+    plan for smaller tiles (host-side replay only)."""
     count, size = ctypes.c_int32(), ctypes.c_int32()
     sched = make_schedule(knots)
-    _check(_lib.qaa_debug_pass_descs(n, dtype, emax, ctypes.byref(sched), T, steps, k0, k1, None, 0,
-                                     ctypes.byref(count),
-                                     ctypes.byref(size)), "qaa_debug_pass_descs")
+    _check(_lib.qaa_debug_pass_descs(n, dtype, emax, ctypes.byref(sched), T, steps, k0, k1, int(tile_bits), None, 0,
+                                     ctypes.byref(count), ctypes.byref(size)), "qaa_debug_pass_descs")
     if size.value != ctypes.sizeof(PassDesc):
         raise RuntimeError("pass descriptor layout mismatch (%d vs %d bytes)" % (size.value, ctypes.sizeof(PassDesc)))
     arr = (PassDesc * max(1, count.value))()
-    _check(_lib.qaa_debug_pass_descs(n, dtype, emax, ctypes.byref(sched), T, steps, k0, k1, arr, count.value,
-                                     ctypes.byref(count),
-                                     ctypes.byref(size)), "qaa_debug_pass_descs")
+    _check(_lib.qaa_debug_pass_descs(n, dtype, emax, ctypes.byref(sched), T, steps, k0, k1, int(tile_bits), arr,
+                                     count.value, ctypes.byref(count), ctypes.byref(size)), "qaa_debug_pass_descs")
     return list(arr)[:count.value]
 
 

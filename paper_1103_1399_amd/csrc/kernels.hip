@@ -162,8 +162,10 @@ __global__ void __launch_bounds__(256) energy_kernel(const ClauseRec *__restrict
         hi = max(hi, (uint32_t)__shfl_xor((int)hi, off, 64));
         over |= (uint32_t)__shfl_xor((int)over, off, 64);
     }
+    // stats[0] holds ~E_min (the maximum of the complements), so that a
+    // zero-filled block is the neutral start for all three
     if ((threadIdx.x & 63) == 0) {
-        atomicMin(&stats[0], lo);
+        atomicMax(&stats[0], ~lo);
         atomicMax(&stats[1], hi);
         if (over) atomicOr(&stats[2], over);
     }

@@ -1,6 +1,6 @@
 // qaa_api.hip -- host runtime behind include/qaa.h: argument validation,
 // instance encoding, the pass planner, the per-step pass sequence and the
-// per-device scratch used by reductions.
+// per-call scratch of the reductions.
 #include "qaa.h"
 #include "qaa_internal.h"
 
@@ -64,16 +64,14 @@ namespace {
     } while (0)
 
 // ---------------------------------------------------------------------------
-// Per-device scratch (reduction partials and small counters).
+// Per-device context: the side stream that batched small states run on.
+// Reductions (energy-table statistics, observables) take their scratch per
+// call from the stream-ordered allocator, so concurrent calls on different
+// streams share nothing and need no lock.
 // ---------------------------------------------------------------------------
 struct DeviceCtx {
-    std::mutex mu;
+    std::mutex mu;                          // enqueueing on `side`
     bool ready = false;
-    uint32_t *stats = nullptr;              // [4] energy min / max / overflow
-    unsigned long long *count = nullptr;    // [1]
-    double *partials = nullptr;             // [2048 * 3]
-    double *obs_out = nullptr;              // [4]
-    void *host_pinned = nullptr;            // 256 B staging for readbacks
     hipStream_t side = nullptr;             // second stream for batched small states
 };
 
@@ -93,20 +91,23 @@ qaa_status device_ctx(DeviceCtx **out)
     }
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (!ctx->ready) {
-        char *base = nullptr;
-        const size_t bytes = 256 + 2048 * 3 * sizeof(double) + 64;
-        QAA_HIP(hipMalloc(reinterpret_cast<void **>(&base), bytes));
-        ctx->stats = reinterpret_cast<uint32_t *>(base);
-        ctx->count = reinterpret_cast<unsigned long long *>(base + 64);
-        ctx->obs_out = reinterpret_cast<double *>(base + 128);
-        ctx->partials = reinterpret_cast<double *>(base + 256);
-        QAA_HIP(hipHostMalloc(&ctx->host_pinned, 256, hipHostMallocDefault));
         QAA_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
         ctx->ready = true;
     }
     *out = ctx;
     return QAA_OK;
 }
+
+// Per-call device scratch from the stream-ordered allocator, released in
+// stream order when the holder goes out of scope (every return path).
+struct StreamScratch {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    ~StreamScratch()
+    {
+        if (p) (void)hipFreeAsync(p, s);
+    }
+};
 
 }  // namespace
 
@@ -224,9 +225,6 @@ extern "C" qaa_status qaa_energy_table(qaa_instance *inst, void *d_table, qaa_et
     if (etype != QAA_E_U8 && etype != QAA_E_U16)
         return fail(QAA_ERR_INVALID_ARG, "qaa_energy_table: bad etype %d", (int)etype);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    DeviceCtx *ctx = nullptr;
-    qaa_status st = device_ctx(&ctx);
-    if (st != QAA_OK) return st;
     int dev = 0;
     QAA_HIP(hipGetDevice(&dev));
 
@@ -251,24 +249,28 @@ extern "C" qaa_status qaa_energy_table(qaa_instance *inst, void *d_table, qaa_et
         }
     }
 
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    QAA_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(ctx->stats), 0xFFFFFFFFu, 1, s));
-    QAA_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(ctx->stats + 1), 0u, 3, s));
-    QAA_HIP(launch_energy(recs, inst->m, inst->n, d_table, (int)etype, ctx->stats, s));
-    uint32_t *h = reinterpret_cast<uint32_t *>(ctx->host_pinned);
-    QAA_HIP(hipMemcpyAsync(h, ctx->stats, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    // stats[0] = ~E_min (max of complements), stats[1] = E_max, stats[2] =
+    // uint8 overflow flag; count = number of z at E_min
+    StreamScratch scr;
+    scr.s = s;
+    QAA_HIP(hipMallocAsync(&scr.p, 64, s));
+    uint32_t *stats = reinterpret_cast<uint32_t *>(scr.p);
+    unsigned long long *count = reinterpret_cast<unsigned long long *>(stats + 4);
+    QAA_HIP(launch_zero_u64(reinterpret_cast<unsigned long long *>(stats), 3, s));
+    QAA_HIP(launch_energy(recs, inst->m, inst->n, d_table, (int)etype, stats, s));
+    uint32_t h[4] = {0, 0, 0, 0};
+    QAA_HIP(hipMemcpyAsync(h, stats, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     QAA_HIP(hipStreamSynchronize(s));
-    const uint32_t emin = h[0], emax = h[1], over = h[2];
+    const uint32_t emin = ~h[0], emax = h[1], over = h[2];
     if (etype == QAA_E_U8 && (over || emax > 255))
         return fail(QAA_ERR_UNSUPPORTED, "qaa_energy_table: E_max=%u does not fit uint8; use QAA_E_U16", emax);
-    QAA_HIP(hipMemsetAsync(ctx->count, 0, sizeof(unsigned long long), s));
-    QAA_HIP(launch_count_equal(d_table, (int)etype, inst->n, (int)emin, ctx->count, s));
-    unsigned long long *hc = reinterpret_cast<unsigned long long *>(h + 8);
-    QAA_HIP(hipMemcpyAsync(hc, ctx->count, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    QAA_HIP(launch_count_equal(d_table, (int)etype, inst->n, (int)emin, count, s));
+    unsigned long long hc = 0;
+    QAA_HIP(hipMemcpyAsync(&hc, count, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     QAA_HIP(hipStreamSynchronize(s));
     inst->e_min = (int32_t)emin;
     inst->e_max = (int32_t)emax;
-    inst->degeneracy = (int64_t)*hc;
+    inst->degeneracy = (int64_t)hc;
     return ok();
 }
 
@@ -379,10 +381,13 @@ PlanChoice plan_choice(int n, int dtype, int sets)
     return c;
 }
 
-Plan make_plan(int n, int dtype)
+// tile_override: 0 for the library's tile shape; otherwise a smaller tile
+// of that many bits, for host-side replay of plans with more qubit sets at
+// small n (qaa_debug_pass_descs only: no kernel is built for such tiles).
+Plan make_plan(int n, int dtype, int tile_override = 0)
 {
     Plan p;
-    const int TB = kPassTileBits[dtype];
+    const int TB = tile_override ? tile_override : kPassTileBits[dtype];
     if (n <= kResRegBits[dtype] + kResThrBits) {
         p.resident = true;
         return p;
@@ -881,6 +886,7 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, 
     unsigned long long *acc = nullptr;
     if (norm_control_enabled()) {
         QAA_HIP(hipMallocAsync(reinterpret_cast<void **>(&acc), 3 * sizeof(unsigned long long), s));
+        // a fill kernel, not a memset node: callers may capture this call
         QAA_HIP(launch_zero_u64(acc, 3, s));
     }
     bool prof;
@@ -1309,15 +1315,16 @@ extern "C" qaa_status qaa_observables(const qaa_state *st, qaa_obs *out, void *s
     qaa_status r = check_state_table(st, "qaa_observables");
     if (r != QAA_OK) return r;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    DeviceCtx *ctx = nullptr;
-    r = device_ctx(&ctx);
-    if (r != QAA_OK) return r;
-    std::lock_guard<std::mutex> lk(ctx->mu);
     const int nb = observables_blocks(st->inst->n);
+    StreamScratch scr;
+    scr.s = s;
+    QAA_HIP(hipMallocAsync(&scr.p, sizeof(double) * (3 * (size_t)nb + 4), s));
+    double *partials = reinterpret_cast<double *>(scr.p);
+    double *res = partials + 3 * (size_t)nb;
     QAA_HIP(launch_observables(st->amp, (int)st->dtype, st->table, (int)st->etype, st->inst->n, st->inst->e_min,
-                               ctx->partials, nb, ctx->obs_out, s));
-    double *h = reinterpret_cast<double *>(ctx->host_pinned);
-    QAA_HIP(hipMemcpyAsync(h, ctx->obs_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+                               partials, nb, res, s));
+    double h[3] = {0.0, 0.0, 0.0};
+    QAA_HIP(hipMemcpyAsync(h, res, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
     QAA_HIP(hipStreamSynchronize(s));
     out->norm = h[0];
     out->energy = h[1];
@@ -1422,18 +1429,23 @@ extern "C" qaa_status qaa_plan_info(int32_t n, qaa_dtype dtype, int32_t *tile_bi
 }
 
 extern "C" qaa_status qaa_debug_pass_descs(int32_t n, qaa_dtype dtype, int32_t emax, const qaa_schedule *sched,
-                                           double T, int64_t steps, int64_t k0, int64_t k1, void *out,
-                                           int32_t capacity, int32_t *count, int32_t *desc_bytes)
+                                           double T, int64_t steps, int64_t k0, int64_t k1, int32_t tile_bits,
+                                           void *out, int32_t capacity, int32_t *count, int32_t *desc_bytes)
 {
     if (n < 1 || n > QAA_MAX_QUBITS) return fail(QAA_ERR_INVALID_ARG, "qaa_debug_pass_descs: n out of range");
     if (dtype != QAA_C64 && dtype != QAA_C128) return fail(QAA_ERR_INVALID_ARG, "qaa_debug_pass_descs: bad dtype");
+    // a replayed tile keeps >= 4 thread-index bits (the low four carry the
+    // contiguous runs) and room for one rotated qubit beside the passengers
+    if (tile_bits != 0 && (tile_bits < kPassRegBits[dtype] + 4 || tile_bits > kPassTileBits[dtype]))
+        return fail(QAA_ERR_INVALID_ARG, "qaa_debug_pass_descs: tile_bits must be 0 or in %d..%d",
+                    kPassRegBits[dtype] + 4, kPassTileBits[dtype]);
     if (steps < 0 || k0 < 0 || k1 < k0 || k1 > steps || !count)
         return fail(QAA_ERR_INVALID_ARG, "qaa_debug_pass_descs: bad step range");
     if (desc_bytes) *desc_bytes = (int32_t)sizeof(PassDesc);
     SchedKnots sc;
     qaa_status r = to_knots(sched, &sc, "qaa_debug_pass_descs");
     if (r != QAA_OK) return r;
-    const Plan p = make_plan(n, (int)dtype);
+    const Plan p = make_plan(n, (int)dtype, tile_bits);
     if (p.resident || k0 == k1) {
         *count = 0;
         return ok();

@@ -133,7 +133,7 @@ def test_bad_schedules_are_rejected(sched, msg):
         assert lib.qaa_evolve_batch(1, states, scheds, t_arr, n_arr, None) == qaa.QAA_ERR_INVALID_ARG
         assert msg in qaa.qaa_last_error()
         cnt, size = ctypes.c_int32(), ctypes.c_int32()
-        assert lib.qaa_debug_pass_descs(20, 0, 10, ctypes.byref(sc), 1.0, 10, 0, 10, None, 0, ctypes.byref(cnt),
+        assert lib.qaa_debug_pass_descs(20, 0, 10, ctypes.byref(sc), 1.0, 10, 0, 10, 0, None, 0, ctypes.byref(cnt),
                                         ctypes.byref(size)) == qaa.QAA_ERR_INVALID_ARG
     finally:
         qaa.qaa_instance_destroy(h)

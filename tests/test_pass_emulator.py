@@ -31,17 +31,19 @@ def _pad(l, dtype):
     return l + (2 * (l >> 5) if dtype == 0 else (l >> 4))
 
 
-def _replay(n, dtype, E, psi, T, N, k0, k1, knots=None):
-    plan = qaa.qaa_plan_info(n, dtype)
-    TB = plan["tile_bits"]
+def _replay(n, dtype, E, psi, T, N, k0, k1, knots=None, tile_bits=0):
+    descs = qaa.qaa_debug_pass_descs(n, dtype, int(E.max()), T, N, k0, k1, knots, tile_bits=tile_bits)
+    if not descs:
+        return psi, descs
+    TB = n - descs[0].n_rest
+    assert TB == (tile_bits or qaa.qaa_plan_info(n, dtype)["tile_bits"])
     RB = 5 if dtype == qaa.QAA_C64 else 4
     WB = TB - RB
     R, WG = 1 << RB, 1 << WB
     TSP = _pad(1 << TB, dtype)
-    descs = qaa.qaa_debug_pass_descs(n, dtype, int(E.max()), T, N, k0, k1, knots)
     tid = np.arange(WG, dtype=np.int64)
-    reg = np.arange(R, dtype=np.int64)
     for d in descs:
+        assert n - d.n_rest == TB
         tile_pos = list(d.tile_pos[:TB])
         rest_pos = list(d.rest_pos[:d.n_rest])
         assert sorted(tile_pos + rest_pos) == list(range(n))
@@ -131,6 +133,43 @@ def test_pass_plan_replays_the_oracle(n, dtype, T, N):
     ref = oracle.init_uniform(n)
     oracle.evolve(n, inst.clauses, ref, T, N)
     assert np.max(np.abs(got - ref)) < 1e-12
+
+
+@pytest.mark.parametrize("n,dtype,tile_bits,sets,T,N", [
+    (16, 0, 10, 3, 6.0, 4),     # 10 + 5 + 1: a ragged top set
+    (20, 0, 10, 3, 5.0, 3),     # 10 + 5 + 5: three full sets, as n = 28 runs
+    (21, 0, 10, 4, 5.0, 3),     # 10 + 5 + 5 + 1: four sets, as n = 30..34 run
+    (22, 0, 9, 5, 4.0, 2),      # 9 + 4 + 4 + 4 + 1: five sets
+    (18, 1, 9, 3, 5.0, 3),      # complex128: 9 + 5 + 4
+    (21, 1, 8, 5, 5.0, 2),      # complex128: 8 + 4 + 4 + 4 + 1
+])
+def test_smaller_tile_plans_replay_the_oracle(n, dtype, tile_bits, sets, T, N):
+    """The planner's plans for smaller tiles: three, four and five qubit
+    sets (the shapes n = 28..34 run with the library's tiles) at sizes the
+    oracle handles, with clauses, replayed against the oracle.  Covers the
+    zig-zag set order, the passenger-qubit move and the turn passes of
+    every plan depth."""
+    inst = planted_unique_3sat(n, 700 + n)
+    E = oracle.energy(n, inst.clauses).astype(np.int64)
+    psi = np.full(1 << n, 2.0 ** (-n / 2), np.complex128)
+    got, descs = _replay(n, dtype, E, psi, T, N, 0, N, tile_bits=tile_bits)
+    n_sets = len({d.set_id for d in descs})
+    assert n_sets == sets
+    assert len(descs) == (n_sets - 1) * N + 1
+    ref = oracle.init_uniform(n)
+    oracle.evolve(n, inst.clauses, ref, T, N)
+    assert np.max(np.abs(got - ref)) < 1e-12
+
+
+def test_smaller_tile_override_is_checked():
+    with pytest.raises(qaa.QaaError):
+        qaa.qaa_debug_pass_descs(20, 0, 10, 5.0, 10, 0, 10, tile_bits=8)
+    with pytest.raises(qaa.QaaError):
+        qaa.qaa_debug_pass_descs(20, 0, 10, 5.0, 10, 0, 10, tile_bits=14)
+    # the library's own tile size gives the library's own plan
+    a = qaa.qaa_debug_pass_descs(20, 0, 10, 5.0, 10, 0, 10, tile_bits=13)
+    b = qaa.qaa_debug_pass_descs(20, 0, 10, 5.0, 10, 0, 10)
+    assert [bytes(x) for x in a] == [bytes(x) for x in b]
 
 
 @pytest.mark.parametrize("n,T,N,chunk_log2", [(22, 5.0, 3, 19), (22, 4.0, 2, 20)])
