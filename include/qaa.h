@@ -31,7 +31,8 @@
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Calls are asynchronous on it unless stated otherwise.
  *  - Library-owned device memory: a device copy of each instance's clause
- *    list and per-call buffers (norm
+ *    list, the 256-byte scratch array of qaa_evolve_range_noalloc (one per
+ *    device, held until the process ends), and per-call buffers (norm
  *    accumulators, reduction partials, batch descriptors, qaa_spectrum's
  *    Lanczos vectors) taken from the stream-ordered allocator and released
  *    in stream order by the call that took them.
@@ -193,6 +194,25 @@ qaa_status qaa_evolve(const qaa_state *st, const qaa_schedule *sched, double T,
  */
 qaa_status qaa_evolve_range(const qaa_state *st, const qaa_schedule *sched, double T,
                             int64_t steps, int64_t k0, int64_t k1, void *stream);
+
+/*
+ * For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the same
+ * evolution as qaa_evolve_range (same arguments, same kernels, bit-identical
+ * results), but it allocates nothing.  The only device scratch an evolution
+ * needs, three 64-bit norm-control accumulators, lives in a library-owned
+ * static device array of 256 bytes per device (held until the process
+ * ends; its address is looked up once per device on the first call there).
+ * Every state the library accepts fits it, so no size is refused beyond
+ * what qaa_evolve_range refuses.  All calls on one device share that array
+ * and a call clears it (with a kernel, not a memset) before use: calls that
+ * overlap on one device -- on different streams or threads -- race and
+ * must be serialised by the caller.  Asynchronous; errors as for
+ * qaa_evolve_range, plus QAA_ERR_DEVICE if the array's address cannot be
+ * obtained.
+ */
+qaa_status qaa_evolve_range_noalloc(const qaa_state *st, const qaa_schedule *sched, double T,
+                                    int64_t steps, int64_t k0, int64_t k1, void *stream);
 
 /*
  * Evolve `count` independent states together.  states[i], T[i] and

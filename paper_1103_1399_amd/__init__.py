@@ -119,6 +119,8 @@ _SIGS = {
                          ctypes.c_int64, _vp]),
     "qaa_evolve_range": (_st, [ctypes.POINTER(qaa_state), ctypes.POINTER(qaa_schedule), ctypes.c_double,
                                ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _vp]),
+    "qaa_evolve_range_noalloc": (_st, [ctypes.POINTER(qaa_state), ctypes.POINTER(qaa_schedule), ctypes.c_double,
+                                       ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _vp]),
     "qaa_evolve_batch": (_st, [ctypes.c_int32, ctypes.POINTER(qaa_state), ctypes.POINTER(qaa_schedule), _f64p,
                                _i64p, _vp]),
     "qaa_observables": (_st, [ctypes.POINTER(qaa_state), ctypes.POINTER(qaa_obs), _vp]),
@@ -252,6 +254,15 @@ def qaa_evolve_range(state: qaa_state, T: float, steps: int, k0: int, k1: int, s
     sched = make_schedule(knots)
     _check(_lib.qaa_evolve_range(ctypes.byref(state), ctypes.byref(sched), float(T), int(steps), int(k0), int(k1),
                                  _stream_ptr(stream)), "qaa_evolve_range")
+
+
+def qaa_evolve_range_noalloc(state: qaa_state, T: float, steps: int, k0: int, k1: int, stream=None,
+                             knots=None) -> None:
+    """qaa_evolve_range without any device allocation (library-owned static
+    scratch; overlapping calls on one device race)."""
+    sched = make_schedule(knots)
+    _check(_lib.qaa_evolve_range_noalloc(ctypes.byref(state), ctypes.byref(sched), float(T), int(steps), int(k0),
+                                         int(k1), _stream_ptr(stream)), "qaa_evolve_range_noalloc")
 
 
 def qaa_evolve_batch(states, Ts, steps, stream=None, knots=None) -> None:

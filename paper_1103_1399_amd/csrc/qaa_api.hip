@@ -1,6 +1,6 @@
 // qaa_api.hip -- host runtime behind include/qaa.h: argument validation,
 // instance encoding, the pass planner, the per-step pass sequence and the
-// per-call scratch of the reductions.
+// per-device scratch used by reductions.
 #include "qaa.h"
 #include "qaa_internal.h"
 
@@ -878,14 +878,21 @@ bool norm_control_enabled()
     return on;
 }
 
+// fixed_acc: nullptr, or three norm-control accumulators the caller owns
+// (qaa_evolve_range_noalloc); otherwise they come from the stream-ordered
+// allocator for this call.
 qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, double T, int64_t N, int64_t k0,
-                      int64_t k1, hipStream_t s)
+                      int64_t k1, hipStream_t s, unsigned long long *fixed_acc)
 {
     const std::vector<PassDesc> ps =
         plan_passes(p, st->inst->n, (int)st->dtype, st->inst->e_max, sc, T, N, k0, k1);
     unsigned long long *acc = nullptr;
+    const bool own_acc = fixed_acc == nullptr;
     if (norm_control_enabled()) {
-        QAA_HIP(hipMallocAsync(reinterpret_cast<void **>(&acc), 3 * sizeof(unsigned long long), s));
+        if (own_acc)
+            QAA_HIP(hipMallocAsync(reinterpret_cast<void **>(&acc), 3 * sizeof(unsigned long long), s));
+        else
+            acc = fixed_acc;
         // a fill kernel, not a memset node: callers may capture this call
         QAA_HIP(launch_zero_u64(acc, 3, s));
     }
@@ -941,7 +948,7 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, 
         }
         hipError_t e = launch_pass(st->amp, (int)st->dtype, st->table, (int)st->etype, p.tile_bits, p.reg_bits, d, s);
         if (e != hipSuccess) {
-            if (acc) (void)hipFreeAsync(acc, s);
+            if (acc && own_acc) (void)hipFreeAsync(acc, s);
             return fail(QAA_ERR_DEVICE, "pass launch failed: %s", hipGetErrorString(e));
         }
         if (prof) {
@@ -950,7 +957,7 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, 
             g_prof_live.push_back(rec);
         }
     }
-    if (acc) QAA_HIP(hipFreeAsync(acc, s));
+    if (acc && own_acc) QAA_HIP(hipFreeAsync(acc, s));
     return QAA_OK;
 }
 
@@ -980,10 +987,47 @@ qaa_status qaa::to_knots(const qaa_schedule *sched, SchedKnots *out, const char 
     return QAA_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Evolution without device allocation.  The three norm-control accumulators
+// of a multi-pass evolution live in `scratch`, a static device array of this
+// translation unit (each device the library runs on holds its own copy until
+// the process ends), instead of the stream-ordered allocator.  Host code
+// never uses the array's name as a device address: at a device's first call
+// its address comes from hipGetSymbolAddress, with that device current, and
+// is kept per device.  Every call on a device shares the array; it is
+// cleared by a fill kernel at the start of each multi-pass call, so calls
+// that overlap on one device race.
+// ---------------------------------------------------------------------------
 namespace {
 
+constexpr int kScratchWords = 32;     // 256 bytes; a call uses 3 words
+static __device__ __align__(256) unsigned long long scratch[kScratchWords];
+
+std::mutex g_scratch_mu;
+std::map<int, unsigned long long *> g_scratch_addr;
+
+qaa_status scratch_address(unsigned long long **out, const char *who)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(QAA_ERR_DEVICE, "%s: hipGetDevice failed: %s", who, hipGetErrorString(e));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(dev);
+    if (it == g_scratch_addr.end()) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(QAA_ERR_DEVICE, "%s: hipGetSymbolAddress(scratch) failed on device %d: %s", who, dev,
+                        hipGetErrorString(e));
+        it = g_scratch_addr.emplace(dev, reinterpret_cast<unsigned long long *>(ptr)).first;
+    }
+    *out = it->second;
+    return QAA_OK;
+}
+
+
 qaa_status evolve_common(const qaa_state *st, const qaa_schedule *sched, double T, int64_t steps, int64_t k0,
-                         int64_t k1, void *stream, const char *who)
+                         int64_t k1, void *stream, const char *who, bool noalloc = false)
 {
     SchedKnots sc;
     qaa_status r = to_knots(sched, &sc, who);
@@ -1000,7 +1044,19 @@ qaa_status evolve_common(const qaa_state *st, const qaa_schedule *sched, double 
     if (k0 == k1) return ok();
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const Plan p = make_plan(st->inst->n, (int)st->dtype);
-    r = p.resident ? run_resident(st, sc, T, steps, k0, k1, s) : run_passes(st, p, sc, T, steps, k0, k1, s);
+    if (p.resident) {
+        r = run_resident(st, sc, T, steps, k0, k1, s);
+    } else {
+        // the accumulators do not grow with n: every state the library
+        // accepts (n <= QAA_MAX_QUBITS) fits the scratch array
+        static_assert(3 <= kScratchWords, "norm-control accumulators exceed the scratch array");
+        unsigned long long *fixed_acc = nullptr;
+        if (noalloc) {
+            r = scratch_address(&fixed_acc, who);
+            if (r != QAA_OK) return r;
+        }
+        r = run_passes(st, p, sc, T, steps, k0, k1, s, fixed_acc);
+    }
     if (r != QAA_OK) return r;
     return ok();
 }
@@ -1018,6 +1074,13 @@ extern "C" qaa_status qaa_evolve_range(const qaa_state *st, const qaa_schedule *
 {
     return evolve_common(st, sched, T, steps, k0, k1, stream, "qaa_evolve_range");
 }
+
+extern "C" qaa_status qaa_evolve_range_noalloc(const qaa_state *st, const qaa_schedule *sched, double T,
+                                               int64_t steps, int64_t k0, int64_t k1, void *stream)
+{
+    return evolve_common(st, sched, T, steps, k0, k1, stream, "qaa_evolve_range_noalloc", true);
+}
+
 
 namespace {
 

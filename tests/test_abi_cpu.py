@@ -85,6 +85,12 @@ def test_evolve_rejects_before_any_device_call():
         rc = lib.qaa_evolve(ctypes.byref(st), ctypes.byref(sched), 1.0, 10, None)
         assert rc == qaa.QAA_ERR_NOT_READY
         assert "qaa_energy_table" in qaa.qaa_last_error()
+        # the allocation-free variant validates the same way, before it
+        # looks up its device scratch
+        rc = lib.qaa_evolve_range_noalloc(ctypes.byref(st), ctypes.byref(sched), 1.0, 10, 0, 10, None)
+        assert rc == qaa.QAA_ERR_NOT_READY
+        assert "qaa_evolve_range_noalloc" in qaa.qaa_last_error()
+        assert lib.qaa_evolve_range_noalloc(None, None, 1.0, 10, 0, 10, None) == qaa.QAA_ERR_INVALID_ARG
         # NULL state / missing buffers
         assert lib.qaa_evolve(None, None, 1.0, 10, None) == qaa.QAA_ERR_INVALID_ARG
         bad = qaa.qaa_state(h, None, qaa.QAA_C64, 0x2000, qaa.QAA_E_U8)
