@@ -120,6 +120,15 @@ qaa_status qaa_instance_info(const qaa_instance *inst, int32_t *n, int32_t *m,
  */
 qaa_status qaa_energy_table(qaa_instance *inst, void *d_table, qaa_etype etype, void *stream);
 
+/*
+ * Diagnostic: the energy kernel's arithmetic for one thread, run on the
+ * host: out32[i] = E(z0 + i), i = 0..31 (z0 a multiple of 32 below 2^n; for
+ * n < 5 only z0 = 0, and entries at i >= 2^n carry no meaning).  Host memory
+ * only; exists so that host-side tests can check the bit-sliced counting
+ * without a device.
+ */
+qaa_status qaa_debug_energy_block(const qaa_instance *inst, uint64_t z0, int32_t *out32);
+
 /* ---------------------------------------------------------------------
  * States.
  * ------------------------------------------------------------------- */
@@ -365,29 +374,39 @@ qaa_status qaa_plan_info(int32_t n, qaa_dtype dtype, int32_t *tile_bits, int32_t
                          int32_t *passes_per_step);
 
 /*
- * Qubit assignment of a plan with two or more sets (the tile shapes are
- * fixed; which set rotates which qubit is not):
+ * How a plan with two or more sets assigns qubits and tiles:
  *   balance    : 1 = the top set also rotates set 0's highest qubits, up to
- *                as many as a set above set 0 can hold.
+ *                as many as its tile can hold.
  *   passengers : 1 = with three or more sets, the low "passenger" qubits
  *                (1..4 for complex64, 0..3 for complex128), which ride in
  *                every set's tiles, rotate in the set-1 passes instead of
  *                the set-0 turn.
+ *   tiles      : 0 = every set in the base tile (2^13 amplitudes for
+ *                complex64, 2^12 for complex128); 1 = the top set's passes
+ *                in 2^14-amplitude tiles (longer contiguous runs in the pass
+ *                that gathers from the whole state); 2 = every set in
+ *                2^14-amplitude tiles, the qubits above set 0 split evenly.
+ *                Tiles 1 and 2 apply to complex64 states with a uint8 table
+ *                and n >= 22 only (elsewhere, and in qaa_evolve_batch, the
+ *                base tile is used whatever is recorded).
  * Results do not depend on the choice beyond FP32 rounding order.  The
  * choice is process-wide per (n, dtype); the environment variables
- * QAA_PLAN_BALANCE / QAA_PLAN_PASSENGERS (0 or 1), if set, override it.
+ * QAA_PLAN_BALANCE / QAA_PLAN_PASSENGERS (0 or 1) and QAA_PLAN_TILES
+ * (0, 1 or 2), if set, override it.
  */
 typedef struct qaa_plan_choice {
     int32_t balance;
     int32_t passengers;
+    int32_t tiles;
 } qaa_plan_choice;
 
-/* The choice in effect for (n, dtype): recorded, else the built-in default
- * (balance for two sets, passengers for three or more). */
+/* The choice in effect for (n, dtype) with a uint8 table: recorded, else
+ * the built-in default (balance for two sets, passengers for three or
+ * more, the tiles measured fastest for n). */
 qaa_status qaa_plan_get(int32_t n, qaa_dtype dtype, qaa_plan_choice *out);
 
-/* Record a choice for (n, dtype) (each field 0 or 1); NULL restores the
- * default.  Affects calls made after it returns. */
+/* Record a choice for (n, dtype) (balance and passengers 0 or 1, tiles 0, 1
+ * or 2); NULL restores the default.  Affects calls made after it returns. */
 qaa_status qaa_plan_set(int32_t n, qaa_dtype dtype, const qaa_plan_choice *choice);
 
 /*
@@ -416,9 +435,12 @@ qaa_status qaa_debug_tridiag_levels(const double *alpha, const double *beta, int
  * n-qubit state (energies up to emax) over steps k0..k1-1 of `steps`
  * under schedule `sched` (NULL: linear).
  *   tile_bits : 0 for the library's own plan; otherwise the plan the same
- *               planner makes for tiles of that many qubits (complex64
- *               9..13, complex128 8..12).  Smaller tiles give plans with
- *               three and four qubit sets already at small n, so host-side
+ *               planner makes for base tiles of that many qubits (complex64
+ *               9..13, complex128 8..12) and, where the plan choice asks for
+ *               wider tiles (qaa_plan_choice.tiles, honoured from
+ *               n >= tile_bits + 9), wide tiles one qubit larger.  Smaller
+ *               tiles give the plan shapes of large n (three to five qubit
+ *               sets, wide top sets) already at small n, so host-side
  *               replays can check them against a reference; no kernel runs
  *               such tiles.  QAA_ERR_INVALID_ARG outside that range.
  * Writes up to `capacity` descriptors of *desc_bytes bytes each into the

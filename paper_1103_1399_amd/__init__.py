@@ -90,7 +90,7 @@ class qaa_obs(ctypes.Structure):
 
 
 class qaa_plan_choice(ctypes.Structure):
-    _fields_ = [("balance", ctypes.c_int32), ("passengers", ctypes.c_int32)]
+    _fields_ = [("balance", ctypes.c_int32), ("passengers", ctypes.c_int32), ("tiles", ctypes.c_int32)]
 
 
 class qaa_server_config(ctypes.Structure):
@@ -113,6 +113,7 @@ _SIGS = {
     "qaa_instance_destroy": (None, [_vp]),
     "qaa_instance_info": (_st, [_vp, _i32p, _i32p, _i32p, _i32p, _i64p]),
     "qaa_energy_table": (_st, [_vp, _vp, ctypes.c_int, _vp]),
+    "qaa_debug_energy_block": (_st, [_vp, ctypes.c_uint64, _i32p]),
     "qaa_state_init_uniform": (_st, [ctypes.POINTER(qaa_state), _vp]),
     "qaa_state_init_basis": (_st, [ctypes.POINTER(qaa_state), ctypes.c_uint64, _vp]),
     "qaa_evolve": (_st, [ctypes.POINTER(qaa_state), ctypes.POINTER(qaa_schedule), ctypes.c_double,
@@ -213,6 +214,13 @@ def _check_buffer(t, n: int, elem_bytes: int, what: str) -> None:
 def qaa_energy_table(handle: int, table, etype: int, stream=None) -> None:
     _check_buffer(table, qaa_instance_info(handle)["n"], 1 if int(etype) == QAA_E_U8 else 2, "energy table")
     _check(_lib.qaa_energy_table(handle, table.data_ptr(), int(etype), _stream_ptr(stream)), "qaa_energy_table")
+
+
+def qaa_debug_energy_block(handle: int, z0: int):
+    """E(z0 .. z0 + 31) by the energy kernel's arithmetic, on the host."""
+    out = (ctypes.c_int32 * 32)()
+    _check(_lib.qaa_debug_energy_block(handle, int(z0), out), "qaa_debug_energy_block")
+    return list(out)
 
 
 def make_state(handle: int, amp, table=None, etype: int | None = None) -> qaa_state:
@@ -388,7 +396,7 @@ def qaa_profile_read(reset: bool = True) -> dict:
 def qaa_plan_get(n: int, dtype: int = QAA_C64) -> dict:
     c = qaa_plan_choice()
     _check(_lib.qaa_plan_get(int(n), int(dtype), ctypes.byref(c)), "qaa_plan_get")
-    return {"balance": c.balance, "passengers": c.passengers}
+    return {"balance": c.balance, "passengers": c.passengers, "tiles": c.tiles}
 
 
 def qaa_plan_set(n: int, dtype: int = QAA_C64, choice: dict | None = None) -> None:
@@ -396,7 +404,7 @@ def qaa_plan_set(n: int, dtype: int = QAA_C64, choice: dict | None = None) -> No
     if choice is None:
         _check(_lib.qaa_plan_set(int(n), int(dtype), None), "qaa_plan_set")
         return
-    c = qaa_plan_choice(int(choice["balance"]), int(choice["passengers"]))
+    c = qaa_plan_choice(int(choice["balance"]), int(choice["passengers"]), int(choice.get("tiles", 0)))
     _check(_lib.qaa_plan_set(int(n), int(dtype), ctypes.byref(c)), "qaa_plan_set")
 
 
@@ -405,7 +413,7 @@ def qaa_autotune(state: qaa_state, steps: int = 20, stream=None) -> dict:
     ms = ctypes.c_double()
     _check(_lib.qaa_autotune(ctypes.byref(state), int(steps), ctypes.byref(best), ctypes.byref(ms),
                              _stream_ptr(stream)), "qaa_autotune")
-    return {"balance": best.balance, "passengers": best.passengers, "ms_per_step": ms.value}
+    return {"balance": best.balance, "passengers": best.passengers, "tiles": best.tiles, "ms_per_step": ms.value}
 
 
 def _result_dict(r: qaa_server_result) -> dict:

@@ -101,59 +101,128 @@ __host__ __device__ inline Rot<F> make_rot(double t, double s)
 template <typename ET> constexpr int lut_cap() { return sizeof(ET) == 1 ? kLutMaxU8 : kLutMax; }
 
 // ---------------------------------------------------------------------------
-// Energy table.  Thread t scores z = 8t .. 8t+7 against every clause with
-// 16-bit packed counters (no overflow: m <= 65535).
+// Energy table, bit-sliced.  Thread t scores z = 32t .. 32t+31 at once: for
+// each clause the 32 outcomes form one word (bit i: z = 32t + i violates
+// it), and the words are summed bit-parallel into counter planes (plane p
+// holds bit p of the 32 counts).  Eight clauses at a time go through a
+// carry-save tree (ones, twos and fours are running planes; the eights it
+// produces ripple into the planes above), about 9 word operations per clause
+// for 32 basis states.  K planes count up to 2^K - 1: K = 8 when m <= 255,
+// else 16 (m <= 65535), so no count can overflow.
 // ---------------------------------------------------------------------------
-template <typename ET>
+
+// Carry-save adder on bit planes: a + b + c = lo + 2 hi, bit by bit.
+__host__ __device__ inline void csa(uint32_t &hi, uint32_t &lo, uint32_t a, uint32_t b, uint32_t c)
+{
+    const uint32_t u = a ^ b;
+    hi = (a & b) | (u & c);
+    lo = u ^ c;
+}
+
+// The counts of z = 32t .. 32t+31 (e[i] for z = 32t + i) against clauses
+// cl[0..m).  Shared by the kernel and the host-side check.
+template <int K>
+__host__ __device__ inline void energy_block(const ClauseRec *__restrict__ cl, int m, uint32_t t, uint32_t (&e)[32])
+{
+    auto word = [&](const ClauseRec &r) { return (t & r.mhi) == r.phi ? r.low : 0u; };
+    uint32_t ones = 0u, twos = 0u, fours = 0u;
+    uint32_t plane[K];
+#pragma unroll
+    for (int p = 0; p < K; ++p) plane[p] = 0u;
+    int c = 0;
+    for (; c + 8 <= m; c += 8) {
+        uint32_t w[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) w[j] = word(cl[c + j]);
+        uint32_t twos_a, twos_b, fours_a, fours_b, eights;
+        csa(twos_a, ones, ones, w[0], w[1]);
+        csa(twos_b, ones, ones, w[2], w[3]);
+        csa(fours_a, twos, twos, twos_a, twos_b);
+        csa(twos_a, ones, ones, w[4], w[5]);
+        csa(twos_b, ones, ones, w[6], w[7]);
+        csa(fours_b, twos, twos, twos_a, twos_b);
+        csa(eights, fours, fours, fours_a, fours_b);
+        uint32_t carry = eights;
+#pragma unroll
+        for (int p = 3; p < K; ++p) {
+            const uint32_t nc = plane[p] & carry;
+            plane[p] ^= carry;
+            carry = nc;
+        }
+    }
+    for (; c < m; ++c) {      // the last m mod 8 clauses: plain ripple adds
+        uint32_t carry = word(cl[c]);
+        uint32_t nc = ones & carry;
+        ones ^= carry;
+        carry = nc;
+        nc = twos & carry;
+        twos ^= carry;
+        carry = nc;
+        nc = fours & carry;
+        fours ^= carry;
+        carry = nc;
+#pragma unroll
+        for (int p = 3; p < K; ++p) {
+            nc = plane[p] & carry;
+            plane[p] ^= carry;
+            carry = nc;
+        }
+    }
+    plane[0] = ones;
+    plane[1] = twos;
+    plane[2] = fours;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+        uint32_t v = 0u;
+#pragma unroll
+        for (int p = 0; p < K; ++p) v |= ((plane[p] >> i) & 1u) << p;
+        e[i] = v;
+    }
+}
+
+template <typename ET, int K>
 __global__ void __launch_bounds__(256) energy_kernel(const ClauseRec *__restrict__ cl, int m, int n,
                                                      ET *__restrict__ table, uint32_t *__restrict__ stats)
 {
     const uint64_t dim = 1ull << n;
-    const uint64_t zb = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 8ull;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;     // n <= 34: t < 2^29
+    const uint64_t zb = (uint64_t)t * 32ull;
     uint32_t lo = 0xFFFFFFFFu, hi = 0u, over = 0u;
     if (zb < dim) {
-        uint64_t acc_a = 0, acc_b = 0;
-        for (int c = 0; c < m; ++c) {
-            const ClauseRec r = cl[c];
-            const bool hit = (zb & r.mhi) == r.phi;
-            acc_a += hit ? r.lo_a : 0ull;
-            acc_b += hit ? r.lo_b : 0ull;
-        }
-        const int cnt = dim < 8 ? (int)dim : 8;
-        uint32_t e[8];
+        uint32_t e[32];
+        energy_block<K>(cl, m, t, e);
+        const int cnt = dim < 32 ? (int)dim : 32;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            e[j] = (uint32_t)((acc_a >> (16 * j)) & 0xFFFFu);
-            e[j + 4] = (uint32_t)((acc_b >> (16 * j)) & 0xFFFFu);
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            if (j < cnt) {
-                lo = min(lo, e[j]);
-                hi = max(hi, e[j]);
+        for (int i = 0; i < 32; ++i) {
+            if (i < cnt) {
+                lo = min(lo, e[i]);
+                hi = max(hi, e[i]);
             }
         }
-        if (sizeof(ET) == 1) {
-            over = hi > 255u ? 1u : 0u;
-            if (cnt == 8) {
-                uint64_t packed = 0;
+        if (cnt == 32) {
+            if constexpr (sizeof(ET) == 1) {
+                over = hi > 255u ? 1u : 0u;
+                uint4 q[2];
+                uint32_t *qw = reinterpret_cast<uint32_t *>(q);
 #pragma unroll
-                for (int j = 0; j < 8; ++j) packed |= (uint64_t)(e[j] & 0xFFu) << (8 * j);
-                *reinterpret_cast<uint64_t *>(table + zb) = packed;
+                for (int d = 0; d < 8; ++d)
+                    qw[d] = (e[4 * d] & 0xFFu) | ((e[4 * d + 1] & 0xFFu) << 8) | ((e[4 * d + 2] & 0xFFu) << 16) |
+                            ((e[4 * d + 3] & 0xFFu) << 24);
+                uint4 *dst = reinterpret_cast<uint4 *>(table + zb);
+                dst[0] = q[0];
+                dst[1] = q[1];
             } else {
-                for (int j = 0; j < cnt; ++j) table[zb + j] = (ET)e[j];
+                uint4 q[4];
+                uint32_t *qw = reinterpret_cast<uint32_t *>(q);
+#pragma unroll
+                for (int d = 0; d < 16; ++d) qw[d] = (e[2 * d] & 0xFFFFu) | ((e[2 * d + 1] & 0xFFFFu) << 16);
+                uint4 *dst = reinterpret_cast<uint4 *>(table + zb);
+#pragma unroll
+                for (int d = 0; d < 4; ++d) dst[d] = q[d];
             }
         } else {
-            if (cnt == 8) {
-                uint4 packed;
-                packed.x = e[0] | (e[1] << 16);
-                packed.y = e[2] | (e[3] << 16);
-                packed.z = e[4] | (e[5] << 16);
-                packed.w = e[6] | (e[7] << 16);
-                *reinterpret_cast<uint4 *>(table + zb) = packed;
-            } else {
-                for (int j = 0; j < cnt; ++j) table[zb + j] = (ET)e[j];
-            }
+            if (sizeof(ET) == 1) over = hi > 255u ? 1u : 0u;
+            for (int i = 0; i < cnt; ++i) table[zb + i] = (ET)e[i];
         }
     }
     // wave reduction of min / max / overflow, one atomic per wave
@@ -549,12 +618,13 @@ __device__ __forceinline__ unsigned long long tile_loop(typename V2<F>::T *__res
     return ss;
 }
 
-// Two workgroups per CU (LDS-bound) means two waves per SIMD: the register
-// budget is held to that occupancy.
+// Two workgroups of 256 threads per CU (2^13-amplitude tiles, LDS-bound),
+// or one of 512 (2^14-amplitude tiles), means two waves per SIMD: the
+// register budget is held to that occupancy.
 // PIPE: persistent grid (workgroup b takes tiles b, b + grid, ...) with the
 // next tile's loads in flight; otherwise one workgroup per tile.
 template <typename F, typename ET, int TB, int RB, bool PHASE, bool PIPE>
-__global__ void __launch_bounds__(1 << (TB - RB), 2)
+__global__ void __launch_bounds__(1 << (TB - RB), (TB - RB) >= 9 ? 1 : 2)
 pass_kernel(typename V2<F>::T *__restrict__ amp, const ET *__restrict__ table, const PassDesc d)
 {
     if (d.acc_zero && blockIdx.x == 0 && threadIdx.x == 0) *d.acc_zero = 0ull;
@@ -987,11 +1057,15 @@ hipError_t launch_resident_t(const ResidentDesc *descs_dev, const ResidentDesc *
 }  // namespace
 
 // Tile shapes compiled into the library (planner picks among them).
-//   complex64 : tile 2^13 = 8192 amps, 32 per thread, 256 threads
+//   complex64 : tile 2^13 = 8192 amps, 32 per thread, 256 threads;
+//               tile 2^14 = 16384 amps, 32 per thread, 512 threads (uint8 table)
 //   complex128: tile 2^12 = 4096 amps, 16 per thread, 256 threads
 hipError_t launch_pass(void *amp, int dtype, const void *table, int etype, int tile_bits, int reg_bits,
                        const PassDesc &d, hipStream_t s)
 {
+    // 2^14-amplitude tiles: complex64 with a uint8 table only (LDS)
+    if (dtype == 0 && tile_bits == kWideTileBits && reg_bits == 5 && etype == 0)
+        return launch_pass_t<float, uint8_t, kWideTileBits, 5>(amp, table, d, s);
     if (dtype == 0 && tile_bits == 13 && reg_bits == 5) {
         if (etype == 0) return launch_pass_t<float, uint8_t, 13, 5>(amp, table, d, s);
         return launch_pass_t<float, uint16_t, 13, 5>(amp, table, d, s);
@@ -1071,15 +1145,35 @@ hipError_t launch_resident(const ResidentDesc *descs_dev, const ResidentDesc *on
 hipError_t launch_energy(const ClauseRec *cl, int m, int n, void *table, int etype, uint32_t *stats, hipStream_t s)
 {
     const uint64_t dim = 1ull << n;
-    const uint64_t threads = (dim + 7) / 8;
+    const uint64_t threads = (dim + 31) / 32;
     const unsigned grid = (unsigned)((threads + 255) / 256);
-    if (etype == 0)
-        hipLaunchKernelGGL((energy_kernel<uint8_t>), dim3(grid), dim3(256), 0, s, cl, m, n,
-                           reinterpret_cast<uint8_t *>(table), stats);
-    else
-        hipLaunchKernelGGL((energy_kernel<uint16_t>), dim3(grid), dim3(256), 0, s, cl, m, n,
-                           reinterpret_cast<uint16_t *>(table), stats);
+    const bool narrow = m <= 255;       // every count fits 8 planes
+    if (etype == 0) {
+        if (narrow)
+            hipLaunchKernelGGL((energy_kernel<uint8_t, 8>), dim3(grid), dim3(256), 0, s, cl, m, n,
+                               reinterpret_cast<uint8_t *>(table), stats);
+        else
+            hipLaunchKernelGGL((energy_kernel<uint8_t, 16>), dim3(grid), dim3(256), 0, s, cl, m, n,
+                               reinterpret_cast<uint8_t *>(table), stats);
+    } else {
+        if (narrow)
+            hipLaunchKernelGGL((energy_kernel<uint16_t, 8>), dim3(grid), dim3(256), 0, s, cl, m, n,
+                               reinterpret_cast<uint16_t *>(table), stats);
+        else
+            hipLaunchKernelGGL((energy_kernel<uint16_t, 16>), dim3(grid), dim3(256), 0, s, cl, m, n,
+                               reinterpret_cast<uint16_t *>(table), stats);
+    }
     return hipGetLastError();
+}
+
+void energy_block_host(const ClauseRec *cl, int m, uint32_t t, uint32_t *out32)
+{
+    uint32_t e[32];
+    if (m <= 255)
+        energy_block<8>(cl, m, t, e);
+    else
+        energy_block<16>(cl, m, t, e);
+    for (int i = 0; i < 32; ++i) out32[i] = e[i];
 }
 
 hipError_t launch_count_equal(const void *table, int etype, int n, int value, unsigned long long *count,

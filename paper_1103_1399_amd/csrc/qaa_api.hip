@@ -129,7 +129,8 @@ namespace {
 
 // Encode one clause: violated iff every literal is false, i.e. iff
 // x_v = 0 for each positive literal and x_v = 1 for each negated one
-// (Sec. 2.2).  mask = the three variable bits, pat = the negated ones.
+// (Sec. 2.2).  mask = the three variable bits, pat = the negated ones; the
+// record splits the test at bit 5 (see ClauseRec).
 ClauseRec encode_clause(const int32_t *c)
 {
     uint64_t mask = 0, pat = 0;
@@ -140,16 +141,12 @@ ClauseRec encode_clause(const int32_t *c)
         if (c[j] < 0) pat |= bit;
     }
     ClauseRec r;
-    r.mhi = mask & ~7ull;
-    r.phi = pat & ~7ull;
-    r.lo_a = r.lo_b = 0;
-    for (uint64_t j = 0; j < 8; ++j) {
-        const uint64_t hit = ((j & mask & 7ull) == (pat & 7ull)) ? 1ull : 0ull;
-        if (j < 4)
-            r.lo_a |= hit << (16 * j);
-        else
-            r.lo_b |= hit << (16 * (j - 4));
-    }
+    r.mhi = (uint32_t)(mask >> 5);
+    r.phi = (uint32_t)(pat >> 5);
+    r.low = 0;
+    for (uint32_t i = 0; i < 32; ++i)
+        if ((i & (uint32_t)(mask & 31)) == (uint32_t)(pat & 31)) r.low |= 1u << i;
+    r.pad_ = 0;
     return r;
 }
 
@@ -210,6 +207,17 @@ extern "C" qaa_status qaa_instance_info(const qaa_instance *inst, int32_t *n, in
     if (e_min) *e_min = inst->e_min;
     if (e_max) *e_max = inst->e_max;
     if (degeneracy) *degeneracy = inst->degeneracy;
+    return ok();
+}
+
+extern "C" qaa_status qaa_debug_energy_block(const qaa_instance *inst, uint64_t z0, int32_t *out32)
+{
+    if (!inst || !out32) return fail(QAA_ERR_INVALID_ARG, "qaa_debug_energy_block: NULL argument");
+    if (z0 % 32 || (inst->n >= 5 && z0 >= (1ull << inst->n)) || (inst->n < 5 && z0 != 0))
+        return fail(QAA_ERR_INVALID_ARG, "qaa_debug_energy_block: z0 must be a multiple of 32 below 2^n");
+    uint32_t e[32];
+    energy_block_host(inst->recs.data(), inst->m, (uint32_t)(z0 >> 5), e);
+    for (int i = 0; i < 32; ++i) out32[i] = (int32_t)e[i];
     return ok();
 }
 
@@ -330,45 +338,69 @@ extern "C" qaa_status qaa_state_init_basis(const qaa_state *st, uint64_t z0, voi
 namespace {
 
 struct SetPlan {
-    std::vector<int> tile;       // physical bits of the tile, ascending (size TB)
+    int tb = 0;                  // tile bits of this set's passes
+    std::vector<int> tile;       // physical bits of the tile, ascending (size tb)
     std::vector<int> rot_local;  // tile-local indices of the rotated qubits
 };
 
 struct Plan {
     bool resident = false;
-    int tile_bits = 0, reg_bits = 0;
+    int tile_bits = 0, reg_bits = 0;    // set 0's tile bits; register bits of every set
     std::vector<SetPlan> sets;
 };
 
-// Plan choices per (n, dtype).  balance: the top set takes set 0's highest
-// qubits until it rotates as many as a set above set 0 can.  passengers:
-// with three or more sets, the passenger qubits (except complex64's bit 0)
-// rotate in the set-1 passes (see make_plan).  Defaults, measured per n
-// (complex64): with two sets the turn over set 0 otherwise rotates up to 13
-// qubits twice against a handful in the other turn, and balancing gains up
-// to 6 % (n = 20); with three sets the top set's shorter contiguous runs
-// cost as much as set 0 saves (n = 26 and 28 lose about 1 %), so balancing
-// is off there, while moving the passengers is 3 % faster at n = 28.
-// qaa_plan_set / qaa_autotune record other choices; the environment
-// variables QAA_PLAN_BALANCE and QAA_PLAN_PASSENGERS (0 or 1) override all.
+// Plan choices per (n, dtype).
+//   balance: the top set takes set 0's highest qubits until it rotates as
+//     many as it can hold.
+//   passengers: with three or more sets, the passenger qubits (except
+//     complex64's bit 0) rotate in the set-1 passes (see make_plan).
+//   tiles (complex64 with a uint8 table, n >= 22 only): 0 = every set in
+//     2^13-amplitude tiles; 1 = the top set's passes in 2^14-amplitude tiles
+//     (7 or more passenger bits at n = 28: 1 KiB runs of state, 128-byte
+//     runs of the table); 2 = every set in 2^14-amplitude tiles with the
+//     high qubits split evenly over the sets above set 0.
+// Defaults, measured per n (complex64): with two sets the turn over set 0
+// otherwise rotates up to 13 qubits twice against a handful in the other
+// turn, and balancing gains up to 6 % (n = 20); with three sets the top
+// set's shorter contiguous runs cost as much as set 0 saves (n = 26 and 28
+// lose about 1 %), so balancing is off there, while moving the passengers
+// is 3 % faster at n = 28.  qaa_plan_set / qaa_autotune record other
+// choices; the environment variables QAA_PLAN_BALANCE, QAA_PLAN_PASSENGERS
+// (0 or 1) and QAA_PLAN_TILES (0, 1 or 2) override all.
 struct PlanChoice {
-    int balance, passengers;
+    int balance, passengers, tiles;     // -1: the default for the plan's shape
 };
 
 std::mutex g_plan_mu;
 std::map<std::pair<int, int>, PlanChoice> g_plan_choice;
 
-PlanChoice default_plan_choice(int sets) { return PlanChoice{sets == 2 ? 1 : 0, sets >= 3 ? 1 : 0}; }
+// Default tiles per n (complex64, measured: ms per step at T = 50, 5000-step
+// schedule).  The 2^14 top set pays where it removes a whole qubit set:
+// n = 22 runs two sets instead of three (0.063 -> 0.045 ms), n = 30 three
+// instead of four (10.4 -> 8.0 ms); n = 31, 32 reach three sets only with
+// 2^14 tiles everywhere.  Where the set count does not change, the 2^14
+// tiles' single workgroup per CU costs more than the longer runs gain
+// (n = 28: 1.71 -> 1.76 ms with the top set wide, 1.98 ms all wide).
+int default_tiles(int n, int dtype)
+{
+    if (dtype != 0) return 0;
+    if (n == 22 || n == 30) return 1;
+    if (n == 31 || n == 32) return 2;
+    return 0;
+}
+PlanChoice default_plan_choice(int sets) { return PlanChoice{sets == 2 ? 1 : 0, sets >= 3 ? 1 : 0, 0}; }
 
 int env_knob(const char *name)
 {
     const char *e = std::getenv(name);
-    return e ? (e[0] == '1' ? 1 : 0) : -1;
+    return e ? (e[0] >= '0' && e[0] <= '9' ? e[0] - '0' : 0) : -1;
 }
 
-PlanChoice plan_choice(int n, int dtype, int sets)
+// The recorded (or environment-forced) choice for (n, dtype); fields the
+// caller did not fix are -1.
+PlanChoice recorded_choice(int n, int dtype)
 {
-    PlanChoice c = default_plan_choice(sets);
+    PlanChoice c{-1, -1, -1};
     {
         std::lock_guard<std::mutex> lk(g_plan_mu);
         auto it = g_plan_choice.find({n, dtype});
@@ -376,64 +408,109 @@ PlanChoice plan_choice(int n, int dtype, int sets)
     }
     static const int force_balance = env_knob("QAA_PLAN_BALANCE");
     static const int force_passengers = env_knob("QAA_PLAN_PASSENGERS");
-    if (force_balance >= 0) c.balance = force_balance;
-    if (force_passengers >= 0) c.passengers = force_passengers;
+    static const int force_tiles = env_knob("QAA_PLAN_TILES");
+    if (force_balance >= 0) c.balance = force_balance ? 1 : 0;
+    if (force_passengers >= 0) c.passengers = force_passengers ? 1 : 0;
+    if (force_tiles >= 0) c.tiles = std::min(force_tiles, 2);
     return c;
 }
 
-// tile_override: 0 for the library's tile shape; otherwise a smaller tile
-// of that many bits, for host-side replay of plans with more qubit sets at
+// Whether 2^14-amplitude tiles can run this state: complex64 with a uint8
+// table (tile, padding, phase table and energies fill 154 KiB of the 160 KiB
+// of LDS), and n >= 22 (base tile + 9) so that plans below that keep their
+// two sets of base tiles.
+bool wide_tiles_ok(int n, int dtype, int etype, int base = kPassTileBits[0])
+{
+    return dtype == 0 && etype == 0 && n >= base + 9;
+}
+
+// The plan for n qubits.  etype matters only for the tile choice (wide
+// tiles need a uint8 table); uniform: every set in the library's base tile
+// (the batched kernel's requirement); tile_override: 0 for the library's
+// tile shape, otherwise a smaller base tile of that many bits (and a wide
+// tile one bit larger), for host-side replay of the same plan shapes at
 // small n (qaa_debug_pass_descs only: no kernel is built for such tiles).
-Plan make_plan(int n, int dtype, int tile_override = 0)
+Plan make_plan(int n, int dtype, int etype, bool uniform = false, int tile_override = 0, PlanChoice *used = nullptr)
 {
     Plan p;
-    const int TB = tile_override ? tile_override : kPassTileBits[dtype];
     if (n <= kResRegBits[dtype] + kResThrBits) {
         p.resident = true;
         return p;
     }
-    p.tile_bits = TB;
-    p.reg_bits = kPassRegBits[dtype];
+    const int base = tile_override ? tile_override : kPassTileBits[dtype];
     const int pas = kPassengerBits[dtype];
-    const int q = TB - pas;                    // qubits a set above set 0 can rotate
-    // Qubits above the tile go to sets of q, ascending.  The top set then
-    // takes set 0's highest qubits until it rotates q of them (set 0 keeps at
-    // least the passenger bits, which only it rotates): the turn passes over
-    // set 0 and over the top set then rotate comparable numbers of qubits.
+    PlanChoice c = recorded_choice(n, dtype);
+    const int wide = tile_override ? tile_override + 1 : kWideTileBits;
+    int tiles = c.tiles >= 0 ? c.tiles : (tile_override ? 0 : default_tiles(n, dtype));
+    if (uniform || !wide_tiles_ok(n, dtype, etype, base)) tiles = 0;
+    const int tb0 = tiles == 2 ? wide : base;
+    const int tb_mid = tiles == 2 ? wide : base;
+    const int tb_top = tiles >= 1 ? wide : base;
+    const int q_mid = tb_mid - pas, q_top = tb_top - pas;   // qubits a high set can rotate
+    // Qubits above set 0's tile go to the sets above it, ascending.  The
+    // lower high sets take q_mid each and the top set the rest (tiles 0,
+    // 1); with tiles 2 they are split evenly, the top set taking the
+    // smaller share (its passes gather from the whole state, so its
+    // passenger runs matter most).
+    const int H = n - tb0;
+    int h = 1;
+    while ((h - 1) * q_mid + q_top < H) ++h;
+    std::vector<int> sizes(h, 0);
+    if (tiles == 2) {
+        for (int j = 0; j < h; ++j) sizes[j] = H / h + (j < H % h ? 1 : 0);
+    } else {
+        int left = H;
+        for (int j = 0; j < h - 1; ++j) {
+            sizes[j] = std::min(q_mid, left);
+            left -= sizes[j];
+        }
+        sizes[h - 1] = left;
+    }
     std::vector<std::vector<int>> hi_sets;
-    for (int b = TB; b < n; b += q) {
+    for (int j = 0, b = tb0; j < h; b += sizes[j], ++j) {
         std::vector<int> r;
-        for (int j = b; j < std::min(n, b + q); ++j) r.push_back(j);
+        for (int q = b; q < b + sizes[j]; ++q) r.push_back(q);
         hi_sets.push_back(r);
     }
-    const PlanChoice choice = plan_choice(n, dtype, 1 + (int)hi_sets.size());
+    const PlanChoice def = default_plan_choice(1 + h);
+    const int balance = c.balance >= 0 ? c.balance : def.balance;
+    const int passengers = c.passengers >= 0 ? c.passengers : def.passengers;
+    if (used) *used = PlanChoice{balance, passengers, tiles};
+    p.tile_bits = tb0;
+    p.reg_bits = kPassRegBits[dtype];
+    // The top set takes set 0's highest qubits until it rotates q_top of
+    // them (set 0 keeps at least the passenger bits, which only it
+    // rotates): the turn passes over set 0 and over the top set then rotate
+    // comparable numbers of qubits.
     int moved = 0;
-    if (!hi_sets.empty() && choice.balance)
-        moved = std::min(q - (int)hi_sets.back().size(), TB - pas);
-    for (int j = 0; j < moved; ++j) hi_sets.back().push_back(TB - 1 - j);
+    if (balance) moved = std::min(q_top - (int)hi_sets.back().size(), tb0 - pas);
+    for (int j = 0; j < moved; ++j) hi_sets.back().push_back(tb0 - 1 - j);
     SetPlan s0;
-    for (int b = 0; b < TB; ++b) {
+    s0.tb = tb0;
+    for (int b = 0; b < tb0; ++b) {
         s0.tile.push_back(b);
-        if (b < TB - moved) s0.rot_local.push_back(b);
+        if (b < tb0 - moved) s0.rot_local.push_back(b);
     }
     p.sets.push_back(s0);
-    for (std::vector<int> r : hi_sets) {
+    for (size_t j = 0; j < hi_sets.size(); ++j) {
+        std::vector<int> r = hi_sets[j];
         std::sort(r.begin(), r.end());
-        SetPlan s;
-        const int extra = TB - (int)r.size();  // low passenger bits
-        for (int j = 0; j < extra; ++j) s.tile.push_back(j);
-        for (int b : r) s.tile.push_back(b);
-        std::sort(s.tile.begin(), s.tile.end());
-        for (int j = 0; j < TB; ++j)
-            if (std::find(r.begin(), r.end(), s.tile[j]) != r.end()) s.rot_local.push_back(j);
-        p.sets.push_back(s);
+        SetPlan st;
+        st.tb = j + 1 == hi_sets.size() ? tb_top : tb_mid;
+        const int extra = st.tb - (int)r.size();  // low passenger bits
+        for (int b = 0; b < extra; ++b) st.tile.push_back(b);
+        for (int b : r) st.tile.push_back(b);
+        std::sort(st.tile.begin(), st.tile.end());
+        for (int b = 0; b < st.tb; ++b)
+            if (std::find(r.begin(), r.end(), st.tile[b]) != r.end()) st.rot_local.push_back(b);
+        p.sets.push_back(st);
     }
     // With three or more sets, every step visits set 1 once, next to set 0
     // and with no phase in between, and set 1's tile holds the passenger
     // bits.  Those qubits' rotations move from set 0 to set 1: the turn
     // over set 0 then rotates 8 qubits twice instead of 13, the middle
     // passes (HBM-bound, with VALU to spare) 13 instead of 8.
-    if (p.sets.size() >= 3 && choice.passengers) {
+    if (p.sets.size() >= 3 && passengers) {
         // (complex64: bit 0 stays with set 0; it is a register bit of every
         // group, so it costs set 0 no extra exchange)
         const int lo = dtype == 0 ? 1 : 0;
@@ -446,6 +523,29 @@ Plan make_plan(int n, int dtype, int tile_override = 0)
         for (int j : p.sets[1].rot_local) r1.push_back(j);
         p.sets[1].rot_local = r1;
     }
+    return p;
+}
+
+// The plan under an explicit choice, whatever is recorded for (n, dtype).
+Plan make_plan_with(int n, int dtype, int etype, const PlanChoice &c)
+{
+    PlanChoice saved{-1, -1, -1};
+    bool had = false;
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        auto it = g_plan_choice.find({n, dtype});
+        if (it != g_plan_choice.end()) {
+            saved = it->second;
+            had = true;
+        }
+        g_plan_choice[{n, dtype}] = c;
+    }
+    Plan p = make_plan(n, dtype, etype);
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    if (had)
+        g_plan_choice[{n, dtype}] = saved;
+    else
+        g_plan_choice.erase({n, dtype});
     return p;
 }
 
@@ -686,7 +786,7 @@ std::vector<PassDesc> build_passes(const Plan &p, int n, int dty, int emax, cons
                                    int64_t N, int64_t k0, int64_t k1)
 {
     std::vector<PassDesc> out;
-    const int TB = p.tile_bits, RB = p.reg_bits;
+    const int RB = p.reg_bits;
     const int r = (int)p.sets.size();
     const double dt = T / (double)N;
     PassDesc base;
@@ -702,6 +802,7 @@ std::vector<PassDesc> build_passes(const Plan &p, int n, int dty, int emax, cons
             if (first && k > k0) continue;    // merged into the previous turn pass
             PassDesc d = base;
             const SetPlan &sp = p.sets[set];
+            const int TB = sp.tb;
             for (int j = 0; j < TB; ++j) d.tile_pos[j] = (uint8_t)sp.tile[j];
             int nr = 0;
             d.rest_mask = 0;
@@ -946,7 +1047,8 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, 
                         (2.0 * amp_bytes + (d.phase_at >= 0 ? e_bytes : 0.0));
             QAA_HIP(hipEventRecord(rec.a, s));
         }
-        hipError_t e = launch_pass(st->amp, (int)st->dtype, st->table, (int)st->etype, p.tile_bits, p.reg_bits, d, s);
+        hipError_t e = launch_pass(st->amp, (int)st->dtype, st->table, (int)st->etype, d.n - d.n_rest, p.reg_bits,
+                                   d, s);
         if (e != hipSuccess) {
             if (acc && own_acc) (void)hipFreeAsync(acc, s);
             return fail(QAA_ERR_DEVICE, "pass launch failed: %s", hipGetErrorString(e));
@@ -1043,7 +1145,7 @@ qaa_status evolve_common(const qaa_state *st, const qaa_schedule *sched, double 
                     lut_limit(st->etype) - 1);
     if (k0 == k1) return ok();
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const Plan p = make_plan(st->inst->n, (int)st->dtype);
+    const Plan p = make_plan(st->inst->n, (int)st->dtype, (int)st->etype);
     if (p.resident) {
         r = run_resident(st, sc, T, steps, k0, k1, s);
     } else {
@@ -1088,13 +1190,14 @@ namespace {
 // order documented at BatchInst.
 void batch_structs(const Plan &p, int n, int dty, std::vector<PassDesc> &out)
 {
-    const int TB = p.tile_bits, RB = p.reg_bits;
+    const int RB = p.reg_bits;
     const int r = (int)p.sets.size();
     auto make = [&](int set, bool v1, bool ph, bool v2) {
         PassDesc d;
         std::memset(&d, 0, sizeof d);
         d.n = n;
         const SetPlan &sp = p.sets[set];
+        const int TB = sp.tb;
         for (int j = 0; j < TB; ++j) d.tile_pos[j] = (uint8_t)sp.tile[j];
         int nr = 0;
         for (int b = 0; b < n; ++b)
@@ -1168,7 +1271,7 @@ qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states
     };
     std::map<int, GroupPlan> groups;
     for (int i : idx) {
-        const Plan p = make_plan(states[i].inst->n, dty);
+        const Plan p = make_plan(states[i].inst->n, dty, ety, true);
         GroupPlan &g = groups[(int)p.sets.size()];
         g.r = (int)p.sets.size();
         g.order.push_back(i);
@@ -1187,7 +1290,7 @@ qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states
         g.chunk_prefix.assign(1, 0);
         for (int i : g.order) {
             const int n = states[i].inst->n;
-            const Plan p = make_plan(n, dty);
+            const Plan p = make_plan(n, dty, ety, true);
             if (!base_of_n.count(n)) {
                 base_of_n[n] = (int)structs.size();
                 batch_structs(p, n, dty, structs);
@@ -1290,7 +1393,7 @@ extern "C" qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, c
     for (int i = 0; i < count; ++i) {
         if (steps[i] == 0) continue;
         const int dt = (int)states[i].dtype, et = (int)states[i].etype;
-        if (make_plan(states[i].inst->n, dt).resident)
+        if (make_plan(states[i].inst->n, dt, et, true).resident)
             small[dt][et].push_back(make_resident_desc(&states[i], scs[i], T[i], steps[i], 0, steps[i], kResRegBits[dt]));
         else
             large[dt][et].push_back(i);
@@ -1404,10 +1507,12 @@ extern "C" qaa_status qaa_plan_get(int32_t n, qaa_dtype dtype, qaa_plan_choice *
 {
     if (n < 1 || n > QAA_MAX_QUBITS || (dtype != QAA_C64 && dtype != QAA_C128) || !out)
         return fail(QAA_ERR_INVALID_ARG, "qaa_plan_get: bad argument");
-    const Plan p = make_plan(n, (int)dtype);
-    const PlanChoice c = plan_choice(n, (int)dtype, p.resident ? 1 : (int)p.sets.size());
+    PlanChoice c{0, 0, 0};
+    const Plan p = make_plan(n, (int)dtype, QAA_E_U8, false, 0, &c);
+    if (p.resident) c = default_plan_choice(1);
     out->balance = c.balance;
     out->passengers = c.passengers;
+    out->tiles = c.tiles;
     return ok();
 }
 
@@ -1416,11 +1521,11 @@ extern "C" qaa_status qaa_plan_set(int32_t n, qaa_dtype dtype, const qaa_plan_ch
     if (n < 1 || n > QAA_MAX_QUBITS || (dtype != QAA_C64 && dtype != QAA_C128))
         return fail(QAA_ERR_INVALID_ARG, "qaa_plan_set: bad argument");
     if (choice && ((choice->balance != 0 && choice->balance != 1) ||
-                   (choice->passengers != 0 && choice->passengers != 1)))
-        return fail(QAA_ERR_INVALID_ARG, "qaa_plan_set: choices are 0 or 1");
+                   (choice->passengers != 0 && choice->passengers != 1) || choice->tiles < 0 || choice->tiles > 2))
+        return fail(QAA_ERR_INVALID_ARG, "qaa_plan_set: balance and passengers are 0 or 1, tiles 0, 1 or 2");
     std::lock_guard<std::mutex> lk(g_plan_mu);
     if (choice)
-        g_plan_choice[{n, (int)dtype}] = PlanChoice{choice->balance, choice->passengers};
+        g_plan_choice[{n, (int)dtype}] = PlanChoice{choice->balance, choice->passengers, choice->tiles};
     else
         g_plan_choice.erase({n, (int)dtype});
     return ok();
@@ -1432,15 +1537,22 @@ extern "C" qaa_status qaa_autotune(const qaa_state *scratch, int64_t steps, qaa_
     qaa_status r = check_state_table(scratch, "qaa_autotune");
     if (r != QAA_OK) return r;
     if (steps < 1) return fail(QAA_ERR_INVALID_ARG, "qaa_autotune: steps < 1");
-    const int n = scratch->inst->n, dt = (int)scratch->dtype;
-    const Plan p0 = make_plan(n, dt);
+    const int n = scratch->inst->n, dt = (int)scratch->dtype, et = (int)scratch->etype;
+    const Plan p0 = make_plan(n, dt, et);
     std::vector<PlanChoice> cands;
-    if (p0.resident || p0.sets.size() < 2)
+    if (p0.resident || p0.sets.size() < 2) {
         cands.push_back(default_plan_choice(1));
-    else if (p0.sets.size() == 2)
-        cands = {PlanChoice{0, 0}, PlanChoice{1, 0}};
-    else
-        cands = {PlanChoice{0, 0}, PlanChoice{0, 1}, PlanChoice{1, 0}, PlanChoice{1, 1}};
+    } else {
+        const int max_tiles = wide_tiles_ok(n, dt, et) ? 2 : 0;
+        for (int t = 0; t <= max_tiles; ++t)
+            for (int b = 0; b <= 1; ++b)
+                for (int q = 0; q <= 1; ++q) {
+                    PlanChoice c{b, q, t};
+                    // the passenger move applies only to three or more sets
+                    if (q && make_plan_with(n, dt, et, c).sets.size() < 3) continue;
+                    cands.push_back(c);
+                }
+    }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     QAA_HIP(hipEventCreate(&e0));
@@ -1449,7 +1561,7 @@ extern "C" qaa_status qaa_autotune(const qaa_state *scratch, int64_t steps, qaa_
     float best_ms = 0.0f;
     PlanChoice best_c = cands[0];
     for (const PlanChoice &c : cands) {
-        const qaa_plan_choice qc{c.balance, c.passengers};
+        const qaa_plan_choice qc{c.balance, c.passengers, c.tiles};
         qaa_plan_set(n, scratch->dtype, &qc);
         r = qaa_state_init_uniform(scratch, stream);
         if (r == QAA_OK) r = qaa_evolve_range(scratch, nullptr, T, steps, 0, 1, stream);     // warm-up
@@ -1472,7 +1584,7 @@ extern "C" qaa_status qaa_autotune(const qaa_state *scratch, int64_t steps, qaa_
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    const qaa_plan_choice qb{best_c.balance, best_c.passengers};
+    const qaa_plan_choice qb{best_c.balance, best_c.passengers, best_c.tiles};
     qaa_plan_set(n, scratch->dtype, &qb);
     if (best) *best = qb;
     if (ms_per_step) *ms_per_step = (double)best_ms / (double)steps;
@@ -1484,7 +1596,7 @@ extern "C" qaa_status qaa_plan_info(int32_t n, qaa_dtype dtype, int32_t *tile_bi
 {
     if (n < 1 || n > QAA_MAX_QUBITS) return fail(QAA_ERR_INVALID_ARG, "qaa_plan_info: n out of range");
     if (dtype != QAA_C64 && dtype != QAA_C128) return fail(QAA_ERR_INVALID_ARG, "qaa_plan_info: bad dtype");
-    const Plan p = make_plan(n, (int)dtype);
+    const Plan p = make_plan(n, (int)dtype, QAA_E_U8);
     if (tile_bits) *tile_bits = p.resident ? 0 : p.tile_bits;
     if (sets) *sets = p.resident ? 1 : (int32_t)p.sets.size();
     if (passes_per_step) *passes_per_step = p.resident ? 0 : (int32_t)p.sets.size() - 1;
@@ -1508,7 +1620,7 @@ extern "C" qaa_status qaa_debug_pass_descs(int32_t n, qaa_dtype dtype, int32_t e
     SchedKnots sc;
     qaa_status r = to_knots(sched, &sc, "qaa_debug_pass_descs");
     if (r != QAA_OK) return r;
-    const Plan p = make_plan(n, (int)dtype, tile_bits);
+    const Plan p = make_plan(n, (int)dtype, QAA_E_U8, false, tile_bits);
     if (p.resident || k0 == k1) {
         *count = 0;
         return ok();

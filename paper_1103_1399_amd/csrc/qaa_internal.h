@@ -42,13 +42,13 @@ __host__ __device__ inline double sched_mid(const double *v, int count, int64_t 
 // One clause in the form the energy kernel consumes.  A clause over three
 // distinct variables is violated by z iff (z & mask) == pat, where mask has
 // the clause's three variable bits and pat has the bits of the negated
-// literals.  The kernel scores 8 consecutive z at once: the part of the test
-// on bits >= 3 (mhi/phi) is one compare for all 8, and lo_a/lo_b hold the
-// 0/1 outcome of the bits-0..2 part for z mod 8 = 0..3 / 4..7 as four 16-bit
-// lanes each, ready to be added to packed counters.
+// literals.  The kernel scores 32 consecutive z at once, so the test splits
+// at bit 5: the high part ((z >> 5) & mhi) == phi is one compare for all 32,
+// and bit i of `low` is the outcome of the low part for z & 31 == i.
 struct ClauseRec {
-    uint64_t mhi, phi;
-    uint64_t lo_a, lo_b;
+    uint32_t mhi, phi;     // mask / pattern bits >= 5, shifted down by 5
+    uint32_t low;          // bit i: (i & mask) == (pat & mask & 31), i = 0..31
+    uint32_t pad_;
 };
 
 // One HBM pass of the split-step evolution over tiles of 2^TB amplitudes.
@@ -170,6 +170,9 @@ struct BatchInst {
 // Kernel launch helpers (defined in the .hip files).
 hipError_t launch_energy(const ClauseRec *cl, int m, int n, void *table, int etype,
                          uint32_t *stats, hipStream_t s);
+// Host evaluation of the energy kernel's per-thread arithmetic: the counts
+// of z = 32t .. 32t+31 into out32[0..32) (for host-side checks).
+void energy_block_host(const ClauseRec *cl, int m, uint32_t t, uint32_t *out32);
 hipError_t launch_count_equal(const void *table, int etype, int n, int value,
                               unsigned long long *count, hipStream_t s);
 hipError_t launch_init_uniform(void *amp, int dtype, int n, hipStream_t s);
@@ -207,6 +210,9 @@ inline void resident_shape(int n, int *rb, int *wb)
 }
 // Pass tile shapes: complex64 2^13 (5 register bits), complex128 2^12 (4).
 constexpr int kPassTileBits[2] = {13, 12};
+// Wide tile (complex64 with a uint8 table only): 2^14 amplitudes, 512
+// threads x 32 registers, one workgroup per CU (154 KiB of LDS).
+constexpr int kWideTileBits = 14;
 constexpr int kPassRegBits[2] = {5, 4};
 // Low physical bits every high-qubit tile carries so that each global access
 // is a contiguous 256-byte run (32 complex64 / 16 complex128).

@@ -164,10 +164,13 @@ def test_good_schedule_passes_to_the_state_checks():
     (13, 0, (0, 1, 0)),
     (14, 0, (13, 2, 1)),
     (21, 0, (13, 2, 1)),
-    (22, 0, (13, 3, 2)),
+    (22, 0, (13, 2, 1)),        # the top set in a 2^14 tile holds the 9 high qubits
+    (23, 0, (13, 3, 2)),
     (28, 0, (13, 3, 2)),
     (29, 0, (13, 3, 2)),
-    (30, 0, (13, 4, 3)),
+    (30, 0, (13, 3, 2)),        # 13 + 8 + 9: the top set in a 2^14 tile
+    (31, 0, (14, 3, 2)),        # 14 + 9 + 8: every set in 2^14 tiles
+    (33, 0, (13, 4, 3)),
     (34, 0, (13, 4, 3)),
     (12, 1, (0, 1, 0)),
     (13, 1, (12, 2, 1)),
@@ -216,19 +219,30 @@ def test_one_hip_runtime_in_process():
     assert len(hip) == 1, hip
 
 
+def _bp(choice):
+    return {"balance": choice["balance"], "passengers": choice["passengers"]}
+
+
 def test_plan_choice_defaults_set_and_reset():
-    assert qaa.qaa_plan_get(16) == {"balance": 1, "passengers": 0}      # two sets
-    assert qaa.qaa_plan_get(28) == {"balance": 0, "passengers": 1}      # three sets
+    assert _bp(qaa.qaa_plan_get(16)) == {"balance": 1, "passengers": 0}      # two sets
+    assert qaa.qaa_plan_get(16)["tiles"] == 0                                # below n = 22: base tiles only
+    assert _bp(qaa.qaa_plan_get(28)) == {"balance": 0, "passengers": 1}      # three sets
+    default28 = qaa.qaa_plan_get(28)
     try:
-        qaa.qaa_plan_set(28, qaa.QAA_C64, {"balance": 1, "passengers": 0})
-        assert qaa.qaa_plan_get(28) == {"balance": 1, "passengers": 0}
-        assert qaa.qaa_plan_get(28, qaa.QAA_C128) == {"balance": 0, "passengers": 1}   # per dtype
+        qaa.qaa_plan_set(28, qaa.QAA_C64, {"balance": 1, "passengers": 0, "tiles": 2})
+        assert qaa.qaa_plan_get(28) == {"balance": 1, "passengers": 0, "tiles": 2}
+        assert qaa.qaa_plan_info(28)["tile_bits"] == 14
+        assert qaa.qaa_plan_get(28, qaa.QAA_C128)["tiles"] == 0          # per dtype; complex128: base tiles
+        qaa.qaa_plan_set(28, qaa.QAA_C128, {"balance": 0, "passengers": 1, "tiles": 2})
+        assert qaa.qaa_plan_get(28, qaa.QAA_C128)["tiles"] == 0          # recorded but not applicable
+        assert qaa.qaa_plan_info(28, qaa.QAA_C128)["tile_bits"] == 12
     finally:
         qaa.qaa_plan_set(28, qaa.QAA_C64, None)
-    assert qaa.qaa_plan_get(28) == {"balance": 0, "passengers": 1}
+        qaa.qaa_plan_set(28, qaa.QAA_C128, None)
+    assert qaa.qaa_plan_get(28) == default28
     lib = qaa._lib
-    bad = qaa.qaa_plan_choice(2, 0)
-    assert lib.qaa_plan_set(28, 0, ctypes.byref(bad)) == qaa.QAA_ERR_INVALID_ARG
+    for bad in (qaa.qaa_plan_choice(2, 0, 0), qaa.qaa_plan_choice(0, 0, 3), qaa.qaa_plan_choice(0, 0, -1)):
+        assert lib.qaa_plan_set(28, 0, ctypes.byref(bad)) == qaa.QAA_ERR_INVALID_ARG
     assert lib.qaa_plan_set(35, 0, None) == qaa.QAA_ERR_INVALID_ARG
     assert lib.qaa_plan_get(28, 0, None) == qaa.QAA_ERR_INVALID_ARG
     assert lib.qaa_autotune(None, 10, None, None, None) == qaa.QAA_ERR_INVALID_ARG

@@ -31,19 +31,22 @@ def _pad(l, dtype):
     return l + (2 * (l >> 5) if dtype == 0 else (l >> 4))
 
 
-def _replay(n, dtype, E, psi, T, N, k0, k1, knots=None, tile_bits=0):
+def _replay(n, dtype, E, psi, T, N, k0, k1, knots=None, tile_bits=0, any_tile=False):
     descs = qaa.qaa_debug_pass_descs(n, dtype, int(E.max()), T, N, k0, k1, knots, tile_bits=tile_bits)
     if not descs:
         return psi, descs
-    TB = n - descs[0].n_rest
-    assert TB == (tile_bits or qaa.qaa_plan_info(n, dtype)["tile_bits"])
     RB = 5 if dtype == qaa.QAA_C64 else 4
-    WB = TB - RB
-    R, WG = 1 << RB, 1 << WB
-    TSP = _pad(1 << TB, dtype)
-    tid = np.arange(WG, dtype=np.int64)
+    R = 1 << RB
     for d in descs:
-        assert n - d.n_rest == TB
+        # each pass's tile size (sets may differ: 2^14-amplitude top sets)
+        TB = n - d.n_rest
+        if tile_bits and not any_tile:
+            assert TB == tile_bits
+        assert TB in ((9, 10, 11, 12, 13, 14) if dtype == qaa.QAA_C64 else (8, 9, 10, 11, 12))
+        WB = TB - RB
+        WG = 1 << WB
+        TSP = _pad(1 << TB, dtype)
+        tid = np.arange(WG, dtype=np.int64)
         tile_pos = list(d.tile_pos[:TB])
         rest_pos = list(d.rest_pos[:d.n_rest])
         assert sorted(tile_pos + rest_pos) == list(range(n))
@@ -117,7 +120,7 @@ def _replay(n, dtype, E, psi, T, N, k0, k1, knots=None, tile_bits=0):
     return psi, descs
 
 
-@pytest.mark.parametrize("n,dtype,T,N", [(14, 0, 5.0, 4), (16, 0, 6.0, 3), (21, 0, 5.0, 2), (22, 0, 5.0, 2),
+@pytest.mark.parametrize("n,dtype,T,N", [(14, 0, 5.0, 4), (16, 0, 6.0, 3), (21, 0, 5.0, 2), (22, 0, 5.0, 1),
                                          (13, 1, 5.0, 4), (17, 1, 5.0, 3),
                                          # large steps: rotation angles reduced by pi (odd and even n)
                                          (15, 0, 50.0, 5), (14, 0, 40.0, 3)])
@@ -136,12 +139,13 @@ def test_pass_plan_replays_the_oracle(n, dtype, T, N):
 
 
 @pytest.mark.parametrize("n,dtype,tile_bits,sets,T,N", [
-    (16, 0, 10, 3, 6.0, 4),     # 10 + 5 + 1: a ragged top set
-    (20, 0, 10, 3, 5.0, 3),     # 10 + 5 + 5: three full sets, as n = 28 runs
-    (21, 0, 10, 4, 5.0, 3),     # 10 + 5 + 5 + 1: four sets, as n = 30..34 run
-    (22, 0, 9, 5, 4.0, 2),      # 9 + 4 + 4 + 4 + 1: five sets
-    (18, 1, 9, 3, 5.0, 3),      # complex128: 9 + 5 + 4
-    (21, 1, 8, 5, 5.0, 2),      # complex128: 8 + 4 + 4 + 4 + 1
+    (16, 0, 10, 3, 6.0, 3),     # 10 + 5 + 1: a ragged top set
+    (20, 0, 10, 3, 5.0, 2),     # 10 + 5 + 5: three full sets, as n = 28 runs
+    (18, 0, 9, 4, 5.0, 2),      # 9 + 4 + 4 + 1: four sets, as n = 30..34 run
+    (19, 0, 9, 4, 4.0, 2),      # 9 + 4 + 4 + 2
+    (17, 1, 9, 3, 5.0, 3),      # complex128: 9 + 5 + 3
+    (17, 1, 8, 4, 5.0, 2),      # complex128: 8 + 4 + 4 + 1
+    (21, 1, 8, 5, 5.0, 1),      # complex128: 8 + 4 + 4 + 4 + 1
 ])
 def test_smaller_tile_plans_replay_the_oracle(n, dtype, tile_bits, sets, T, N):
     """The planner's plans for smaller tiles: three, four and five qubit
@@ -161,6 +165,39 @@ def test_smaller_tile_plans_replay_the_oracle(n, dtype, tile_bits, sets, T, N):
     assert np.max(np.abs(got - ref)) < 1e-12
 
 
+@pytest.mark.parametrize("n,tile_bits,tiles,sets,T,N,passengers", [
+    (22, 0, 1, 2, 5.0, 1, (0,)),        # the library's n = 22: 13 + 9, the top set in a 2^14 tile
+    (18, 9, 1, 3, 5.0, 2, (0, 1)),      # 9 + 4 + 5: three sets, the top one wide (as n = 30)
+    (19, 9, 1, 4, 4.0, 2, (1,)),        # 9 + 4 + 4 + 2: four sets, the top one wide
+    (19, 9, 2, 3, 4.0, 2, (0, 1)),      # 10 + 5 + 4: every set wide, the high qubits split evenly
+    (20, 9, 2, 3, 4.0, 2, (1,)),        # 10 + 5 + 5 (as n = 31, 32)
+])
+def test_wide_tile_plans_replay_the_oracle(n, tile_bits, tiles, sets, T, N, passengers):
+    """Plans with wide tiles (the top set only, or every set with the high
+    qubits split evenly) replayed against the oracle, with clauses and both
+    choices of the passenger move where three sets allow it: the library's
+    2^14 tiles at n = 22, and the same shapes at smaller n with base tiles
+    of 2^9 amplitudes and wide ones of 2^10."""
+    inst = planted_unique_3sat(n, 800 + n)
+    E = oracle.energy(n, inst.clauses).astype(np.int64)
+    ref = oracle.init_uniform(n)
+    oracle.evolve(n, inst.clauses, ref, T, N)
+    wide = tile_bits + 1 if tile_bits else 14
+    for pas in passengers:
+        try:
+            qaa.qaa_plan_set(n, qaa.QAA_C64, {"balance": 0, "passengers": pas, "tiles": tiles})
+            psi = np.full(1 << n, 2.0 ** (-n / 2), np.complex128)
+            got, descs = _replay(n, 0, E, psi, T, N, 0, N, tile_bits=tile_bits, any_tile=True)
+        finally:
+            qaa.qaa_plan_set(n, qaa.QAA_C64, None)
+        tbs = sorted({n - d.n_rest for d in descs})
+        assert wide in tbs
+        n_sets = len({d.set_id for d in descs})
+        assert n_sets == sets
+        assert len(descs) == (n_sets - 1) * N + 1
+        assert np.max(np.abs(got - ref)) < 1e-12
+
+
 def test_smaller_tile_override_is_checked():
     with pytest.raises(qaa.QaaError):
         qaa.qaa_debug_pass_descs(20, 0, 10, 5.0, 10, 0, 10, tile_bits=8)
@@ -172,7 +209,7 @@ def test_smaller_tile_override_is_checked():
     assert [bytes(x) for x in a] == [bytes(x) for x in b]
 
 
-@pytest.mark.parametrize("n,T,N,chunk_log2", [(22, 5.0, 3, 19), (22, 4.0, 2, 20)])
+@pytest.mark.parametrize("n,T,N,chunk_log2", [(22, 5.0, 2, 19), (22, 4.0, 2, 20)])
 def test_chunked_schedule_replays_the_oracle(n, T, N, chunk_log2, monkeypatch):
     """Passes between two passes over the top qubit set run chunk group by
     chunk group; the reordered launches still give the oracle's result."""
@@ -180,7 +217,11 @@ def test_chunked_schedule_replays_the_oracle(n, T, N, chunk_log2, monkeypatch):
     inst = planted_unique_3sat(n, 600 + n)
     E = oracle.energy(n, inst.clauses).astype(np.int64)
     psi = np.full(1 << n, 2.0 ** (-n / 2), np.complex128)
-    got, descs = _replay(n, 0, E, psi, T, N, 0, N)
+    try:    # three sets of 2^13 tiles (chunking needs a top set above set 1)
+        qaa.qaa_plan_set(n, qaa.QAA_C64, {"balance": 0, "passengers": 1, "tiles": 0})
+        got, descs = _replay(n, 0, E, psi, T, N, 0, N)
+    finally:
+        qaa.qaa_plan_set(n, qaa.QAA_C64, None)
     cbits = min(n + 3 - chunk_log2, n - 21)        # the top qubit set starts at bit 21
     assert any(d.tile_count < (1 << d.n_rest) for d in descs)
     assert all(d.tile_count in ((1 << d.n_rest), (1 << (d.n_rest - cbits))) for d in descs)
@@ -189,10 +230,12 @@ def test_chunked_schedule_replays_the_oracle(n, T, N, chunk_log2, monkeypatch):
     assert np.max(np.abs(got - ref)) < 1e-12
 
 
-@pytest.mark.parametrize("n,choice", [(16, {"balance": 0, "passengers": 0}), (16, {"balance": 1, "passengers": 0}),
-                                      (22, {"balance": 0, "passengers": 0}), (22, {"balance": 1, "passengers": 0}),
-                                      (22, {"balance": 0, "passengers": 1}), (22, {"balance": 1, "passengers": 1})])
-def test_every_plan_choice_replays_the_oracle(n, choice):
+@pytest.mark.parametrize("n,tile_bits,choice", [
+    (16, 0, {"balance": 0, "passengers": 0, "tiles": 0}), (16, 0, {"balance": 1, "passengers": 0, "tiles": 0}),
+    # three sets (10 + 5 + 3 with 10-bit tiles, the shape of n = 22..29)
+    (18, 10, {"balance": 0, "passengers": 0, "tiles": 0}), (18, 10, {"balance": 1, "passengers": 0, "tiles": 0}),
+    (18, 10, {"balance": 0, "passengers": 1, "tiles": 0}), (18, 10, {"balance": 1, "passengers": 1, "tiles": 0})])
+def test_every_plan_choice_replays_the_oracle(n, tile_bits, choice):
     """Which set rotates which qubit is a free choice (qaa_plan_set); every
     choice must still rotate each qubit exactly once per step."""
     T, N = 5.0, 2          # two steps: first, middle, both turns and last passes
@@ -201,7 +244,7 @@ def test_every_plan_choice_replays_the_oracle(n, choice):
     psi = np.full(1 << n, 2.0 ** (-n / 2), np.complex128)
     try:
         qaa.qaa_plan_set(n, 0, choice)
-        got, _ = _replay(n, 0, E, psi, T, N, 0, N)
+        got, _ = _replay(n, 0, E, psi, T, N, 0, N, tile_bits=tile_bits)
     finally:
         qaa.qaa_plan_set(n, 0, None)
     ref = oracle.init_uniform(n)
@@ -239,7 +282,7 @@ def _tables():
 @pytest.mark.parametrize("name,n,dtype,T,N",
                          [(name, n, dt, T, N) for name in _tables() for (n, dt, T, N) in ((16, 0, 6.0, 5),
                                                                                           (15, 1, 7.0, 4))]
-                         + [("256 random knots", 22, 0, 5.0, 3)])      # three qubit sets
+                         + [("256 random knots", 18, 0, 5.0, 3)])      # three qubit sets (10-bit tiles)
 def test_table_schedule_replays_the_oracle(name, n, dtype, T, N):
     """The host planner's coefficients for a schedule table (every pass kind,
     merged phases between steps of different s) give the oracle's result."""
@@ -247,7 +290,7 @@ def test_table_schedule_replays_the_oracle(name, n, dtype, T, N):
     inst = planted_unique_3sat(n, 800 + n)
     E = oracle.energy(n, inst.clauses).astype(np.int64)
     psi = np.full(1 << n, 2.0 ** (-n / 2), np.complex128)
-    got, _ = _replay(n, dtype, E, psi, T, N, 0, N, knots)
+    got, _ = _replay(n, dtype, E, psi, T, N, 0, N, knots, tile_bits=10 if n == 18 else 0)
     ref = oracle.init_uniform(n)
     oracle.evolve(n, inst.clauses, ref, T, N, knots=knots)
     assert np.max(np.abs(got - ref)) < 1e-12
