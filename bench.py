@@ -277,6 +277,80 @@ def run_serving(qaa, count, rates, n_lo, n_hi, t_lo, t_hi, slots, budget):
                         % (n_lo, n_hi, t_lo, t_hi, slots, budget / 2.0 ** 30), "points": out}
 
 
+def _bootstrap_ci(xs, q, reps=2000, seed=1):
+    """95 % bootstrap interval of the q-th percentile of xs."""
+    import random
+    rng = random.Random(seed)
+    est = sorted(_percentile([xs[rng.randrange(len(xs))] for _ in xs], q) for _ in range(reps))
+    return [est[int(0.025 * reps)], est[int(0.975 * reps) - 1]]
+
+
+def _serve_stream(qaa, wl, slots, budget):
+    """Submit the requests of wl at their arrival times; returns results and
+    the wall time from the first arrival to the last completion."""
+    from qaa_inputs import planted_unique_3sat
+    lits = [planted_unique_3sat(w["n"], w["seed"]).literals() for w in wl]
+    sv = qaa.qaa_server_create(budget, slots)
+    try:
+        t0 = time.perf_counter()
+        tickets = []
+        for w, li in zip(wl, lits):
+            delay = t0 + w["arrival"] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(qaa.qaa_server_submit(sv, w["n"], li, w["T"], w["steps"]))
+        res = []
+        for i, t in enumerate(tickets):
+            res.append(qaa.qaa_server_wait(sv, t))
+            log("  request %d/%d n=%d T=%.1f done: latency %.2f s" % (i + 1, len(tickets), wl[i]["n"], wl[i]["T"],
+                                                                      res[-1]["latency_s"]))
+        t_end = time.perf_counter()
+    finally:
+        qaa.qaa_server_destroy(sv)
+    bad = [r for r in res if r["status"] != qaa.QAA_OK]
+    if bad:
+        raise RuntimeError("serving: %d requests failed (status %d)" % (len(bad), bad[0]["status"]))
+    return res, t_end - t0
+
+
+def run_serving_c5(qaa, fractions, count, capacity, capacity_sample, slots, budget):
+    """The serving workload at its configured scale: n ~ U{16..31}, T ~
+    U[10, 200), dt = 0.01, Poisson arrivals at fractions of the measured
+    capacity.  Capacity (solves/s) comes from a closed-loop run: a sample of
+    requests from the same distribution submitted at once, completed
+    requests over the makespan.  Latency p50/p99 with 95 % bootstrap
+    intervals per arrival rate."""
+    from qaa_inputs import serving_workload
+    out = {"workload": "Poisson arrivals, n ~ U{16..31}, T ~ U[10,200), dt ~ 0.01, %d slots, %.0f GiB budget"
+                       % (slots, budget / 2.0 ** 30)}
+    if capacity is None:
+        wl = serving_workload(capacity_sample, 1e9, seed=55)      # all arrive at once
+        log("serving capacity: %d requests at once (n = %s)" % (capacity_sample, [w["n"] for w in wl]))
+        res, secs = _serve_stream(qaa, wl, slots, budget)
+        capacity = capacity_sample / secs
+        out["capacity"] = {"requests": capacity_sample, "seconds": secs, "solves_per_s": capacity,
+                           "amp_steps": sum((1 << w["n"]) * w["steps"] for w in wl)}
+        log("serving capacity: %.4f solves/s" % capacity)
+    else:
+        out["capacity"] = {"solves_per_s": capacity, "given": True}
+    points = []
+    for f in fractions:
+        rate = f * capacity
+        wl = serving_workload(count, rate, seed=int(1000 * f) + 7)
+        log("serving at %.2f of capacity: %.4f requests/s, %d requests" % (f, rate, count))
+        res, secs = _serve_stream(qaa, wl, slots, budget)
+        lat = [r["latency_s"] for r in res]
+        points.append({"fraction": f, "rate_per_s": rate, "requests": count, "seconds": secs,
+                       "p50_s": _percentile(lat, 50), "p50_ci95": _bootstrap_ci(lat, 50),
+                       "p99_s": _percentile(lat, 99), "p99_ci95": _bootstrap_ci(lat, 99),
+                       "mean_queued_s": sum(r["queued_s"] for r in res) / count,
+                       "solves_per_s": count / secs,
+                       "n": [w["n"] for w in wl], "latency_s": lat})
+        log("serving %.2f: p50 %.2f s p99 %.2f s" % (f, points[-1]["p50_s"], points[-1]["p99_s"]))
+    out["points"] = points
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,6 +379,13 @@ def main():
     ap.add_argument("--serve-t", type=str, default="10,50", help="T range lo,hi of served requests")
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-c5", type=str, default="", metavar="FRACTIONS",
+                    help="the serving workload at its configured scale (n ~ U{16..31}, T ~ U[10,200)) at these "
+                         "comma-separated fractions of measured capacity; tens of minutes, off by default")
+    ap.add_argument("--serve-c5-requests", type=int, default=20)
+    ap.add_argument("--serve-c5-capacity", type=float, default=None,
+                    help="capacity in solves/s from an earlier run (skips the closed-loop measurement)")
+    ap.add_argument("--serve-c5-capacity-sample", type=int, default=8)
     ap.add_argument("--spectrum", type=str, default="20,21,150", metavar="N,POINTS,ITERS",
                     help="lowest two levels of H(s) for an n-qubit instance on POINTS values of s with ITERS "
                          "Lanczos steps each (qaa_spectrum); empty: skip")
@@ -483,6 +564,11 @@ def main():
         tlo, thi = (float(x) for x in args.serve_t.split(","))
         extras["serving"] = run_serving(qaa, args.serve_requests, rates, nlo, nhi, tlo, thi, args.serve_slots,
                                         int(args.serve_budget_gib * 2 ** 30))
+
+    if args.serve_c5:
+        fr = [float(x) for x in args.serve_c5.split(",") if x]
+        extras["serving_c5"] = run_serving_c5(qaa, fr, args.serve_c5_requests, args.serve_c5_capacity,
+                                              args.serve_c5_capacity_sample, args.serve_slots, 256 << 30)
 
     value = (2.0 ** n) / s_per_step
     out = {

@@ -306,9 +306,8 @@ qaa_status qaa_observables(const qaa_state *st, qaa_obs *out, void *stream);
 
 /* ---------------------------------------------------------------------
  * Serving: a solve-request server.  Requests are admitted in arrival order
- * when one of `slots` workers is free and their HBM footprint (2^n * 9
- * bytes: complex64 state plus uint8 energy table) fits the budget beside
- * the admitted ones; each worker runs its solve (energy table, uniform
+ * when one of `slots` workers is free and their HBM footprint
+ * (qaa_server_footprint) fits the budget beside the admitted ones; each worker runs its solve (energy table, uniform
  * start, qaa_evolve, qaa_observables) on its own HIP stream, so solves
  * admitted while others run overlap on the device.  The server allocates
  * and frees each request's device buffers on the current device of the
@@ -330,6 +329,13 @@ typedef struct qaa_server_result {
     double queued_s;            /* time from submit to admission (so far, if not admitted) */
     double latency_s;           /* time from submit to completion (so far, if not done) */
 } qaa_server_result;
+
+/* Device bytes a request of n qubits and m clauses is charged at
+ * admission: the complex64 state (8 * 2^n), the energy table (2^n bytes, or
+ * 2 * 2^n when m > 255, since only then can a count exceed 255 and the
+ * solve widen the table), 16 bytes per clause record and 64 KiB of the
+ * library's per-call scratch.  0 for n or m out of range. */
+uint64_t qaa_server_footprint(int32_t n, int32_t m);
 
 /* Start a server (threads and streams).  QAA_ERR_INVALID_ARG for a NULL
  * argument, slots outside 1..64 or a zero budget. */
@@ -411,13 +417,25 @@ qaa_status qaa_plan_set(int32_t n, qaa_dtype dtype, const qaa_plan_choice *choic
 
 /*
  * Autotuner: time `steps` steps (step size 0.01) of every candidate choice
- * for the scratch state's (n, dtype) on the stream, record the fastest with
- * qaa_plan_set, and return it (*best, *ms_per_step may be NULL).  The
- * scratch state's amplitudes are overwritten; its energy table must have
- * been computed.  SYNCHRONOUS.
+ * (balance x passengers x tiles, those that apply) for the scratch state's
+ * (n, dtype) on the stream, record the fastest with qaa_plan_set, and
+ * return it (*best, *ms_per_step may be NULL).  If the environment variable
+ * QAA_AUTOTUNE_CACHE names a file, every recorded choice is then written
+ * there (as qaa_plan_save), and a later process reads that file before its
+ * first plan lookup, so tuned plans persist across runs; qaa_evolve_batch
+ * follows the recorded balance and passengers for each n.  The scratch
+ * state's amplitudes are overwritten; its energy table must have been
+ * computed.  SYNCHRONOUS.
  */
 qaa_status qaa_autotune(const qaa_state *scratch, int64_t steps, qaa_plan_choice *best, double *ms_per_step,
                         void *stream);
+
+/* Write every recorded plan choice to a text file (one line per (n, dtype):
+ * "n dtype balance passengers tiles"), or record the choices a file holds
+ * (*count: lines recorded; malformed lines are skipped).  Host only.
+ * QAA_ERR_INVALID_ARG if the file cannot be written / read. */
+qaa_status qaa_plan_save(const char *path);
+qaa_status qaa_plan_load(const char *path, int32_t *count);
 
 /*
  * Diagnostic: the host half of qaa_spectrum on a given tridiagonal matrix

@@ -134,6 +134,7 @@ _SIGS = {
                                    _vp, ctypes.c_int32, _i32p, _i32p]),
     "qaa_profile_enable": (_st, [ctypes.c_int32]),
     "qaa_profile_read": (_st, [ctypes.c_void_p, ctypes.c_int32]),
+    "qaa_server_footprint": (ctypes.c_uint64, [ctypes.c_int32, ctypes.c_int32]),
     "qaa_server_create": (_st, [ctypes.POINTER(qaa_server_config), ctypes.POINTER(_vp)]),
     "qaa_server_submit": (_st, [_vp, ctypes.c_int32, ctypes.c_int32, _i32p, ctypes.POINTER(qaa_schedule),
                                 ctypes.c_double, ctypes.c_int64, _i64p]),
@@ -145,6 +146,8 @@ _SIGS = {
     "qaa_plan_set": (_st, [ctypes.c_int32, ctypes.c_int, ctypes.POINTER(qaa_plan_choice)]),
     "qaa_autotune": (_st, [ctypes.POINTER(qaa_state), ctypes.c_int64, ctypes.POINTER(qaa_plan_choice),
                            ctypes.POINTER(ctypes.c_double), _vp]),
+    "qaa_plan_save": (_st, [ctypes.c_char_p]),
+    "qaa_plan_load": (_st, [ctypes.c_char_p, _i32p]),
     "qaa_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "qaa_last_error": (ctypes.c_char_p, []),
     "qaa_version": (ctypes.c_int32, []),
@@ -408,6 +411,16 @@ def qaa_plan_set(n: int, dtype: int = QAA_C64, choice: dict | None = None) -> No
     _check(_lib.qaa_plan_set(int(n), int(dtype), ctypes.byref(c)), "qaa_plan_set")
 
 
+def qaa_plan_save(path: str) -> None:
+    _check(_lib.qaa_plan_save(os.fsencode(path)), "qaa_plan_save")
+
+
+def qaa_plan_load(path: str) -> int:
+    count = ctypes.c_int32()
+    _check(_lib.qaa_plan_load(os.fsencode(path), ctypes.byref(count)), "qaa_plan_load")
+    return count.value
+
+
 def qaa_autotune(state: qaa_state, steps: int = 20, stream=None) -> dict:
     best = qaa_plan_choice()
     ms = ctypes.c_double()
@@ -421,6 +434,11 @@ def _result_dict(r: qaa_server_result) -> dict:
     return {"status": r.status, "done": bool(r.done), "queued_s": r.queued_s, "latency_s": r.latency_s,
             "norm": o.norm, "energy": o.energy, "p_success": o.p_success, "e_min": o.e_min,
             "degeneracy": o.degeneracy}
+
+
+def qaa_server_footprint(n: int, m: int) -> int:
+    """Device bytes a request is charged at admission (0: out of range)."""
+    return int(_lib.qaa_server_footprint(int(n), int(m)))
 
 
 def qaa_server_create(hbm_budget_bytes: int, slots: int) -> int:

@@ -105,10 +105,12 @@ template <typename ET> constexpr int lut_cap() { return sizeof(ET) == 1 ? kLutMa
 // each clause the 32 outcomes form one word (bit i: z = 32t + i violates
 // it), and the words are summed bit-parallel into counter planes (plane p
 // holds bit p of the 32 counts).  Eight clauses at a time go through a
-// carry-save tree (ones, twos and fours are running planes; the eights it
-// produces ripple into the planes above), about 9 word operations per clause
-// for 32 basis states.  K planes count up to 2^K - 1: K = 8 when m <= 255,
-// else 16 (m <= 65535), so no count can overflow.
+// carry-save tree (planes 0..2 are running sums; the eights it produces
+// ripple into the planes above), about 9 word operations per clause for 32
+// basis states.  K = 8 planes count to 255; a carry out of the top plane is
+// recorded (ovf), and the host then recomputes with K = 16 (m <= 65535).
+// Clause records are staged through LDS in chunks, so every wave reads
+// them with low-latency broadcast loads instead of scalar-cache round trips.
 // ---------------------------------------------------------------------------
 
 // Carry-save adder on bit planes: a + b + c = lo + 2 hi, bit by bit.
@@ -119,79 +121,97 @@ __host__ __device__ inline void csa(uint32_t &hi, uint32_t &lo, uint32_t a, uint
     lo = u ^ c;
 }
 
-// The counts of z = 32t .. 32t+31 (e[i] for z = 32t + i) against clauses
-// cl[0..m).  Shared by the kernel and the host-side check.
 template <int K>
-__host__ __device__ inline void energy_block(const ClauseRec *__restrict__ cl, int m, uint32_t t, uint32_t (&e)[32])
+struct BitCounter {
+    uint32_t p[K];       // counter planes: bit i of p[b] is bit b of the count of z = 32t + i
+    uint32_t ovf;        // lanes whose count passed 2^K - 1
+
+    __host__ __device__ void clear()
+    {
+#pragma unroll
+        for (int b = 0; b < K; ++b) p[b] = 0u;
+        ovf = 0u;
+    }
+    // add `carry` at plane `from` and ripple upwards
+    __host__ __device__ void ripple(uint32_t carry, int from)
+    {
+#pragma unroll
+        for (int b = 0; b < K; ++b) {
+            if (b < from) continue;
+            const uint32_t nc = p[b] & carry;
+            p[b] ^= carry;
+            carry = nc;
+        }
+        ovf |= carry;
+    }
+    __host__ __device__ void add8(const uint32_t (&w)[8])
+    {
+        uint32_t twos_a, twos_b, fours_a, fours_b, eights;
+        csa(twos_a, p[0], p[0], w[0], w[1]);
+        csa(twos_b, p[0], p[0], w[2], w[3]);
+        csa(fours_a, p[1], p[1], twos_a, twos_b);
+        csa(twos_a, p[0], p[0], w[4], w[5]);
+        csa(twos_b, p[0], p[0], w[6], w[7]);
+        csa(fours_b, p[1], p[1], twos_a, twos_b);
+        csa(eights, p[2], p[2], fours_a, fours_b);
+        ripple(eights, 3);
+    }
+    __host__ __device__ void counts(uint32_t (&e)[32]) const
+    {
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+            uint32_t v = 0u;
+#pragma unroll
+            for (int b = 0; b < K; ++b) v |= ((p[b] >> i) & 1u) << b;
+            e[i] = v;
+        }
+    }
+};
+
+// Add clauses cl[0..m) for the block of thread t (z = 32t .. 32t+31).
+template <int K>
+__host__ __device__ inline void score_clauses(BitCounter<K> &bc, const ClauseRec *__restrict__ cl, int m, uint32_t t)
 {
     auto word = [&](const ClauseRec &r) { return (t & r.mhi) == r.phi ? r.low : 0u; };
-    uint32_t ones = 0u, twos = 0u, fours = 0u;
-    uint32_t plane[K];
-#pragma unroll
-    for (int p = 0; p < K; ++p) plane[p] = 0u;
     int c = 0;
     for (; c + 8 <= m; c += 8) {
         uint32_t w[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) w[j] = word(cl[c + j]);
-        uint32_t twos_a, twos_b, fours_a, fours_b, eights;
-        csa(twos_a, ones, ones, w[0], w[1]);
-        csa(twos_b, ones, ones, w[2], w[3]);
-        csa(fours_a, twos, twos, twos_a, twos_b);
-        csa(twos_a, ones, ones, w[4], w[5]);
-        csa(twos_b, ones, ones, w[6], w[7]);
-        csa(fours_b, twos, twos, twos_a, twos_b);
-        csa(eights, fours, fours, fours_a, fours_b);
-        uint32_t carry = eights;
-#pragma unroll
-        for (int p = 3; p < K; ++p) {
-            const uint32_t nc = plane[p] & carry;
-            plane[p] ^= carry;
-            carry = nc;
-        }
+        bc.add8(w);
     }
-    for (; c < m; ++c) {      // the last m mod 8 clauses: plain ripple adds
-        uint32_t carry = word(cl[c]);
-        uint32_t nc = ones & carry;
-        ones ^= carry;
-        carry = nc;
-        nc = twos & carry;
-        twos ^= carry;
-        carry = nc;
-        nc = fours & carry;
-        fours ^= carry;
-        carry = nc;
-#pragma unroll
-        for (int p = 3; p < K; ++p) {
-            nc = plane[p] & carry;
-            plane[p] ^= carry;
-            carry = nc;
-        }
-    }
-    plane[0] = ones;
-    plane[1] = twos;
-    plane[2] = fours;
-#pragma unroll
-    for (int i = 0; i < 32; ++i) {
-        uint32_t v = 0u;
-#pragma unroll
-        for (int p = 0; p < K; ++p) v |= ((plane[p] >> i) & 1u) << p;
-        e[i] = v;
-    }
+    for (; c < m; ++c) bc.ripple(word(cl[c]), 0);
 }
 
+constexpr int kClauseChunk = 1024;     // clause records staged in LDS at a time (16 KiB)
+
+// stats: [0] ~E_min (maximum of complements), [1] E_max, [2] some E > 255
+// with a uint8 table, [3] some count passed the K planes (recompute wider)
 template <typename ET, int K>
 __global__ void __launch_bounds__(256) energy_kernel(const ClauseRec *__restrict__ cl, int m, int n,
                                                      ET *__restrict__ table, uint32_t *__restrict__ stats)
 {
+    __shared__ ClauseRec cl_s[kClauseChunk];
     const uint64_t dim = 1ull << n;
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;     // n <= 34: t < 2^29
     const uint64_t zb = (uint64_t)t * 32ull;
-    uint32_t lo = 0xFFFFFFFFu, hi = 0u, over = 0u;
-    if (zb < dim) {
+    const bool active = zb < dim;
+    BitCounter<K> bc;
+    bc.clear();
+    for (int c0 = 0; c0 < m; c0 += kClauseChunk) {
+        const int cm = min(kClauseChunk, m - c0);
+        __syncthreads();         // the previous chunk is read
+        for (int i = (int)threadIdx.x; i < cm; i += (int)blockDim.x) cl_s[i] = cl[c0 + i];
+        __syncthreads();
+        if (active) score_clauses<K>(bc, cl_s, cm, t);
+    }
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u, over = 0u, wide = 0u;
+    if (active) {
         uint32_t e[32];
-        energy_block<K>(cl, m, t, e);
+        bc.counts(e);
         const int cnt = dim < 32 ? (int)dim : 32;
+        const uint32_t valid = cnt == 32 ? 0xFFFFFFFFu : ((1u << cnt) - 1u);
+        wide = (bc.ovf & valid) ? 1u : 0u;
 #pragma unroll
         for (int i = 0; i < 32; ++i) {
             if (i < cnt) {
@@ -225,18 +245,38 @@ __global__ void __launch_bounds__(256) energy_kernel(const ClauseRec *__restrict
             for (int i = 0; i < cnt; ++i) table[zb + i] = (ET)e[i];
         }
     }
-    // wave reduction of min / max / overflow, one atomic per wave
+    // Reduction of min / max / flags: waves, then the workgroup, then one
+    // thread updates the global words -- and only where it would change
+    // them.  All workgroups target the same four words, so unconditional
+    // atomics from every wave serialise at one address (that alone took
+    // 3 ms at n = 28); a possibly stale plain read is safe to test against,
+    // since the words only grow.
     for (int off = 32; off > 0; off >>= 1) {
         lo = min(lo, (uint32_t)__shfl_xor((int)lo, off, 64));
         hi = max(hi, (uint32_t)__shfl_xor((int)hi, off, 64));
         over |= (uint32_t)__shfl_xor((int)over, off, 64);
+        wide |= (uint32_t)__shfl_xor((int)wide, off, 64);
     }
-    // stats[0] holds ~E_min (the maximum of the complements), so that a
-    // zero-filled block is the neutral start for all three
+    __shared__ uint32_t red[4][4];
+    const int wave = (int)(threadIdx.x >> 6);
     if ((threadIdx.x & 63) == 0) {
-        atomicMax(&stats[0], ~lo);
-        atomicMax(&stats[1], hi);
-        if (over) atomicOr(&stats[2], over);
+        red[wave][0] = ~lo;      // stats[0] holds ~E_min (the maximum of the
+        red[wave][1] = hi;       // complements), so that a zero-filled block
+        red[wave][2] = over;     // is the neutral start for all of them
+        red[wave][3] = wide;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int k = (int)threadIdx.x;
+        uint32_t v = red[0][k];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = k < 2 ? max(v, red[w][k]) : (v | red[w][k]);
+        const uint32_t seen = __atomic_load_n(&stats[k], __ATOMIC_RELAXED);
+        if (k < 2 ? v > seen : (v & ~seen) != 0u) {
+            if (k < 2)
+                atomicMax(&stats[k], v);
+            else
+                atomicOr(&stats[k], v);
+        }
     }
 }
 
@@ -751,8 +791,21 @@ batch_pass_kernel(const BatchInst *__restrict__ insts, const uint32_t *__restric
 // ---------------------------------------------------------------------------
 // Whole state in one workgroup: all steps k0..k1-1 in LDS.  Workgroup b
 // evolves state descs[b] (so one launch serves a batch of small states).
+//
+// The steps run in chunks of up to 32.  At the start of a chunk every
+// thread helps build the chunk's coefficients in LDS -- per step the
+// rotation (t, s) and the phase row L[e] = exp(-i (phi e + gphase)),
+// e = 0..emax, evaluated in FP64 and rounded once -- so that inside the
+// chunk a step is only table lookups, rotations and LDS exchanges, with no
+// FP64 transcendental on its critical path.  The state is renormalised
+// exactly (FP64 norm) once per chunk, folded into the chunk's first row; in
+// between the rotations are area-preserving and each phase factor is unit
+// to FP32 rounding, so a chunk drifts by at most a few 1e-7.
+// RING: LDS entries for the chunk's phase rows (rows of emax + 1 entries).
 // ---------------------------------------------------------------------------
-template <typename F, typename ET, int RB, int WB>
+constexpr int kResChunk = 32;
+
+template <typename F, typename ET, int RB, int WB, int RING>
 __device__ __forceinline__ void resident_body(const ResidentDesc &d)
 {
     using F2 = typename V2<F>::T;
@@ -760,8 +813,8 @@ __device__ __forceinline__ void resident_body(const ResidentDesc &d)
     constexpr uint32_t TS = 1u << (RB + WB);
     extern __shared__ __align__(16) unsigned char smem[];
     F2 *tile = reinterpret_cast<F2 *>(smem);
-    F2 *lut = tile + TS;
-    ET *etile = reinterpret_cast<ET *>(lut + lut_cap<ET>());
+    F2 *ring = tile + TS;
+    ET *etile = reinterpret_cast<ET *>(ring + RING);
 
     F2 *__restrict__ amp = reinterpret_cast<F2 *>(d.amp);
     const ET *__restrict__ table = reinterpret_cast<const ET *>(d.table);
@@ -793,21 +846,21 @@ __device__ __forceinline__ void resident_body(const ResidentDesc &d)
         lj_s[g][j] = o;
     }
     if (tid < 8) gm_s[tid] = d.gmask[tid];
-    // schedule knots, read once per step below
     __shared__ double knots_s[kMaxKnots];
     const int kcount = d.sched.count;
     for (int x = (int)tid; x < kcount; x += (int)blockDim.x) knots_s[x] = d.sched.v[x];
-    __syncthreads();     // every thread reads knots_s before its first barrier
 
     for (uint32_t z = tid; z < dim; z += blockDim.x) {
         tile[swz<F>(z)] = amp[z];
         etile[z] = table[z];
     }
 
-    const double T = d.T;
-    const double Nd = (double)d.N;
-    const double dt = T / Nd;
+    const double dt = d.T / (double)d.N;
+    const int width = d.emax + 1;                       // entries of a phase row
+    const int chunk = min(kResChunk, RING / width);     // >= 1: width <= the LUT limit <= RING
     __shared__ double red[(1 << WB) / 64];
+    __shared__ double phi_s[kResChunk], gph_s[kResChunk];
+    __shared__ Rot<F> rot_s[kResChunk];
     double part = 0.0;     // this thread's share of |psi|^2 after the last residency
     // Norm of the state from the per-thread partials: butterfly sums inside
     // each wave, then the wave sums in order (a fixed order: deterministic).
@@ -823,19 +876,41 @@ __device__ __forceinline__ void resident_body(const ResidentDesc &d)
         __syncthreads();      // red is rewritten by the next measure
         return total;
     };
-    auto build_lut = [&](double phi, double gph, double scale) {
-        __syncthreads();
-        for (int e = (int)tid; e <= d.emax; e += (int)blockDim.x) {
-            double sn, cs;
-            sincos(fma(phi, (double)e, gph), &sn, &cs);
-            F2 L;
-            L.x = (F)(scale * cs);
-            L.y = (F)(-scale * sn);
-            lut[e] = L;
+    // phase angle phi_k, global phase and rotation of step k: the half phase
+    // that opens the range (k == k0), else the merged halves of k-1 and k
+    // with step k-1's driver global phase
+    auto step_terms = [&](int64_t k, double &phi, double &gph, double &rt, double &rs) {
+        const double sk = sched_mid(knots_s, kcount, k, d.N);
+        bool flip;
+        rot_params(dt * (1.0 - sk), rt, rs, flip);
+        if (k == d.k0) {
+            phi = 0.5 * dt * sk;
+            gph = 0.0;
+        } else {
+            const double sp = sched_mid(knots_s, kcount, k - 1, d.N);
+            const double thp = dt * (1.0 - sp);
+            double tp, sq;
+            bool fp;
+            rot_params(thp, tp, sq, fp);
+            phi = 0.5 * dt * (sp + sk);
+            gph = step_gphase(n, thp, fp);
         }
-        __syncthreads();
     };
-    auto residency = [&](int g, bool phase, uint32_t rmask, const Rot<F> &k, bool meas) {
+    // rows [0, rows) of the chunk's phase table from phi_s / gph_s; row 0
+    // carries the norm correction
+    auto build_rows = [&](int rows, double scale0) {
+        for (int x = (int)tid; x < rows * width; x += (int)blockDim.x) {
+            const int j = x / width, e = x - j * width;
+            double sn, cs;
+            sincos(fma(phi_s[j], (double)e, gph_s[j]), &sn, &cs);
+            const double sc = j == 0 ? scale0 : 1.0;
+            F2 L;
+            L.x = (F)(sc * cs);
+            L.y = (F)(-sc * sn);
+            ring[x] = L;
+        }
+    };
+    auto residency = [&](int g, const F2 *lut, uint32_t rmask, const Rot<F> &k, bool meas) {
         if (active) {
             const uint32_t lt = lt_s[g][tid];
             const uint32_t slt = swz<F>(lt);
@@ -846,7 +921,7 @@ __device__ __forceinline__ void resident_body(const ResidentDesc &d)
 #pragma unroll
             for (int j = 0; j < R; ++j)
                 if (((uint32_t)j & ~used) == 0) v[j] = tile[slt ^ swz<F>(lj[j])];
-            if (phase) {
+            if (lut) {
 #pragma unroll
                 for (int j = 0; j < R; ++j)
                     if (((uint32_t)j & ~used) == 0) v[j] = cmul<F2, F>(v[j], lut[(uint32_t)etile[lt | lj[j]]]);
@@ -864,48 +939,64 @@ __device__ __forceinline__ void resident_body(const ResidentDesc &d)
         __syncthreads();
     };
 
-    double theta_prev = 0.0, s_prev = 0.0;
-    bool flip_prev = false;
-    for (int64_t k = d.k0; k < d.k1; ++k) {
-        const double sk = sched_mid(knots_s, kcount, k, d.N);
-        const double theta = dt * (1.0 - sk);
-        double phi, gph;
-        if (k == d.k0) {
-            phi = 0.5 * dt * sk;
-            gph = 0.0;
-        } else {
-            phi = 0.5 * dt * (s_prev + sk);
-            gph = step_gphase(n, theta_prev, flip_prev);
+    double scale = 1.0;          // norm correction for the next phase row
+    for (int64_t kc = d.k0; kc < d.k1; kc += chunk) {
+        const int cs = (int)min<int64_t>((int64_t)chunk, d.k1 - kc);
+        __syncthreads();         // knots loaded / the previous chunk's rows read
+        if ((int)tid < cs) {
+            double phi, gph, rt, rs;
+            step_terms(kc + (int)tid, phi, gph, rt, rs);
+            phi_s[tid] = phi;
+            gph_s[tid] = gph;
+            rot_s[tid] = make_rot<F>(rt, rs);
         }
-        const double scale = k == d.k0 ? 1.0 : rsqrt(measure());
-        build_lut(phi, gph, scale);
-        double rt, rs;
-        rot_params(theta, rt, rs, flip_prev);
-        const Rot<F> rk = make_rot<F>(rt, rs);
-        for (int g = 0; g < d.n_groups; ++g) residency(g, g == 0, gm_s[g], rk, g == d.n_groups - 1);
-        theta_prev = theta;
-        s_prev = sk;
+        __syncthreads();
+        build_rows(cs, scale);
+        __syncthreads();
+        for (int j = 0; j < cs; ++j) {
+            const Rot<F> rk = rot_s[j];
+            for (int g = 0; g < d.n_groups; ++g)
+                residency(g, g == 0 ? ring + j * width : nullptr, gm_s[g], rk, j == cs - 1 && g == d.n_groups - 1);
+        }
+        scale = rsqrt(measure());
     }
     if (d.k1 > d.k0) {
-        const double scale = rsqrt(measure());
-        build_lut(0.5 * dt * s_prev, step_gphase(n, theta_prev, flip_prev), scale);
-        residency(0, true, 0u, make_rot<F>(0.0, 0.0), false);
+        // closing half phase of the last step, with its driver global phase
+        __syncthreads();
+        if (tid == 0) {
+            const double sl = sched_mid(knots_s, kcount, d.k1 - 1, d.N);
+            const double thl = dt * (1.0 - sl);
+            double tl, sl2;
+            bool fl;
+            rot_params(thl, tl, sl2, fl);
+            phi_s[0] = 0.5 * dt * sl;
+            gph_s[0] = step_gphase(n, thl, fl);
+        }
+        __syncthreads();
+        build_rows(1, scale);
+        __syncthreads();
+        residency(0, ring, 0u, make_rot<F>(0.0, 0.0), false);
     }
     for (uint32_t z = tid; z < dim; z += blockDim.x) amp[z] = tile[swz<F>(z)];
 }
+
+// Coefficient rows in LDS: a single state has the device to itself, a
+// batch keeps its workgroups small enough for two per CU.
+constexpr int kResRingOne = 2048;
+constexpr int kResRingBatch = 1024;
 
 // One state, descriptor passed by value.
 template <typename F, typename ET, int RB, int WB>
 __global__ void __launch_bounds__(1 << WB) resident_one_kernel(const ResidentDesc d)
 {
-    resident_body<F, ET, RB, WB>(d);
+    resident_body<F, ET, RB, WB, kResRingOne>(d);
 }
 
 // A batch of states, workgroup b takes descs[b].
 template <typename F, typename ET, int RB, int WB>
 __global__ void __launch_bounds__(1 << WB) resident_batch_kernel(const ResidentDesc *__restrict__ descs)
 {
-    resident_body<F, ET, RB, WB>(descs[blockIdx.x]);
+    resident_body<F, ET, RB, WB, kResRingBatch>(descs[blockIdx.x]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1039,7 +1130,8 @@ template <typename F, typename ET, int RB, int WB, bool ONE>
 hipError_t launch_resident_t(const ResidentDesc *descs_dev, const ResidentDesc *one, int count, hipStream_t s)
 {
     using F2 = typename V2<F>::T;
-    const size_t lds = sizeof(F2) * ((size_t(1) << (RB + WB)) + lut_cap<ET>()) + sizeof(ET) * (size_t(1) << (RB + WB));
+    const size_t ring = ONE ? kResRingOne : kResRingBatch;
+    const size_t lds = sizeof(F2) * ((size_t(1) << (RB + WB)) + ring) + sizeof(ET) * (size_t(1) << (RB + WB));
     const void *fn;
     if constexpr (ONE)
         fn = reinterpret_cast<const void *>(&resident_one_kernel<F, ET, RB, WB>);
@@ -1142,21 +1234,21 @@ hipError_t launch_resident(const ResidentDesc *descs_dev, const ResidentDesc *on
     return launch_resident_t<double, uint16_t, 4, 8, false>(descs_dev, nullptr, count, s);
 }
 
-hipError_t launch_energy(const ClauseRec *cl, int m, int n, void *table, int etype, uint32_t *stats, hipStream_t s)
+hipError_t launch_energy(const ClauseRec *cl, int m, int n, void *table, int etype, bool wide, uint32_t *stats,
+                         hipStream_t s)
 {
     const uint64_t dim = 1ull << n;
     const uint64_t threads = (dim + 31) / 32;
     const unsigned grid = (unsigned)((threads + 255) / 256);
-    const bool narrow = m <= 255;       // every count fits 8 planes
     if (etype == 0) {
-        if (narrow)
+        if (!wide)
             hipLaunchKernelGGL((energy_kernel<uint8_t, 8>), dim3(grid), dim3(256), 0, s, cl, m, n,
                                reinterpret_cast<uint8_t *>(table), stats);
         else
             hipLaunchKernelGGL((energy_kernel<uint8_t, 16>), dim3(grid), dim3(256), 0, s, cl, m, n,
                                reinterpret_cast<uint8_t *>(table), stats);
     } else {
-        if (narrow)
+        if (!wide)
             hipLaunchKernelGGL((energy_kernel<uint16_t, 8>), dim3(grid), dim3(256), 0, s, cl, m, n,
                                reinterpret_cast<uint16_t *>(table), stats);
         else
@@ -1168,11 +1260,19 @@ hipError_t launch_energy(const ClauseRec *cl, int m, int n, void *table, int ety
 
 void energy_block_host(const ClauseRec *cl, int m, uint32_t t, uint32_t *out32)
 {
+    // as on the device: 8 planes, 16 when some count passes 255
     uint32_t e[32];
-    if (m <= 255)
-        energy_block<8>(cl, m, t, e);
-    else
-        energy_block<16>(cl, m, t, e);
+    BitCounter<8> narrow;
+    narrow.clear();
+    score_clauses<8>(narrow, cl, m, t);
+    if (!narrow.ovf) {
+        narrow.counts(e);
+    } else {
+        BitCounter<16> wide;
+        wide.clear();
+        score_clauses<16>(wide, cl, m, t);
+        wide.counts(e);
+    }
     for (int i = 0; i < 32; ++i) out32[i] = e[i];
 }
 

@@ -265,13 +265,20 @@ extern "C" qaa_status qaa_energy_table(qaa_instance *inst, void *d_table, qaa_et
     uint32_t *stats = reinterpret_cast<uint32_t *>(scr.p);
     unsigned long long *count = reinterpret_cast<unsigned long long *>(stats + 4);
     QAA_HIP(launch_zero_u64(reinterpret_cast<unsigned long long *>(stats), 3, s));
-    QAA_HIP(launch_energy(recs, inst->m, inst->n, d_table, (int)etype, stats, s));
+    QAA_HIP(launch_energy(recs, inst->m, inst->n, d_table, (int)etype, false, stats, s));
     uint32_t h[4] = {0, 0, 0, 0};
     QAA_HIP(hipMemcpyAsync(h, stats, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     QAA_HIP(hipStreamSynchronize(s));
-    const uint32_t emin = ~h[0], emax = h[1], over = h[2];
-    if (etype == QAA_E_U8 && (over || emax > 255))
-        return fail(QAA_ERR_UNSUPPORTED, "qaa_energy_table: E_max=%u does not fit uint8; use QAA_E_U16", emax);
+    if (h[3] && etype == QAA_E_U16) {
+        // some count passed 255: count again with 16 planes
+        QAA_HIP(launch_zero_u64(reinterpret_cast<unsigned long long *>(stats), 3, s));
+        QAA_HIP(launch_energy(recs, inst->m, inst->n, d_table, (int)etype, true, stats, s));
+        QAA_HIP(hipMemcpyAsync(h, stats, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        QAA_HIP(hipStreamSynchronize(s));
+    }
+    const uint32_t emin = ~h[0], emax = h[1];
+    if (etype == QAA_E_U8 && (h[2] || h[3] || emax > 255))
+        return fail(QAA_ERR_UNSUPPORTED, "qaa_energy_table: E_max > 255 does not fit uint8; use QAA_E_U16");
     QAA_HIP(launch_count_equal(d_table, (int)etype, inst->n, (int)emin, count, s));
     unsigned long long hc = 0;
     QAA_HIP(hipMemcpyAsync(&hc, count, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
@@ -375,17 +382,19 @@ std::mutex g_plan_mu;
 std::map<std::pair<int, int>, PlanChoice> g_plan_choice;
 
 // Default tiles per n (complex64, measured: ms per step at T = 50, 5000-step
-// schedule).  The 2^14 top set pays where it removes a whole qubit set:
-// n = 22 runs two sets instead of three (0.063 -> 0.045 ms), n = 30 three
-// instead of four (10.4 -> 8.0 ms); n = 31, 32 reach three sets only with
-// 2^14 tiles everywhere.  Where the set count does not change, the 2^14
-// tiles' single workgroup per CU costs more than the longer runs gain
-// (n = 28: 1.71 -> 1.76 ms with the top set wide, 1.98 ms all wide).
+// schedule).  Wide tiles pay where they remove a whole qubit set: n = 22
+// runs two sets instead of three with a wide top set (0.063 -> 0.045 ms),
+// n = 23 two sets with every set wide (0.091 -> 0.081 ms), n = 30 three
+// instead of four with a wide top set (10.4 -> 8.0 ms), n = 31, 32 three
+// with every set wide (20.7 -> 18.0 ms, 41.3 -> 38.5 ms).  Where the set
+// count does not change, the 2^14 tiles' single workgroup per CU costs
+// more than the longer runs gain (n = 28: 1.71 ms, 1.76 ms with the top
+// set wide, 1.98 ms all wide; n = 24..29 likewise within 2 %).
 int default_tiles(int n, int dtype)
 {
     if (dtype != 0) return 0;
     if (n == 22 || n == 30) return 1;
-    if (n == 31 || n == 32) return 2;
+    if (n == 23 || n == 31 || n == 32) return 2;
     return 0;
 }
 PlanChoice default_plan_choice(int sets) { return PlanChoice{sets == 2 ? 1 : 0, sets >= 3 ? 1 : 0, 0}; }
@@ -396,10 +405,70 @@ int env_knob(const char *name)
     return e ? (e[0] >= '0' && e[0] <= '9' ? e[0] - '0' : 0) : -1;
 }
 
+// Plan-choice files (qaa_plan_save / qaa_plan_load, and the autotuner's
+// cache named by QAA_AUTOTUNE_CACHE): one line per (n, dtype),
+//     n dtype balance passengers tiles
+// '#' starts a comment.  Reading records every well-formed line and
+// skips the rest; returns the number recorded (-1: the file cannot be read).
+int read_plan_file(const char *path)
+{
+    FILE *f = std::fopen(path, "r");
+    if (!f) return -1;
+    char line[256];
+    int count = 0;
+    while (std::fgets(line, sizeof line, f)) {
+        if (line[0] == '#') continue;
+        int n, dt, b, q, t;
+        if (std::sscanf(line, "%d %d %d %d %d", &n, &dt, &b, &q, &t) != 5) continue;
+        if (n < 1 || n > QAA_MAX_QUBITS || (dt != 0 && dt != 1) || (b != 0 && b != 1) || (q != 0 && q != 1) ||
+            t < 0 || t > 2)
+            continue;
+        g_plan_choice[{n, dt}] = PlanChoice{b, q, t};
+        ++count;
+    }
+    std::fclose(f);
+    return count;
+}
+
+// Writes every recorded choice (caller holds g_plan_mu); false on failure.
+bool write_plan_file(const char *path)
+{
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    std::fprintf(f, "# qaa plan choices: n dtype balance passengers tiles\n");
+    for (const auto &kv : g_plan_choice) {
+        const PlanChoice &c = kv.second;
+        if (c.balance < 0 || c.passengers < 0 || c.tiles < 0) continue;
+        std::fprintf(f, "%d %d %d %d %d\n", kv.first.first, kv.first.second, c.balance, c.passengers, c.tiles);
+    }
+    const bool ok = std::fclose(f) == 0;
+    return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
+// The autotuner's cache file, read once before the first plan lookup.
+const char *autotune_cache_path()
+{
+    static const char *p = std::getenv("QAA_AUTOTUNE_CACHE");
+    return p && p[0] ? p : nullptr;
+}
+
+void load_autotune_cache_once()
+{
+    static std::once_flag once;
+    std::call_once(once, [] {
+        if (const char *p = autotune_cache_path()) {
+            std::lock_guard<std::mutex> lk(g_plan_mu);
+            (void)read_plan_file(p);
+        }
+    });
+}
+
 // The recorded (or environment-forced) choice for (n, dtype); fields the
 // caller did not fix are -1.
 PlanChoice recorded_choice(int n, int dtype)
 {
+    load_autotune_cache_once();
     PlanChoice c{-1, -1, -1};
     {
         std::lock_guard<std::mutex> lk(g_plan_mu);
@@ -1523,11 +1592,32 @@ extern "C" qaa_status qaa_plan_set(int32_t n, qaa_dtype dtype, const qaa_plan_ch
     if (choice && ((choice->balance != 0 && choice->balance != 1) ||
                    (choice->passengers != 0 && choice->passengers != 1) || choice->tiles < 0 || choice->tiles > 2))
         return fail(QAA_ERR_INVALID_ARG, "qaa_plan_set: balance and passengers are 0 or 1, tiles 0, 1 or 2");
+    load_autotune_cache_once();
     std::lock_guard<std::mutex> lk(g_plan_mu);
     if (choice)
         g_plan_choice[{n, (int)dtype}] = PlanChoice{choice->balance, choice->passengers, choice->tiles};
     else
         g_plan_choice.erase({n, (int)dtype});
+    return ok();
+}
+
+extern "C" qaa_status qaa_plan_save(const char *path)
+{
+    if (!path || !path[0]) return fail(QAA_ERR_INVALID_ARG, "qaa_plan_save: no path");
+    load_autotune_cache_once();
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    if (!write_plan_file(path)) return fail(QAA_ERR_INVALID_ARG, "qaa_plan_save: cannot write %s", path);
+    return ok();
+}
+
+extern "C" qaa_status qaa_plan_load(const char *path, int32_t *count)
+{
+    if (!path || !path[0]) return fail(QAA_ERR_INVALID_ARG, "qaa_plan_load: no path");
+    load_autotune_cache_once();
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    const int c = read_plan_file(path);
+    if (c < 0) return fail(QAA_ERR_INVALID_ARG, "qaa_plan_load: cannot read %s", path);
+    if (count) *count = c;
     return ok();
 }
 
@@ -1586,6 +1676,10 @@ extern "C" qaa_status qaa_autotune(const qaa_state *scratch, int64_t steps, qaa_
     (void)hipEventDestroy(e1);
     const qaa_plan_choice qb{best_c.balance, best_c.passengers, best_c.tiles};
     qaa_plan_set(n, scratch->dtype, &qb);
+    if (const char *cache = autotune_cache_path()) {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        if (!write_plan_file(cache)) return fail(QAA_ERR_INVALID_ARG, "qaa_autotune: cannot write the cache %s", cache);
+    }
     if (best) *best = qb;
     if (ms_per_step) *ms_per_step = (double)best_ms / (double)steps;
     return ok();

@@ -168,7 +168,9 @@ struct BatchInst {
 };
 
 // Kernel launch helpers (defined in the .hip files).
-hipError_t launch_energy(const ClauseRec *cl, int m, int n, void *table, int etype,
+// wide: 16 counter planes instead of 8 (needed only when some count > 255);
+// stats[4] as documented at the kernel, zero-filled by the caller.
+hipError_t launch_energy(const ClauseRec *cl, int m, int n, void *table, int etype, bool wide,
                          uint32_t *stats, hipStream_t s);
 // Host evaluation of the energy kernel's per-thread arithmetic: the counts
 // of z = 32t .. 32t+31 into out32[0..32) (for host-side checks).

@@ -2,7 +2,8 @@
 //
 // Requests (a clause list, T and a step count) are admitted in arrival
 // order when a worker slot is free and their HBM footprint fits the budget
-// (2^n * 9 bytes: complex64 state plus uint8 energy table).  Each slot owns
+// (qaa_server_footprint: complex64 state, energy table, clause records and
+// the library's per-call scratch).  Each slot owns
 // a HIP stream and runs the whole solve on it (energy table, uniform start,
 // all steps, observables), so solves admitted while others are running
 // overlap on the device and share it kernel by kernel.  Results do not
@@ -63,7 +64,16 @@ struct qaa_server {
 
 namespace {
 
-size_t footprint_of(int32_t n) { return (size_t(1) << n) * 9; }
+// Device memory a solve can hold at once: the complex64 state, the energy
+// table (uint8, or uint16 when the clause count allows counts above 255:
+// the solve widens the table only then), the instance's clause records and
+// the per-call reduction scratch of the library (observables partials and
+// counters, under 64 KiB).
+size_t footprint_of(int32_t n, int32_t m)
+{
+    const size_t dim = size_t(1) << n;
+    return dim * 8 + dim * (m > 255 ? 2 : 1) + sizeof(qaa::ClauseRec) * (size_t)m + (size_t(64) << 10);
+}
 
 // Run one solve on the worker's stream; returns a status and message.
 qaa_status solve(Request &rq, hipStream_t s, std::string &err)
@@ -185,7 +195,7 @@ extern "C" qaa_status qaa_server_submit(qaa_server *sv, int32_t n, int32_t m, co
         return qaa::set_error(QAA_ERR_INVALID_ARG, "qaa_server_submit: malformed request");
     qaa::SchedKnots sc;
     if (qaa::to_knots(sched, &sc, "qaa_server_submit") != QAA_OK) return QAA_ERR_INVALID_ARG;
-    const size_t fp = footprint_of(n);
+    const size_t fp = footprint_of(n, m);
     if (fp > sv->cfg.hbm_budget_bytes)    // could never be admitted
         return qaa::set_error(QAA_ERR_OUT_OF_MEMORY, "qaa_server_submit: footprint exceeds the HBM budget");
     std::lock_guard<std::mutex> lk(sv->mu);
@@ -203,6 +213,12 @@ extern "C" qaa_status qaa_server_submit(qaa_server *sv, int32_t n, int32_t m, co
     *ticket = rq.id;
     sv->cv_work.notify_all();
     return qaa::set_error(QAA_OK, nullptr);
+}
+
+extern "C" uint64_t qaa_server_footprint(int32_t n, int32_t m)
+{
+    if (n < 1 || n > QAA_MAX_QUBITS || m < 0 || m > 65535) return 0;
+    return (uint64_t)footprint_of(n, m);
 }
 
 namespace {

@@ -165,7 +165,8 @@ def test_good_schedule_passes_to_the_state_checks():
     (14, 0, (13, 2, 1)),
     (21, 0, (13, 2, 1)),
     (22, 0, (13, 2, 1)),        # the top set in a 2^14 tile holds the 9 high qubits
-    (23, 0, (13, 3, 2)),
+    (23, 0, (14, 2, 1)),        # 14 + 9: every set in 2^14 tiles, two sets
+    (24, 0, (13, 3, 2)),
     (28, 0, (13, 3, 2)),
     (29, 0, (13, 3, 2)),
     (30, 0, (13, 3, 2)),        # 13 + 8 + 9: the top set in a 2^14 tile
@@ -295,3 +296,41 @@ def test_binding_checks_buffers_before_handing_pointers_over():
                              torch.zeros(64, dtype=torch.float32), 10, 1)
     finally:
         qaa.qaa_instance_destroy(h)
+
+
+def test_plan_choices_save_and_load(tmp_path):
+    """Plan choices round-trip through a file; malformed lines are skipped."""
+    path = str(tmp_path / "plans.txt")
+    try:
+        qaa.qaa_plan_set(27, qaa.QAA_C64, {"balance": 1, "passengers": 0, "tiles": 1})
+        qaa.qaa_plan_set(20, qaa.QAA_C128, {"balance": 0, "passengers": 0, "tiles": 0})
+        qaa.qaa_plan_save(path)
+        text = open(path).read()
+        assert "27 0 1 0 1" in text and "20 1 0 0 0" in text
+        qaa.qaa_plan_set(27, qaa.QAA_C64, None)
+        qaa.qaa_plan_set(20, qaa.QAA_C128, None)
+        with open(path, "a") as f:
+            f.write("garbage line\n99 0 1 1 1\n26 0 0 1 7\n")
+        assert qaa.qaa_plan_load(path) == 2
+        assert qaa.qaa_plan_get(27) == {"balance": 1, "passengers": 0, "tiles": 1}
+    finally:
+        qaa.qaa_plan_set(27, qaa.QAA_C64, None)
+        qaa.qaa_plan_set(20, qaa.QAA_C128, None)
+    with pytest.raises(qaa.QaaError):
+        qaa.qaa_plan_load(str(tmp_path / "missing.txt"))
+
+
+def test_autotune_cache_is_read_before_the_first_plan(tmp_path):
+    """A process started with QAA_AUTOTUNE_CACHE naming a plan file uses its
+    choices from the first plan lookup on (no GPU needed to plan)."""
+    import subprocess
+    import sys
+    path = tmp_path / "cache.txt"
+    path.write_text("# tuned\n28 0 1 0 2\n")
+    code = ("import paper_1103_1399_amd as q; p = q.qaa_plan_get(28); i = q.qaa_plan_info(28); "
+            "print(p['balance'], p['passengers'], p['tiles'], i['tile_bits'])")
+    env = dict(os.environ, QAA_AUTOTUNE_CACHE=str(path))
+    out = subprocess.run([sys.executable, "-c", code], env=env, cwd=ROOT, capture_output=True, text=True,
+                         timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split() == ["1", "0", "2", "14"]

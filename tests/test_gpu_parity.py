@@ -321,7 +321,11 @@ def test_cache_blocked_schedule_vs_oracle(qaa, monkeypatch):
     n, T, N = 23, 4.0, 5
     inst_in = planted_unique_3sat(n, 41)
     psi, ref = _oracle_run(n, inst_in.clauses, T, N)
-    _, _, st, obs = _run_gpu(qaa, n, inst_in.clauses, T, N)
+    try:    # three sets of 2^13 tiles: chunking needs a top set above set 1
+        qaa.qaa_plan_set(n, qaa.QAA_C64, {"balance": 0, "passengers": 1, "tiles": 0})
+        _, _, st, obs = _run_gpu(qaa, n, inst_in.clauses, T, N)
+    finally:
+        qaa.qaa_plan_set(n, qaa.QAA_C64, None)
     _compare(st, obs, psi, ref, L2_TOL_C64, P_TOL_C64)
 
 

@@ -1,6 +1,8 @@
 """GPU tests of the solve-request server (qaa_server_*): every result equals
 the same solve run alone through qaa_evolve, admission never exceeds the HBM
 budget, and oversize or malformed requests are reported."""
+import time
+
 import numpy as np
 import pytest
 
@@ -75,11 +77,12 @@ def test_server_result_matches_oracle(qaa):
 
 def test_server_admission_respects_budget(qaa):
     n = 18
-    fp = (1 << n) * 9
+    insts = [planted_unique_3sat(n, 200 + i) for i in range(6)]
+    fp = max(qaa.qaa_server_footprint(n, inst.m) for inst in insts)
+    assert fp >= (1 << n) * 9
     sv = qaa.qaa_server_create(hbm_budget_bytes=2 * fp, slots=4)
     try:
-        tickets = [qaa.qaa_server_submit(sv, n, planted_unique_3sat(n, 200 + i).literals(), 5.0, 40)
-                   for i in range(6)]
+        tickets = [qaa.qaa_server_submit(sv, n, inst.literals(), 5.0, 40) for inst in insts]
         peak = 0
         while True:
             s = qaa.qaa_server_stats(sv)
@@ -124,3 +127,37 @@ def test_server_requests_with_schedule_tables(qaa):
     # the tables took effect: the first request differs from its linear run
     lin = _solo(qaa, *reqs[0])
     assert lin["p_success"] != results[0]["p_success"]
+
+
+def test_server_footprint_charges_what_a_solve_can_hold(qaa):
+    n = 20
+    assert qaa.qaa_server_footprint(n, 200) == (1 << n) * 9 + 16 * 200 + (64 << 10)
+    # more than 255 clauses: the table may widen to uint16
+    assert qaa.qaa_server_footprint(n, 300) == (1 << n) * 10 + 16 * 300 + (64 << 10)
+    assert qaa.qaa_server_footprint(0, 10) == 0 and qaa.qaa_server_footprint(n, -1) == 0
+
+
+def test_server_overlaps_solves(qaa):
+    """Continuous batching: a short request submitted while a long one runs
+    is admitted into the free slot and finishes first; the long one is
+    still running when the short one is done, so both were on the device
+    at once (nothing in the library serialises them)."""
+    long_inst = planted_unique_3sat(22, 11)
+    short_inst = planted_unique_3sat(12, 12)
+    sv = qaa.qaa_server_create(hbm_budget_bytes=1 << 32, slots=2)
+    try:
+        t_long = qaa.qaa_server_submit(sv, 22, long_inst.literals(), 100.0, 10000)
+        t0 = time.perf_counter()
+        while qaa.qaa_server_stats(sv)["running"] < 1:
+            assert time.perf_counter() - t0 < 30
+        t_short = qaa.qaa_server_submit(sv, 12, short_inst.literals(), 2.0, 200)
+        r_short = qaa.qaa_server_wait(sv, t_short)
+        r_long = qaa.qaa_server_poll(sv, t_long)
+        assert r_short["done"] and r_short["status"] == qaa.QAA_OK
+        assert not r_long["done"], "the short solve waited for the long one"
+        assert r_short["queued_s"] < 0.1
+        r_long = qaa.qaa_server_wait(sv, t_long)
+        assert r_long["done"] and r_long["status"] == qaa.QAA_OK
+        assert r_long["latency_s"] > r_short["latency_s"]
+    finally:
+        qaa.qaa_server_destroy(sv)
