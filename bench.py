@@ -52,10 +52,14 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
 
 # HBM traffic of the pass kernel measured with rocprofv3 --pmc (FETCH_SIZE and
 # WRITE_SIZE runs, scaled by the same counters' reading for a plain copy of
-# known size).  Valid only for the kernel source it was taken on.
+# known size), per launch of the timed region's mix.  Valid only for the
+# kernel sources it was taken on (the pass kernels, their shared device
+# helpers and the descriptor layout).
+PASS_KERNEL_SOURCES = ("paper_1103_1399_amd/csrc/pass_kernels.hip", "paper_1103_1399_amd/csrc/kernel_common.h",
+                       "paper_1103_1399_amd/csrc/qaa_internal.h")
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "510e8bae49779e60901c1453e6260b1fdfbb7531a3edb4902b6efb42ca603d14",
-    "bytes_per_launch": 4.508597e+09,
+    "kernel_source_sha256": "",
+    "bytes_per_launch": 4.5085e+09,
 }
 
 
@@ -64,9 +68,11 @@ def log(msg):
 
 
 def kernel_source_sha():
-    path = os.path.join(ROOT, "paper_1103_1399_amd", "csrc", "kernels.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for rel in PASS_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def schedule_table(count):
@@ -206,8 +212,13 @@ def run_batch(qaa, torch, count, seed, loop_sample):
     loop_amp_steps = sum((1 << w[0]) * w[2] for w in wl[:loop_sample])
     for inst in insts:
         inst.close()
+    plans = {}
+    for n in sorted({w[0] for w in wl}):
+        info = qaa.qaa_plan_info(n)
+        plans[str(n)] = {"sets": info["sets"], "tile_bits": info["tile_bits"], **qaa.qaa_plan_get(n)}
     return {
         "workload": "%d planted 3-SAT instances, n ~ U{12..22}, T ~ U[10,100), dt ~ 0.01 (seed %d)" % (count, seed),
+        "plan_per_n": plans,
         "solves_per_s": count / t_batch,
         "amp_steps_per_s": amp_steps / t_batch,
         "seconds": t_batch,

@@ -230,8 +230,9 @@ qaa_status qaa_evolve_range_noalloc(const qaa_state *st, const qaa_schedule *sch
  * scheds[i] for states[i], each as in qaa_evolve.
  * States whose whole vector fits one workgroup tile (n <= 13 for complex64,
  * 12 for complex128) run in one launch, one workgroup each; the others run
- * in lock step, one launch per pass covering every state still running,
- * with rotation and phase coefficients computed on the device.  Each result
+ * in lock step, one launch per pass and tile size covering every state
+ * still running, with rotation and phase coefficients computed on the
+ * device.  Each state follows the plan qaa_plan_get reports for its n.  Each result
  * equals what qaa_evolve gives for that state alone up to FP32 rounding
  * (same pass plan per n).  The call waits for the descriptor uploads (and
  * so for work already queued on the stream); the evolution itself is
@@ -393,8 +394,8 @@ qaa_status qaa_plan_info(int32_t n, qaa_dtype dtype, int32_t *tile_bits, int32_t
  *                that gathers from the whole state); 2 = every set in
  *                2^14-amplitude tiles, the qubits above set 0 split evenly.
  *                Tiles 1 and 2 apply to complex64 states with a uint8 table
- *                and n >= 22 only (elsewhere, and in qaa_evolve_batch, the
- *                base tile is used whatever is recorded).
+ *                and n >= 22 only (elsewhere the base tile is used whatever
+ *                is recorded).
  * Results do not depend on the choice beyond FP32 rounding order.  The
  * choice is process-wide per (n, dtype); the environment variables
  * QAA_PLAN_BALANCE / QAA_PLAN_PASSENGERS (0 or 1) and QAA_PLAN_TILES

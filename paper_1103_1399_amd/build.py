@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libqaa.so")
-SOURCES = ["kernels.hip", "qaa_api.hip", "qaa_server.hip", "spectrum.hip"]
+SOURCES = ["kernels.hip", "pass_kernels.hip", "qaa_api.hip", "qaa_server.hip", "spectrum.hip"]
 
 # Packed FP32 instructions stay disabled (plain FMA code only).
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

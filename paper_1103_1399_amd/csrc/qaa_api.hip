@@ -265,14 +265,14 @@ extern "C" qaa_status qaa_energy_table(qaa_instance *inst, void *d_table, qaa_et
     uint32_t *stats = reinterpret_cast<uint32_t *>(scr.p);
     unsigned long long *count = reinterpret_cast<unsigned long long *>(stats + 4);
     QAA_HIP(launch_zero_u64(reinterpret_cast<unsigned long long *>(stats), 3, s));
-    QAA_HIP(launch_energy(recs, inst->m, inst->n, d_table, (int)etype, false, stats, s));
+    QAA_HIP(launch_energy(recs, inst->m, inst->n, d_table, (int)etype, false, stats, 0, nullptr, s));
     uint32_t h[4] = {0, 0, 0, 0};
     QAA_HIP(hipMemcpyAsync(h, stats, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     QAA_HIP(hipStreamSynchronize(s));
     if (h[3] && etype == QAA_E_U16) {
         // some count passed 255: count again with 16 planes
         QAA_HIP(launch_zero_u64(reinterpret_cast<unsigned long long *>(stats), 3, s));
-        QAA_HIP(launch_energy(recs, inst->m, inst->n, d_table, (int)etype, true, stats, s));
+        QAA_HIP(launch_energy(recs, inst->m, inst->n, d_table, (int)etype, true, stats, 0, nullptr, s));
         QAA_HIP(hipMemcpyAsync(h, stats, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         QAA_HIP(hipStreamSynchronize(s));
     }
@@ -494,12 +494,11 @@ bool wide_tiles_ok(int n, int dtype, int etype, int base = kPassTileBits[0])
 }
 
 // The plan for n qubits.  etype matters only for the tile choice (wide
-// tiles need a uint8 table); uniform: every set in the library's base tile
-// (the batched kernel's requirement); tile_override: 0 for the library's
-// tile shape, otherwise a smaller base tile of that many bits (and a wide
-// tile one bit larger), for host-side replay of the same plan shapes at
-// small n (qaa_debug_pass_descs only: no kernel is built for such tiles).
-Plan make_plan(int n, int dtype, int etype, bool uniform = false, int tile_override = 0, PlanChoice *used = nullptr)
+// tiles need a uint8 table); tile_override: 0 for the library's tile shape,
+// otherwise a smaller base tile of that many bits (and a wide tile one bit
+// larger), for host-side replay of the same plan shapes at small n
+// (qaa_debug_pass_descs only: no kernel is built for such tiles).
+Plan make_plan(int n, int dtype, int etype, int tile_override = 0, PlanChoice *used = nullptr)
 {
     Plan p;
     if (n <= kResRegBits[dtype] + kResThrBits) {
@@ -511,7 +510,7 @@ Plan make_plan(int n, int dtype, int etype, bool uniform = false, int tile_overr
     PlanChoice c = recorded_choice(n, dtype);
     const int wide = tile_override ? tile_override + 1 : kWideTileBits;
     int tiles = c.tiles >= 0 ? c.tiles : (tile_override ? 0 : default_tiles(n, dtype));
-    if (uniform || !wide_tiles_ok(n, dtype, etype, base)) tiles = 0;
+    if (!wide_tiles_ok(n, dtype, etype, base)) tiles = 0;
     const int tb0 = tiles == 2 ? wide : base;
     const int tb_mid = tiles == 2 ? wide : base;
     const int tb_top = tiles >= 1 ? wide : base;
@@ -1332,55 +1331,71 @@ qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states
     if (idx.empty()) return QAA_OK;
     const int dty = (int)states[idx[0]].dtype, ety = (int)states[idx[0]].etype;
     const int chunk_tiles = batch_chunk_tiles();
+    // A launch group holds states whose plans have the same number of sets
+    // and the same tile size per set, so that every pass of a step runs one
+    // kernel variant for all of them.  Each state has a chunk table entry
+    // per tile variant its sets use (base [0], wide [1]).
     struct GroupPlan {
         int r = 0;
-        std::vector<int> order;              // state indices, longest first
-        size_t inst_base = 0, chunk_base = 0;
-        std::vector<uint64_t> chunk_prefix;  // chunks of the first q states
+        std::vector<int> tbs;                     // tile bits per set
+        std::vector<int> order;                   // state indices, longest first
+        size_t inst_base = 0, chunk_base[2] = {0, 0};
+        std::vector<uint64_t> chunk_prefix[2];    // chunks of the first q states, per variant
     };
-    std::map<int, GroupPlan> groups;
+    std::map<std::vector<int>, GroupPlan> groups;
+    int RB = 0;
     for (int i : idx) {
-        const Plan p = make_plan(states[i].inst->n, dty, ety, true);
-        GroupPlan &g = groups[(int)p.sets.size()];
+        const Plan p = make_plan(states[i].inst->n, dty, ety);
+        std::vector<int> key{(int)p.sets.size()};
+        for (const SetPlan &sp : p.sets) key.push_back(sp.tb);
+        GroupPlan &g = groups[key];
         g.r = (int)p.sets.size();
+        g.tbs.assign(key.begin() + 1, key.end());
         g.order.push_back(i);
+        RB = p.reg_bits;
     }
     std::vector<PassDesc> structs;
     std::map<int, int> base_of_n;
     std::vector<BatchInst> insts;
-    std::vector<uint32_t> chunk_inst;
-    int TB = 0, RB = 0;
+    std::vector<uint32_t> chunk_inst[2];
     int64_t maxN = 0;
     for (auto &kv : groups) {
         GroupPlan &g = kv.second;
         std::stable_sort(g.order.begin(), g.order.end(), [&](int a, int b) { return steps[a] > steps[b]; });
         g.inst_base = insts.size();
-        g.chunk_base = chunk_inst.size();
-        g.chunk_prefix.assign(1, 0);
+        bool uses[2] = {false, false};
+        for (int tb : g.tbs) uses[tb == kWideTileBits ? 1 : 0] = true;
+        for (int v = 0; v < 2; ++v) {
+            g.chunk_base[v] = chunk_inst[v].size();
+            g.chunk_prefix[v].assign(1, 0);
+        }
         for (int i : g.order) {
             const int n = states[i].inst->n;
-            const Plan p = make_plan(n, dty, ety, true);
             if (!base_of_n.count(n)) {
                 base_of_n[n] = (int)structs.size();
-                batch_structs(p, n, dty, structs);
+                batch_structs(make_plan(n, dty, ety), n, dty, structs);
             }
-            TB = p.tile_bits;
-            RB = p.reg_bits;
             BatchInst b;
             std::memset(&b, 0, sizeof b);
             b.amp = states[i].amp;
             b.table = states[i].table;
             b.T = T[i];
             b.N = steps[i];
-            b.chunk_offset = g.chunk_prefix.back();
             b.n = n;
             b.emax = states[i].inst->e_max;
             b.r = g.r;
             b.struct_base = base_of_n[n];
             b.sched = scs[i];
-            const uint64_t chunks = ((1ull << (n - TB)) + chunk_tiles - 1) / chunk_tiles;
-            for (uint64_t c = 0; c < chunks; ++c) chunk_inst.push_back((uint32_t)(insts.size() - g.inst_base));
-            g.chunk_prefix.push_back(g.chunk_prefix.back() + chunks);
+            for (int v = 0; v < 2; ++v) {
+                b.chunk_offset[v] = g.chunk_prefix[v].back();
+                uint64_t chunks = 0;
+                if (uses[v]) {
+                    const int tb = v ? kWideTileBits : kPassTileBits[dty];
+                    chunks = ((1ull << (n - tb)) + chunk_tiles - 1) / chunk_tiles;
+                }
+                for (uint64_t c = 0; c < chunks; ++c) chunk_inst[v].push_back((uint32_t)(insts.size() - g.inst_base));
+                g.chunk_prefix[v].push_back(g.chunk_prefix[v].back() + chunks);
+            }
             insts.push_back(b);
             maxN = std::max(maxN, steps[i]);
         }
@@ -1394,22 +1409,23 @@ qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states
     }
     BatchInst *d_insts = nullptr;
     PassDesc *d_structs = nullptr;
-    uint32_t *d_chunks = nullptr;
+    uint32_t *d_chunks[2] = {nullptr, nullptr};
     // every buffer this call took goes back in stream order, on every path
     auto release = [&]() {
         if (d_insts) (void)hipFreeAsync(d_insts, s);
         if (d_structs) (void)hipFreeAsync(d_structs, s);
-        if (d_chunks) (void)hipFreeAsync(d_chunks, s);
+        for (int v = 0; v < 2; ++v)
+            if (d_chunks[v]) (void)hipFreeAsync(d_chunks[v], s);
         if (acc) (void)hipFreeAsync(acc, s);
     };
     qaa_status r = upload(insts, &d_insts, s);
     if (r == QAA_OK) r = upload(structs, &d_structs, s);
-    if (r == QAA_OK) r = upload(chunk_inst, &d_chunks, s);
+    for (int v = 0; v < 2 && r == QAA_OK; ++v) r = upload(chunk_inst[v], &d_chunks[v], s);
     if (r != QAA_OK) {
         release();
         return r;
     }
-    std::map<int, int> active;
+    std::map<std::vector<int>, int> active;
     for (auto &kv : groups) active[kv.first] = (int)kv.second.order.size();
     for (int64_t k = 0; k < maxN; ++k) {
         for (auto &kv : groups) {
@@ -1419,8 +1435,14 @@ qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states
             if (a == 0) continue;
             const int jn = k == 0 ? g.r : g.r - 1;
             for (int j = 0; j < jn; ++j) {
-                hipError_t e = launch_batch_pass(d_insts + g.inst_base, d_chunks + g.chunk_base, g.chunk_prefix[a],
-                                                 d_structs, k, j, chunk_tiles, dty, ety, TB, RB, s);
+                // the set this pass visits (zig-zag order, as the kernel derives it)
+                const int pos = k == 0 ? j : j + 1;
+                const int set = (k & 1) == 0 ? pos : g.r - 1 - pos;
+                const int tb = g.tbs[set];
+                const int v = tb == kWideTileBits ? 1 : 0;
+                hipError_t e = launch_batch_pass(d_insts + g.inst_base, d_chunks[v] + g.chunk_base[v],
+                                                 g.chunk_prefix[v][a], d_structs, k, j, chunk_tiles, dty, ety, tb, RB,
+                                                 s);
                 if (e != hipSuccess) {
                     release();
                     return fail(QAA_ERR_DEVICE, "batched pass launch failed: %s", hipGetErrorString(e));
@@ -1462,7 +1484,7 @@ extern "C" qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, c
     for (int i = 0; i < count; ++i) {
         if (steps[i] == 0) continue;
         const int dt = (int)states[i].dtype, et = (int)states[i].etype;
-        if (make_plan(states[i].inst->n, dt, et, true).resident)
+        if (make_plan(states[i].inst->n, dt, et).resident)
             small[dt][et].push_back(make_resident_desc(&states[i], scs[i], T[i], steps[i], 0, steps[i], kResRegBits[dt]));
         else
             large[dt][et].push_back(i);
@@ -1577,7 +1599,7 @@ extern "C" qaa_status qaa_plan_get(int32_t n, qaa_dtype dtype, qaa_plan_choice *
     if (n < 1 || n > QAA_MAX_QUBITS || (dtype != QAA_C64 && dtype != QAA_C128) || !out)
         return fail(QAA_ERR_INVALID_ARG, "qaa_plan_get: bad argument");
     PlanChoice c{0, 0, 0};
-    const Plan p = make_plan(n, (int)dtype, QAA_E_U8, false, 0, &c);
+    const Plan p = make_plan(n, (int)dtype, QAA_E_U8, 0, &c);
     if (p.resident) c = default_plan_choice(1);
     out->balance = c.balance;
     out->passengers = c.passengers;
@@ -1714,7 +1736,7 @@ extern "C" qaa_status qaa_debug_pass_descs(int32_t n, qaa_dtype dtype, int32_t e
     SchedKnots sc;
     qaa_status r = to_knots(sched, &sc, "qaa_debug_pass_descs");
     if (r != QAA_OK) return r;
-    const Plan p = make_plan(n, (int)dtype, QAA_E_U8, false, tile_bits);
+    const Plan p = make_plan(n, (int)dtype, QAA_E_U8, tile_bits);
     if (p.resident || k0 == k1) {
         *count = 0;
         return ok();

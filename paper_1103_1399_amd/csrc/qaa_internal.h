@@ -162,16 +162,19 @@ struct BatchInst {
     unsigned long long *acc;   // 3 norm-control slots of this state
     double T;
     int64_t N;
-    uint64_t chunk_offset;     // first workgroup chunk of this state in its launch group
+    uint64_t chunk_offset[2];  // first workgroup chunk of this state in its launch group, for passes
+                               // in base tiles [0] and in wide tiles [1]
     int32_t n, emax, r, struct_base;
     SchedKnots sched;
 };
 
 // Kernel launch helpers (defined in the .hip files).
 // wide: 16 counter planes instead of 8 (needed only when some count > 255);
-// stats[4] as documented at the kernel, zero-filled by the caller.
+// stats[4] as documented at the kernel, zero-filled by the caller; table may
+// be null (statistics only); count (may be null) receives the number of z
+// with E(z) == count_value.
 hipError_t launch_energy(const ClauseRec *cl, int m, int n, void *table, int etype, bool wide,
-                         uint32_t *stats, hipStream_t s);
+                         uint32_t *stats, int count_value, unsigned long long *count, hipStream_t s);
 // Host evaluation of the energy kernel's per-thread arithmetic: the counts
 // of z = 32t .. 32t+31 into out32[0..32) (for host-side checks).
 void energy_block_host(const ClauseRec *cl, int m, uint32_t t, uint32_t *out32);
