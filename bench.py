@@ -324,6 +324,41 @@ def _serve_stream(qaa, wl, slots, budget):
     return res, t_end - t0
 
 
+def run_recompute(qaa, torch, n, lits, T, N, K, knots, table_amp):
+    """The timed job's K steps again on a state with no energy table (the
+    phase passes score the clauses themselves): energy statistics, initial
+    state and the steps timed apart; the final state compared with the
+    table mode's bit for bit."""
+    amp = torch.empty(1 << n, dtype=torch.complex64, device=table_amp.device)
+    h = qaa.Instance(n, lits)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    qaa.qaa_energy_stats(h.handle)
+    t_stats = time.perf_counter() - t0
+    st = qaa.make_state(h.handle, amp, None, qaa.QAA_E_U8)
+    qaa.qaa_state_init_uniform(st)
+    torch.cuda.synchronize()
+    qaa.qaa_profile_read(reset=True)
+    qaa.qaa_profile_enable(True)
+    t0 = time.perf_counter()
+    qaa.qaa_evolve_range(st, T, N, 0, K, knots=knots)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    qaa.qaa_profile_enable(False)
+    prof = qaa.qaa_profile_read(reset=True)
+    obs = qaa.qaa_observables(st)
+    same = bool(torch.equal(amp, table_amp))
+    h.close()
+    del amp
+    avg_ms = prof["kernel_ms"] / max(1, prof["launches"])
+    return {"steps": K, "ms_per_step_steps": secs / K * 1e3, "energy_stats_s": t_stats,
+            "amp_steps_per_s": (1 << n) * K / secs, "pass_launches": prof["launches"],
+            "avg_launch_ms": avg_ms,
+            "achieved_gbs": prof["alg_bytes"] / max(1, prof["launches"]) / (avg_ms * 1e-3) / 1e9
+            if prof["launches"] else 0.0,
+            "identical_state": same, "p_success": obs["p_success"], "norm": obs["norm"]}
+
+
 def run_serving_c5(qaa, fractions, count, capacity, capacity_sample, slots, budget):
     """The serving workload at its configured scale: n ~ U{16..31}, T ~
     U[10, 200), dt = 0.01, Poisson arrivals at fractions of the measured
@@ -381,7 +416,10 @@ def main():
                          "scaling HBM counter readings")
     ap.add_argument("--batch", type=int, default=512, metavar="COUNT",
                     help="batched workload size (512 is the full one; 0 skips it)")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched and serving workloads")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the recompute-mode, batched, serving and spectrum workloads")
+    ap.add_argument("--no-recompute", dest="recompute", action="store_false",
+                    help="skip the recompute-mode run (the same steps with no energy table)")
     ap.add_argument("--batch-loop-sample", type=int, default=64)
     ap.add_argument("--serve", type=str, default="4,8", metavar="RATES",
                     help="open-loop serving at these comma-separated arrival rates (requests/s); '' skips it")
@@ -536,7 +574,7 @@ def main():
 
     extras = {}
     if args.no_extras:
-        args.batch, args.serve, args.spectrum = 0, "", ""
+        args.batch, args.serve, args.spectrum, args.recompute = 0, "", "", False
     if args.precision:
         log("precision study: complex128 run of the same %d steps" % K)
         ref = torch.empty(1 << n, dtype=torch.complex128, device=dev)
@@ -557,6 +595,11 @@ def main():
         }
         h2.close()
         del ref
+    if args.recompute:
+        log("recompute mode: the same %d steps with no energy table" % K)
+        extras["recompute"] = run_recompute(qaa, torch, n, lits, T, N, K, knots, amp)
+        log("recompute: %.4f ms/step (table mode %.4f), identical state: %s" % (
+            extras["recompute"]["ms_per_step_steps"], secs / K * 1e3, extras["recompute"]["identical_state"]))
     if args.batch:
         log("batched workload (%d instances)" % args.batch)
         extras["batch"] = run_batch(qaa, torch, args.batch, 2024, min(args.batch, args.batch_loop_sample))

@@ -129,6 +129,14 @@ qaa_status qaa_energy_table(qaa_instance *inst, void *d_table, qaa_etype etype, 
  */
 qaa_status qaa_debug_energy_block(const qaa_instance *inst, uint64_t z0, int32_t *out32);
 
+/*
+ * The statistics qaa_energy_table records (e_min, e_max, degeneracy) without
+ * building a table: the energies are scored from the clause records and
+ * discarded (two passes over the 2^n basis states).  Needed before a state
+ * in recompute mode can evolve.  SYNCHRONOUS.
+ */
+qaa_status qaa_energy_stats(qaa_instance *inst, void *stream);
+
 /* ---------------------------------------------------------------------
  * States.
  * ------------------------------------------------------------------- */
@@ -137,9 +145,25 @@ typedef struct qaa_state {
     const qaa_instance *inst;  /* instance the state evolves under */
     void *amp;                 /* device, 2^n interleaved complex amplitudes */
     qaa_dtype dtype;           /* QAA_C64 or QAA_C128 */
-    const void *table;         /* device energy table filled by qaa_energy_table */
-    qaa_etype etype;           /* element type of table */
+    const void *table;         /* device energy table filled by qaa_energy_table, or NULL:
+                                  recompute mode (below) */
+    qaa_etype etype;           /* element type of table (recompute mode: the width the
+                                  energies are held in; QAA_E_U8 needs E_max <= 255) */
 } qaa_state;
+
+/*
+ * Recompute mode.  A state whose table is NULL has the energy function
+ * (Sec. 4.3: the number of violated clauses) scored from the instance's
+ * clause records wherever it is needed -- in the evolution passes that
+ * apply the diagonal phase, once per call for states held in one
+ * workgroup, and in qaa_observables -- instead of being read from a
+ * 2^n-entry table.  Results equal the table mode's to the bit (the same
+ * integer counts).  It saves the table's 2^n (or 2 * 2^n) bytes of HBM at
+ * the cost of ALU time in the phase passes.  qaa_energy_stats (or
+ * qaa_energy_table) must have run for the instance.  Not offered by
+ * qaa_evolve_batch, qaa_autotune and qaa_spectrum (QAA_ERR_UNSUPPORTED /
+ * QAA_ERR_INVALID_ARG for a NULL table).
+ */
 
 /* psi(z) = 2^{-n/2}: the ground state of H_B (Sec. 2.1).  Needs only amp. */
 qaa_status qaa_state_init_uniform(const qaa_state *st, void *stream);

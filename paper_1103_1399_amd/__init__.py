@@ -113,6 +113,7 @@ _SIGS = {
     "qaa_instance_destroy": (None, [_vp]),
     "qaa_instance_info": (_st, [_vp, _i32p, _i32p, _i32p, _i32p, _i64p]),
     "qaa_energy_table": (_st, [_vp, _vp, ctypes.c_int, _vp]),
+    "qaa_energy_stats": (_st, [_vp, _vp]),
     "qaa_debug_energy_block": (_st, [_vp, ctypes.c_uint64, _i32p]),
     "qaa_state_init_uniform": (_st, [ctypes.POINTER(qaa_state), _vp]),
     "qaa_state_init_basis": (_st, [ctypes.POINTER(qaa_state), ctypes.c_uint64, _vp]),
@@ -226,6 +227,11 @@ def qaa_debug_energy_block(handle: int, z0: int):
     return list(out)
 
 
+def qaa_energy_stats(handle: int, stream=None) -> None:
+    """E_min, E_max and the ground-manifold size without building a table."""
+    _check(_lib.qaa_energy_stats(handle, _stream_ptr(stream)), "qaa_energy_stats")
+
+
 def make_state(handle: int, amp, table=None, etype: int | None = None) -> qaa_state:
     import torch
     if amp.dtype == torch.complex64:
@@ -242,7 +248,9 @@ def make_state(handle: int, amp, table=None, etype: int | None = None) -> qaa_st
         _check_buffer(table, n, 1 if etype == QAA_E_U8 else 2, "energy table")
         tp = table.data_ptr()
     else:
-        tp, etype = None, QAA_E_U8
+        # no table: recompute mode (energies scored from the clause records;
+        # etype is the width they are held in, uint8 unless given)
+        tp, etype = None, QAA_E_U8 if etype is None else etype
     return qaa_state(handle, amp.data_ptr(), dt, tp, int(etype))
 
 
@@ -356,6 +364,7 @@ class PassDesc(ctypes.Structure):
                 ("phi", ctypes.c_double), ("gphase", ctypes.c_double),
                 ("tile_begin", ctypes.c_uint64), ("tile_count", ctypes.c_uint64),
                 ("acc_in", ctypes.c_void_p), ("acc_out", ctypes.c_void_p), ("acc_zero", ctypes.c_void_p),
+                ("clauses", ctypes.c_void_p), ("m", ctypes.c_int32), ("pad_", ctypes.c_int32),
                 ("goff_first", ctypes.c_uint64 * 32), ("goff_last", ctypes.c_uint64 * 32),
                 ("ljp", (ctypes.c_uint16 * 32) * 12), ("lj", (ctypes.c_uint16 * 32) * 12),
                 ("rest_mask", ctypes.c_uint64),
@@ -506,6 +515,10 @@ class Instance:
     def info(self) -> dict:
         return qaa_instance_info(self.handle)
 
+    def energy_stats(self, stream=None) -> dict:
+        qaa_energy_stats(self.handle, stream)
+        return self.info()
+
     def energy_table(self, device="cuda", etype: int = QAA_E_U8, stream=None):
         import torch
         dt = torch.uint8 if etype == QAA_E_U8 else torch.int16
@@ -534,14 +547,19 @@ class Instance:
 class State:
     """A device state vector bound to an instance and its energy table."""
 
-    def __init__(self, inst: Instance, table, dtype=None, device="cuda", amp=None):
+    def __init__(self, inst: Instance, table, dtype=None, device="cuda", amp=None, etype=None):
+        """table None: recompute mode (qaa_energy_stats must have run)."""
         import torch
         self.inst = inst
         self.table = table
         if amp is None:
             amp = torch.empty(1 << inst.n, dtype=dtype or torch.complex64, device=device)
         self.amp = amp
-        etype = QAA_E_U8 if table.dtype == torch.uint8 else QAA_E_U16
+        if table is not None:
+            etype = QAA_E_U8 if table.dtype == torch.uint8 else QAA_E_U16
+        elif etype is None:
+            e_max = inst.info()["e_max"]
+            etype = QAA_E_U8 if 0 <= e_max <= 255 else QAA_E_U16
         self.c = make_state(inst.handle, amp, table, etype)
 
     def init_uniform(self, stream=None):

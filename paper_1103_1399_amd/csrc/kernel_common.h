@@ -143,5 +143,92 @@ __device__ __forceinline__ DevCoef dev_step_coef(double T, int64_t N, int64_t k,
     return c;
 }
 
+// ---------------------------------------------------------------------------
+// Bit-sliced clause counting (the energy function of Sec. 4.3), shared by
+// the energy-table kernel and the kernels that recompute E(z) from the
+// clause records instead of reading a table.  A thread scores the 32
+// basis states z = 32t .. 32t+31 at once: per clause one 32-bit word of
+// outcomes, summed into counter planes by carry-save adders.
+// ---------------------------------------------------------------------------
+// Carry-save adder on bit planes: a + b + c = lo + 2 hi, bit by bit.
+__host__ __device__ inline void csa(uint32_t &hi, uint32_t &lo, uint32_t a, uint32_t b, uint32_t c)
+{
+    const uint32_t u = a ^ b;
+    hi = (a & b) | (u & c);
+    lo = u ^ c;
+}
+
+template <int K>
+struct BitCounter {
+    uint32_t p[K];       // counter planes: bit i of p[b] is bit b of the count of z = 32t + i
+    uint32_t ovf;        // lanes whose count passed 2^K - 1
+
+    __host__ __device__ void clear()
+    {
+#pragma unroll
+        for (int b = 0; b < K; ++b) p[b] = 0u;
+        ovf = 0u;
+    }
+    // add `carry` at plane `from` and ripple upwards
+    __host__ __device__ void ripple(uint32_t carry, int from)
+    {
+#pragma unroll
+        for (int b = 0; b < K; ++b) {
+            if (b < from) continue;
+            const uint32_t nc = p[b] & carry;
+            p[b] ^= carry;
+            carry = nc;
+        }
+        ovf |= carry;
+    }
+    __host__ __device__ void add8(const uint32_t (&w)[8])
+    {
+        uint32_t twos_a, twos_b, fours_a, fours_b, eights;
+        csa(twos_a, p[0], p[0], w[0], w[1]);
+        csa(twos_b, p[0], p[0], w[2], w[3]);
+        csa(fours_a, p[1], p[1], twos_a, twos_b);
+        csa(twos_a, p[0], p[0], w[4], w[5]);
+        csa(twos_b, p[0], p[0], w[6], w[7]);
+        csa(fours_b, p[1], p[1], twos_a, twos_b);
+        csa(eights, p[2], p[2], fours_a, fours_b);
+        ripple(eights, 3);
+    }
+    __host__ __device__ void counts(uint32_t (&e)[32]) const
+    {
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+            uint32_t v = 0u;
+#pragma unroll
+            for (int b = 0; b < K; ++b) v |= ((p[b] >> i) & 1u) << b;
+            e[i] = v;
+        }
+    }
+};
+
+// Add clauses cl[0..m) for the block of thread t (z = 32t .. 32t+31).
+template <int K>
+__host__ __device__ inline void score_clauses(BitCounter<K> &bc, const ClauseRec *__restrict__ cl, int m, uint32_t t)
+{
+    auto word = [&](const ClauseRec &r) { return (t & r.mhi) == r.phi ? r.low : 0u; };
+    int c = 0;
+    for (; c + 8 <= m; c += 8) {
+        uint32_t w[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) w[j] = word(cl[c + j]);
+        bc.add8(w);
+    }
+    for (; c < m; ++c) bc.ripple(word(cl[c]), 0);
+}
+
+// Count of z = 32t + lane from the planes.
+template <int K>
+__host__ __device__ inline uint32_t count_of(const BitCounter<K> &bc, uint32_t lane)
+{
+    uint32_t v = 0u;
+#pragma unroll
+    for (int b = 0; b < K; ++b) v |= ((bc.p[b] >> lane) & 1u) << b;
+    return v;
+}
+
 }  // namespace
 }  // namespace qaa

@@ -26,76 +26,6 @@ namespace {
 // them with low-latency broadcast loads instead of scalar-cache round trips.
 // ---------------------------------------------------------------------------
 
-// Carry-save adder on bit planes: a + b + c = lo + 2 hi, bit by bit.
-__host__ __device__ inline void csa(uint32_t &hi, uint32_t &lo, uint32_t a, uint32_t b, uint32_t c)
-{
-    const uint32_t u = a ^ b;
-    hi = (a & b) | (u & c);
-    lo = u ^ c;
-}
-
-template <int K>
-struct BitCounter {
-    uint32_t p[K];       // counter planes: bit i of p[b] is bit b of the count of z = 32t + i
-    uint32_t ovf;        // lanes whose count passed 2^K - 1
-
-    __host__ __device__ void clear()
-    {
-#pragma unroll
-        for (int b = 0; b < K; ++b) p[b] = 0u;
-        ovf = 0u;
-    }
-    // add `carry` at plane `from` and ripple upwards
-    __host__ __device__ void ripple(uint32_t carry, int from)
-    {
-#pragma unroll
-        for (int b = 0; b < K; ++b) {
-            if (b < from) continue;
-            const uint32_t nc = p[b] & carry;
-            p[b] ^= carry;
-            carry = nc;
-        }
-        ovf |= carry;
-    }
-    __host__ __device__ void add8(const uint32_t (&w)[8])
-    {
-        uint32_t twos_a, twos_b, fours_a, fours_b, eights;
-        csa(twos_a, p[0], p[0], w[0], w[1]);
-        csa(twos_b, p[0], p[0], w[2], w[3]);
-        csa(fours_a, p[1], p[1], twos_a, twos_b);
-        csa(twos_a, p[0], p[0], w[4], w[5]);
-        csa(twos_b, p[0], p[0], w[6], w[7]);
-        csa(fours_b, p[1], p[1], twos_a, twos_b);
-        csa(eights, p[2], p[2], fours_a, fours_b);
-        ripple(eights, 3);
-    }
-    __host__ __device__ void counts(uint32_t (&e)[32]) const
-    {
-#pragma unroll
-        for (int i = 0; i < 32; ++i) {
-            uint32_t v = 0u;
-#pragma unroll
-            for (int b = 0; b < K; ++b) v |= ((p[b] >> i) & 1u) << b;
-            e[i] = v;
-        }
-    }
-};
-
-// Add clauses cl[0..m) for the block of thread t (z = 32t .. 32t+31).
-template <int K>
-__host__ __device__ inline void score_clauses(BitCounter<K> &bc, const ClauseRec *__restrict__ cl, int m, uint32_t t)
-{
-    auto word = [&](const ClauseRec &r) { return (t & r.mhi) == r.phi ? r.low : 0u; };
-    int c = 0;
-    for (; c + 8 <= m; c += 8) {
-        uint32_t w[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) w[j] = word(cl[c + j]);
-        bc.add8(w);
-    }
-    for (; c < m; ++c) bc.ripple(word(cl[c]), 0);
-}
-
 constexpr int kClauseChunk = 1024;     // clause records staged in LDS at a time (16 KiB)
 
 // stats: [0] ~E_min (maximum of complements), [1] E_max, [2] some E > 255
@@ -311,7 +241,19 @@ __device__ __forceinline__ void resident_body(const ResidentDesc &d)
 
     for (uint32_t z = tid; z < dim; z += blockDim.x) {
         tile[swz<F>(z)] = amp[z];
-        etile[z] = table[z];
+        if (table) etile[z] = table[z];
+    }
+    if (!table) {
+        // recompute mode: score the state's energies once, 32 z per thread
+        constexpr int K = sizeof(ET) == 1 ? 8 : 16;
+        const uint32_t blocks = (dim + 31u) / 32u;
+        for (uint32_t b = tid; b < blocks; b += blockDim.x) {
+            BitCounter<K> bc;
+            bc.clear();
+            score_clauses<K>(bc, d.clauses, d.m, b);
+            const uint32_t cnt = dim < 32u ? dim : 32u;
+            for (uint32_t i = 0; i < cnt; ++i) etile[32u * b + i] = (ET)count_of<K>(bc, i);
+        }
     }
 
     const double dt = d.T / (double)d.N;
@@ -546,6 +488,58 @@ __global__ void __launch_bounds__(256) obs_partial_kernel(const typename V2<F>::
     }
 }
 
+// Recompute mode (no table): thread blocks of 32 consecutive z, each scored
+// against the clause records (staged in LDS when they fit), then summed as
+// obs_partial_kernel does.
+template <typename F, int K>
+__global__ void __launch_bounds__(256) obs_recompute_kernel(const typename V2<F>::T *__restrict__ amp, int n,
+                                                            const ClauseRec *__restrict__ cl, int m, uint32_t emin,
+                                                            double *__restrict__ partials)
+{
+    __shared__ ClauseRec cl_s[kClauseChunk];
+    const bool staged = m <= kClauseChunk;
+    if (staged)
+        for (int i = (int)threadIdx.x; i < m; i += (int)blockDim.x) cl_s[i] = cl[i];
+    __syncthreads();
+    const ClauseRec *src = staged ? cl_s : cl;
+    const uint64_t dim = 1ull << n;
+    const uint64_t blocks = (dim + 31) / 32;
+    const uint32_t cnt = dim < 32 ? (uint32_t)dim : 32u;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < blocks; b += stride) {
+        BitCounter<K> bc;
+        bc.clear();
+        score_clauses<K>(bc, src, m, (uint32_t)b);
+        for (uint32_t i = 0; i < cnt; ++i) {
+            const typename V2<F>::T v = amp[32 * b + i];
+            const double p = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+            const uint32_t e = count_of<K>(bc, i);
+            a0 += p;
+            a1 += (double)e * p;
+            a2 += e == emin ? p : 0.0;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        a0 += __shfl_xor(a0, off, 64);
+        a1 += __shfl_xor(a1, off, 64);
+        a2 += __shfl_xor(a2, off, 64);
+    }
+    __shared__ double red[4][3];
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[wave][0] = a0;
+        red[wave][1] = a1;
+        red[wave][2] = a2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w][threadIdx.x];
+        partials[(uint64_t)blockIdx.x * 3 + threadIdx.x] = t;
+    }
+}
+
 __global__ void __launch_bounds__(256) obs_final_kernel(const double *__restrict__ partials, int nblocks,
                                                         double *__restrict__ out)
 {
@@ -726,11 +720,28 @@ int observables_blocks(int n)
     return (int)grid_for(dim, 256 * 16, 2048);
 }
 
-hipError_t launch_observables(const void *amp, int dtype, const void *table, int etype, int n, int emin,
-                              double *partials, int nblocks, double *out, hipStream_t s)
+hipError_t launch_observables(const void *amp, int dtype, const void *table, int etype, const ClauseRec *clauses,
+                              int m, int n, int emin, double *partials, int nblocks, double *out, hipStream_t s)
 {
     const uint64_t dim = 1ull << n;
-    if (dtype == 0) {
+    if (!table) {
+        const bool narrow = etype == 0;      // counts fit 8 planes when E_max <= 255
+        if (dtype == 0) {
+            if (narrow)
+                hipLaunchKernelGGL((obs_recompute_kernel<float, 8>), dim3(nblocks), dim3(256), 0, s,
+                                   reinterpret_cast<const float2 *>(amp), n, clauses, m, (uint32_t)emin, partials);
+            else
+                hipLaunchKernelGGL((obs_recompute_kernel<float, 16>), dim3(nblocks), dim3(256), 0, s,
+                                   reinterpret_cast<const float2 *>(amp), n, clauses, m, (uint32_t)emin, partials);
+        } else {
+            if (narrow)
+                hipLaunchKernelGGL((obs_recompute_kernel<double, 8>), dim3(nblocks), dim3(256), 0, s,
+                                   reinterpret_cast<const double2 *>(amp), n, clauses, m, (uint32_t)emin, partials);
+            else
+                hipLaunchKernelGGL((obs_recompute_kernel<double, 16>), dim3(nblocks), dim3(256), 0, s,
+                                   reinterpret_cast<const double2 *>(amp), n, clauses, m, (uint32_t)emin, partials);
+        }
+    } else if (dtype == 0) {
         if (etype == 0)
             hipLaunchKernelGGL((obs_partial_kernel<float, uint8_t>), dim3(nblocks), dim3(256), 0, s,
                                reinterpret_cast<const float2 *>(amp), reinterpret_cast<const uint8_t *>(table), dim,

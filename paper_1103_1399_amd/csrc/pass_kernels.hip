@@ -92,7 +92,7 @@ __device__ __forceinline__ uint32_t desc_u16(const PassDesc &d, uint32_t byte_of
 // Issue the HBM loads of one tile: residency-0 registers and, for a phase
 // pass, the tile's energies (16 consecutive bytes per access; tile bits 0..3
 // are physical bits 0..3 in every plan).
-template <typename F, typename ET, int TB, int RB, bool PHASE>
+template <typename F, typename ET, int TB, int RB, bool PHASE, bool RECOMP>
 __device__ __forceinline__ void pass_load(TileRegs<F, ET, TB, RB> &tr, const typename V2<F>::T *__restrict__ amp,
                                           const ET *__restrict__ table, const PassDesc &d, uint64_t base, uint64_t tg,
                                           uint32_t tid)
@@ -121,7 +121,7 @@ __device__ __forceinline__ void pass_load(TileRegs<F, ET, TB, RB> &tr, const typ
             v[j] = p[d.goff_first[j]];
         }
     }
-    if constexpr (PHASE) {
+    if constexpr (PHASE && !RECOMP) {
 #pragma unroll
         for (int i = 0; i < P::NE; ++i) {
             const uint32_t c = tid + (uint32_t)i * P::WG;
@@ -133,13 +133,56 @@ __device__ __forceinline__ void pass_load(TileRegs<F, ET, TB, RB> &tr, const typ
     }
 }
 
+// Clause records a recompute-mode workgroup keeps in LDS at a time.
+constexpr int kPassClauses = 128;
+
+// The energies of the tile at `base` into etile, recomputed from the clause
+// records: thread tid scores the RUN consecutive tile-local indices
+// tid*RUN .. tid*RUN + RUN - 1 (RUN = 32 for complex64, 16 for complex128:
+// the tile's passenger bits), which are consecutive basis states z because
+// the low tile bits are the low physical bits in every plan.  Clause
+// records come from cls in LDS (staged once per launch when m fits, else
+// in chunks here).
+template <typename F, typename ET, int TB, int RB>
+__device__ __forceinline__ void tile_energies(const PassDesc &d, uint64_t base, uint32_t tid, ET *etile,
+                                              ClauseRec *cls)
+{
+    using P = PassTraits<F, ET, TB, RB>;
+    constexpr int RUN = (int)(P::TS / P::WG);
+    constexpr int LRUN = RUN == 32 ? 5 : 4;
+    static_assert(RUN == (1 << LRUN), "one run of consecutive z per thread");
+    constexpr int K = sizeof(ET) == 1 ? 8 : 16;      // E <= 255 with a uint8 width, else <= 1023
+    const uint32_t l0 = tid * (uint32_t)RUN;
+    uint64_t off = 0;
+#pragma unroll
+    for (int j = LRUN; j < TB; ++j) off |= (uint64_t)((l0 >> j) & 1u) << d.tile_pos[j];
+    const uint64_t z0 = base | off;
+    const uint32_t t = (uint32_t)(z0 >> 5), lane0 = (uint32_t)(z0 & 31u);
+    BitCounter<K> bc;
+    bc.clear();
+    const int m = d.m;
+    if (m <= kPassClauses) {
+        score_clauses<K>(bc, cls, m, t);
+    } else {
+        for (int c0 = 0; c0 < m; c0 += kPassClauses) {
+            const int cm = min(kPassClauses, m - c0);
+            lds_barrier();
+            for (int i = (int)tid; i < cm; i += (int)P::WG) cls[i] = d.clauses[c0 + i];
+            lds_barrier();
+            score_clauses<K>(bc, cls, cm, t);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < RUN; ++i) etile[l0 + i] = (ET)count_of<K>(bc, lane0 + (uint32_t)i);
+}
+
 // Residencies of one tile, ending with the store to HBM.
-template <typename F, typename ET, int TB, int RB, bool PHASE>
+template <typename F, typename ET, int TB, int RB, bool PHASE, bool RECOMP>
 __device__ __forceinline__ void pass_compute(TileRegs<F, ET, TB, RB> &tr, typename V2<F>::T *__restrict__ amp,
                                              const PassDesc &d, uint64_t base,
                                              uint64_t tg_last, uint32_t tid,
                                              typename V2<F>::T *tile, const typename V2<F>::T *lut, ET *etile,
-                                             const Rot<F> &kA, const Rot<F> &kB, bool meas,
+                                             ClauseRec *cls, const Rot<F> &kA, const Rot<F> &kB, bool meas,
                                              unsigned long long &ssq)
 {
     using P = PassTraits<F, ET, TB, RB>;
@@ -151,7 +194,10 @@ __device__ __forceinline__ void pass_compute(TileRegs<F, ET, TB, RB> &tr, typena
     const auto &ev = tr.ev;
     // the previous tile's LDS reads are finished before this tile writes
     lds_barrier();
-    if constexpr (PHASE) {
+    if constexpr (PHASE && RECOMP) {
+        tile_energies<F, ET, TB, RB>(d, base, tid, etile, cls);
+        lds_barrier();
+    } else if constexpr (PHASE) {
 #pragma unroll
         for (int i = 0; i < P::NE; ++i)
             *reinterpret_cast<uint4 *>(etile + (size_t)(tid + (uint32_t)i * P::WG) * P::EPV) = ev[i];
@@ -283,7 +329,7 @@ __device__ __forceinline__ void pass_compute(TileRegs<F, ET, TB, RB> &tr, typena
 // computed (PIPE), else only tile `first`.  The phase table (a pass with a
 // phase) is built in LDS from phi, gphase and the norm correction *acc_in.
 // Returns this thread's fixed-point share of sum |psi|^2 when meas is set.
-template <typename F, typename ET, int TB, int RB, bool PHASE, bool PIPE>
+template <typename F, typename ET, int TB, int RB, bool PHASE, bool PIPE, bool RECOMP = false>
 __device__ __forceinline__ unsigned long long tile_loop(typename V2<F>::T *__restrict__ amp,
                                                         const ET *__restrict__ table, const PassDesc &d,
                                                         uint64_t first, uint64_t stride, uint64_t end, double phi,
@@ -298,8 +344,15 @@ __device__ __forceinline__ unsigned long long tile_loop(typename V2<F>::T *__res
     F2 *tile = reinterpret_cast<F2 *>(smem);
     F2 *lut = tile + P::TSP;
     ET *etile = reinterpret_cast<ET *>(lut + lut_cap<ET>());
+    ClauseRec *cls = reinterpret_cast<ClauseRec *>(etile + P::TS);     // recompute mode only
 
     const uint32_t tid = threadIdx.x;
+    if constexpr (PHASE && RECOMP) {
+        // clause records staged once for every tile of this launch (the
+        // first residency's barrier orders them before their first use)
+        if (d.m <= kPassClauses)
+            for (int i = (int)tid; i < d.m; i += (int)P::WG) cls[i] = d.clauses[i];
+    }
     uint64_t tg_first = 0, tg_last = 0;
 #pragma unroll
     for (int k = 0; k < P::WB; ++k) {
@@ -316,7 +369,7 @@ __device__ __forceinline__ unsigned long long tile_loop(typename V2<F>::T *__res
     const uint64_t mirror = d.reverse ? 2 * d.tile_begin + d.tile_count - 1 : 0;
     auto tile_at = [&](uint64_t x) { return tile_base<F, ET, TB, RB>(d, d.reverse ? mirror - x : x); };
     uint64_t w = first;             // callers pass first < end
-    pass_load<F, ET, TB, RB, PHASE>(ta, amp, table, d, tile_at(w), tg_first, tid);
+    pass_load<F, ET, TB, RB, PHASE, RECOMP>(ta, amp, table, d, tile_at(w), tg_first, tid);
 
     if constexpr (PHASE) {
         const double scale = acc_in ? rsqrt((double)(*acc_in) * (1.0 / kNormFixedScale)) : 1.0;
@@ -332,21 +385,21 @@ __device__ __forceinline__ unsigned long long tile_loop(typename V2<F>::T *__res
 
     unsigned long long ss = 0ull;
     if constexpr (!PIPE) {
-        pass_compute<F, ET, TB, RB, PHASE>(ta, amp, d, tile_at(w), tg_last, tid, tile, lut, etile,
-                                           kA, kB, meas, ss);
+        pass_compute<F, ET, TB, RB, PHASE, RECOMP>(ta, amp, d, tile_at(w), tg_last, tid, tile, lut, etile,
+                                                   cls, kA, kB, meas, ss);
     }
     while (PIPE) {
         const uint64_t w1 = w + stride;
-        pass_load<F, ET, TB, RB, PHASE>(tb, amp, table, d, tile_at(w1 < end ? w1 : w), tg_first,
+        pass_load<F, ET, TB, RB, PHASE, RECOMP>(tb, amp, table, d, tile_at(w1 < end ? w1 : w), tg_first,
                                         tid);
-        pass_compute<F, ET, TB, RB, PHASE>(ta, amp, d, tile_at(w), tg_last, tid, tile, lut, etile,
-                                           kA, kB, meas, ss);
+        pass_compute<F, ET, TB, RB, PHASE, RECOMP>(ta, amp, d, tile_at(w), tg_last, tid, tile, lut, etile,
+                                                   cls, kA, kB, meas, ss);
         if (w1 >= end) break;
         const uint64_t w2 = w1 + stride;
-        pass_load<F, ET, TB, RB, PHASE>(ta, amp, table, d, tile_at(w2 < end ? w2 : w1), tg_first,
+        pass_load<F, ET, TB, RB, PHASE, RECOMP>(ta, amp, table, d, tile_at(w2 < end ? w2 : w1), tg_first,
                                         tid);
-        pass_compute<F, ET, TB, RB, PHASE>(tb, amp, d, tile_at(w1), tg_last, tid, tile, lut,
-                                           etile, kA, kB, meas, ss);
+        pass_compute<F, ET, TB, RB, PHASE, RECOMP>(tb, amp, d, tile_at(w1), tg_last, tid, tile, lut,
+                                                   etile, cls, kA, kB, meas, ss);
         if (w2 >= end) break;
         w = w2;
     }
@@ -358,13 +411,13 @@ __device__ __forceinline__ unsigned long long tile_loop(typename V2<F>::T *__res
 // register budget is held to that occupancy.
 // PIPE: persistent grid (workgroup b takes tiles b, b + grid, ...) with the
 // next tile's loads in flight; otherwise one workgroup per tile.
-template <typename F, typename ET, int TB, int RB, bool PHASE, bool PIPE>
+template <typename F, typename ET, int TB, int RB, bool PHASE, bool PIPE, bool RECOMP>
 __global__ void __launch_bounds__(1 << (TB - RB), (TB - RB) >= 9 ? 1 : 2)
 pass_kernel(typename V2<F>::T *__restrict__ amp, const ET *__restrict__ table, const PassDesc d)
 {
     if (d.acc_zero && blockIdx.x == 0 && threadIdx.x == 0) *d.acc_zero = 0ull;
     const uint64_t first = d.tile_begin + blockIdx.x;     // grid size <= tile_count
-    const unsigned long long ss = tile_loop<F, ET, TB, RB, PHASE, PIPE>(
+    const unsigned long long ss = tile_loop<F, ET, TB, RB, PHASE, PIPE, RECOMP>(
         amp, table, d, first, gridDim.x, d.tile_begin + d.tile_count, d.phi, d.gphase, d.emax, d.acc_in,
         make_rot<F>(d.tA, d.sA), make_rot<F>(d.tB, d.sB), d.acc_out != nullptr);
     if (d.acc_out) norm_accumulate(d.acc_out, ss);
@@ -442,14 +495,15 @@ batch_pass_kernel(const BatchInst *__restrict__ insts, const uint32_t *__restric
     if (acc_out) norm_accumulate(acc_out, ss);
 }
 
-template <typename F, typename ET, int TB, int RB, bool PHASE, bool PIPE>
+template <typename F, typename ET, int TB, int RB, bool PHASE, bool PIPE, bool RECOMP>
 hipError_t launch_pass_p(void *amp, const void *table, const PassDesc &d, hipStream_t s)
 {
     using F2 = typename V2<F>::T;
     constexpr int DT = sizeof(F) == 4 ? 0 : 1;
     constexpr size_t TS = size_t(1) << TB;
-    const size_t lds = sizeof(F2) * (TS + kPadN[DT] * (TS >> kPadS[DT]) + lut_cap<ET>()) + sizeof(ET) * TS;
-    const void *fn = reinterpret_cast<const void *>(&pass_kernel<F, ET, TB, RB, PHASE, PIPE>);
+    const size_t lds = sizeof(F2) * (TS + kPadN[DT] * (TS >> kPadS[DT]) + lut_cap<ET>()) + sizeof(ET) * TS +
+                       (RECOMP ? sizeof(ClauseRec) * kPassClauses : 0);
+    const void *fn = reinterpret_cast<const void *>(&pass_kernel<F, ET, TB, RB, PHASE, PIPE, RECOMP>);
     // persistent grid: as many workgroups as fit on the device at once
     // (set up once per instantiation; static initialisation is thread-safe)
     struct Setup {
@@ -466,7 +520,7 @@ hipError_t launch_pass_p(void *amp, const void *table, const PassDesc &d, hipStr
     }();
     if (setup.err != hipSuccess) return setup.err;
     const unsigned grid = PIPE ? (unsigned)std::min<uint64_t>(d.tile_count, setup.resident) : (unsigned)d.tile_count;
-    hipLaunchKernelGGL((pass_kernel<F, ET, TB, RB, PHASE, PIPE>), dim3(grid), dim3(1u << (TB - RB)), lds, s,
+    hipLaunchKernelGGL((pass_kernel<F, ET, TB, RB, PHASE, PIPE, RECOMP>), dim3(grid), dim3(1u << (TB - RB)), lds, s,
                        reinterpret_cast<F2 *>(amp), reinterpret_cast<const ET *>(table), d);
     return hipGetLastError();
 }
@@ -487,9 +541,20 @@ inline int pass_variant()
 template <typename F, typename ET, int TB, int RB, bool PHASE>
 hipError_t launch_pass_v(void *amp, const void *table, const PassDesc &d, hipStream_t s)
 {
+    // recompute mode (no table): passes with a phase score their tiles'
+    // energies from the clause records
+    if (PHASE && !table) {
+        if constexpr (PHASE) {
+            // (the persistent form would spill registers with 16-bit energies)
+            const int v = pass_variant();
+            if (sizeof(ET) == 2 || v == 0 || (v < 0 && !d.persist))
+                return launch_pass_p<F, ET, TB, RB, true, false, true>(amp, table, d, s);
+            if constexpr (sizeof(ET) == 1) return launch_pass_p<F, ET, TB, RB, true, true, true>(amp, table, d, s);
+        }
+    }
     const int v = pass_variant();
-    if (v == 0 || (v < 0 && !d.persist)) return launch_pass_p<F, ET, TB, RB, PHASE, false>(amp, table, d, s);
-    return launch_pass_p<F, ET, TB, RB, PHASE, true>(amp, table, d, s);
+    if (v == 0 || (v < 0 && !d.persist)) return launch_pass_p<F, ET, TB, RB, PHASE, false, false>(amp, table, d, s);
+    return launch_pass_p<F, ET, TB, RB, PHASE, true, false>(amp, table, d, s);
 }
 
 template <typename F, typename ET, int TB, int RB>

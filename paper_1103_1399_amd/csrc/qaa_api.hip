@@ -224,6 +224,74 @@ extern "C" qaa_status qaa_debug_energy_block(const qaa_instance *inst, uint64_t 
 // ---------------------------------------------------------------------------
 // Energy table
 // ---------------------------------------------------------------------------
+namespace {
+
+// The instance's clause records on the calling thread's device (uploaded
+// on first use, kept until the instance is destroyed).
+qaa_status device_clauses(qaa_instance *inst, ClauseRec **out, const char *who)
+{
+    int dev = 0;
+    QAA_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(inst->mu);
+    auto it = inst->dev_recs.find(dev);
+    if (it != inst->dev_recs.end()) {
+        *out = it->second;
+        return QAA_OK;
+    }
+    ClauseRec *recs = nullptr;
+    const size_t bytes = sizeof(ClauseRec) * std::max<size_t>(1, inst->recs.size());
+    QAA_HIP(hipMalloc(reinterpret_cast<void **>(&recs), bytes));
+    if (!inst->recs.empty()) {
+        hipError_t e = hipMemcpy(recs, inst->recs.data(), sizeof(ClauseRec) * inst->recs.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(recs);
+            return fail(QAA_ERR_DEVICE, "%s: clause upload failed: %s", who, hipGetErrorString(e));
+        }
+    }
+    inst->dev_recs[dev] = recs;
+    *out = recs;
+    return QAA_OK;
+}
+
+}  // namespace
+
+extern "C" qaa_status qaa_energy_stats(qaa_instance *inst, void *stream)
+{
+    const char *who = "qaa_energy_stats";
+    if (!inst) return fail(QAA_ERR_INVALID_ARG, "%s: inst is NULL", who);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    ClauseRec *recs = nullptr;
+    qaa_status r = device_clauses(inst, &recs, who);
+    if (r != QAA_OK) return r;
+    // the statistics of qaa_energy_table, with no table written: E_min and
+    // E_max in one pass, then the number of z at E_min in a second
+    StreamScratch scr;
+    scr.s = s;
+    QAA_HIP(hipMallocAsync(&scr.p, 64, s));
+    uint32_t *stats = reinterpret_cast<uint32_t *>(scr.p);
+    unsigned long long *count = reinterpret_cast<unsigned long long *>(stats + 4);
+    uint32_t h[4] = {0, 0, 0, 0};
+    bool wide = false;
+    for (int pass = 0; pass < 2; ++pass) {
+        QAA_HIP(launch_zero_u64(reinterpret_cast<unsigned long long *>(stats), 3, s));
+        QAA_HIP(launch_energy(recs, inst->m, inst->n, nullptr, QAA_E_U16, wide, stats, 0, nullptr, s));
+        QAA_HIP(hipMemcpyAsync(h, stats, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        QAA_HIP(hipStreamSynchronize(s));
+        if (!h[3]) break;
+        wide = true;              // some count passed 255: count again with 16 planes
+    }
+    const uint32_t emin = ~h[0], emax = h[1];
+    QAA_HIP(launch_zero_u64(reinterpret_cast<unsigned long long *>(stats), 3, s));
+    QAA_HIP(launch_energy(recs, inst->m, inst->n, nullptr, QAA_E_U16, wide, stats, (int)emin, count, s));
+    unsigned long long hc = 0;
+    QAA_HIP(hipMemcpyAsync(&hc, count, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    QAA_HIP(hipStreamSynchronize(s));
+    inst->e_min = (int32_t)emin;
+    inst->e_max = (int32_t)emax;
+    inst->degeneracy = (int64_t)hc;
+    return ok();
+}
+
 extern "C" qaa_status qaa_energy_table(qaa_instance *inst, void *d_table, qaa_etype etype, void *stream)
 {
     if (!inst) return fail(QAA_ERR_INVALID_ARG, "qaa_energy_table: inst is NULL");
@@ -233,29 +301,9 @@ extern "C" qaa_status qaa_energy_table(qaa_instance *inst, void *d_table, qaa_et
     if (etype != QAA_E_U8 && etype != QAA_E_U16)
         return fail(QAA_ERR_INVALID_ARG, "qaa_energy_table: bad etype %d", (int)etype);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    int dev = 0;
-    QAA_HIP(hipGetDevice(&dev));
-
     ClauseRec *recs = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(inst->mu);
-        auto it = inst->dev_recs.find(dev);
-        if (it == inst->dev_recs.end()) {
-            const size_t bytes = sizeof(ClauseRec) * std::max<size_t>(1, inst->recs.size());
-            QAA_HIP(hipMalloc(reinterpret_cast<void **>(&recs), bytes));
-            if (!inst->recs.empty()) {
-                hipError_t e = hipMemcpy(recs, inst->recs.data(), sizeof(ClauseRec) * inst->recs.size(),
-                                         hipMemcpyHostToDevice);
-                if (e != hipSuccess) {
-                    (void)hipFree(recs);
-                    return fail(QAA_ERR_DEVICE, "qaa_energy_table: clause upload failed: %s", hipGetErrorString(e));
-                }
-            }
-            inst->dev_recs[dev] = recs;
-        } else {
-            recs = it->second;
-        }
-    }
+    qaa_status rc = device_clauses(inst, &recs, "qaa_energy_table");
+    if (rc != QAA_OK) return rc;
 
     // stats[0] = ~E_min (max of complements), stats[1] = E_max, stats[2] =
     // uint8 overflow flag; count = number of z at E_min
@@ -306,17 +354,22 @@ qaa_status check_state_amp(const qaa_state *st, const char *who)
     return QAA_OK;
 }
 
-qaa_status check_state_table(const qaa_state *st, const char *who)
+// A state with a table, or without one (recompute mode: the energies are
+// scored from the clause records where they are needed; etype is then the
+// width they are held in).  Either way the energy statistics must be known.
+qaa_status check_state_table(const qaa_state *st, const char *who, bool allow_recompute = true)
 {
     qaa_status r = check_state_amp(st, who);
     if (r != QAA_OK) return r;
-    if (!st->table) return fail(QAA_ERR_INVALID_ARG, "%s: state has no energy table", who);
+    if (!st->table && !allow_recompute)
+        return fail(QAA_ERR_UNSUPPORTED, "%s: needs an energy table (recompute mode is not offered here)", who);
     if (st->etype != QAA_E_U8 && st->etype != QAA_E_U16)
         return fail(QAA_ERR_INVALID_ARG, "%s: bad etype %d", who, (int)st->etype);
     if (reinterpret_cast<uintptr_t>(st->table) % 16)
         return fail(QAA_ERR_INVALID_ARG, "%s: energy table must be 16-byte aligned", who);
     if (st->inst->e_max < 0)
-        return fail(QAA_ERR_NOT_READY, "%s: qaa_energy_table has not run for this instance", who);
+        return fail(QAA_ERR_NOT_READY, "%s: neither qaa_energy_table nor qaa_energy_stats has run for this instance",
+                    who);
     return QAA_OK;
 }
 
@@ -806,7 +859,7 @@ void fill_residencies(PassDesc &d, const SetPlan &sp, int tb, int rb, int dt, bo
 }
 
 ResidentDesc make_resident_desc(const qaa_state *st, const SchedKnots &sc, double T, int64_t N, int64_t k0,
-                                int64_t k1, int rb)
+                                int64_t k1, int rb, const ClauseRec *clauses = nullptr)
 {
     const int n = st->inst->n;
     ResidentDesc d;
@@ -814,6 +867,8 @@ ResidentDesc make_resident_desc(const qaa_state *st, const SchedKnots &sc, doubl
     d.sched = sc;
     d.amp = st->amp;
     d.table = st->table;
+    d.clauses = clauses;
+    d.m = st->inst->m;
     d.n = n;
     d.emax = st->inst->e_max;
     d.T = T;
@@ -841,7 +896,12 @@ qaa_status run_resident(const qaa_state *st, const SchedKnots &sc, double T, int
 {
     int rb = 0, wb = 0;
     resident_shape(st->inst->n, &rb, &wb);
-    const ResidentDesc d = make_resident_desc(st, sc, T, N, k0, k1, rb);
+    ClauseRec *recs = nullptr;       // recompute mode: the kernel scores its energies once
+    if (!st->table) {
+        qaa_status rc = device_clauses(const_cast<qaa_instance *>(st->inst), &recs, "evolve");
+        if (rc != QAA_OK) return rc;
+    }
+    const ResidentDesc d = make_resident_desc(st, sc, T, N, k0, k1, rb, recs);
     QAA_HIP(launch_resident(nullptr, &d, 1, (int)st->dtype, (int)st->etype, rb, wb, s));
     return QAA_OK;
 }
@@ -1055,6 +1115,11 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, 
 {
     const std::vector<PassDesc> ps =
         plan_passes(p, st->inst->n, (int)st->dtype, st->inst->e_max, sc, T, N, k0, k1);
+    ClauseRec *recs = nullptr;       // recompute mode: passes with a phase score their tiles
+    if (!st->table) {
+        qaa_status rc = device_clauses(const_cast<qaa_instance *>(st->inst), &recs, "evolve");
+        if (rc != QAA_OK) return rc;
+    }
     unsigned long long *acc = nullptr;
     const bool own_acc = fixed_acc == nullptr;
     if (norm_control_enabled()) {
@@ -1082,6 +1147,8 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, 
     // and start on data still in the last-level cache.
     bool prev_low = false, prev_rev = false;
     for (PassDesc d : ps) {
+        d.clauses = recs;
+        d.m = st->inst->m;
         const bool full = d.tile_begin == 0 && d.tile_count == (1ull << d.n_rest);
         const bool low = d.set_id != top && full;
         d.reverse = (low && prev_low && !prev_rev) ? 1 : 0;
@@ -1112,7 +1179,7 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, 
             QAA_HIP(prof_event(&rec.a));
             QAA_HIP(prof_event(&rec.b));
             rec.bytes = dim * (double)d.tile_count / std::ldexp(1.0, d.n_rest) *
-                        (2.0 * amp_bytes + (d.phase_at >= 0 ? e_bytes : 0.0));
+                        (2.0 * amp_bytes + (d.phase_at >= 0 && st->table ? e_bytes : 0.0));
             QAA_HIP(hipEventRecord(rec.a, s));
         }
         hipError_t e = launch_pass(st->amp, (int)st->dtype, st->table, (int)st->etype, d.n - d.n_rest, p.reg_bits,
@@ -1466,7 +1533,7 @@ extern "C" qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, c
     for (int i = 0; i < count; ++i) {
         qaa_status r = to_knots(scheds ? &scheds[i] : nullptr, &scs[i], "qaa_evolve_batch");
         if (r != QAA_OK) return r;
-        r = check_state_table(&states[i], "qaa_evolve_batch");
+        r = check_state_table(&states[i], "qaa_evolve_batch", false);
         if (r != QAA_OK) return r;
         if (!(T[i] >= 0.0) || !std::isfinite(T[i]) || steps[i] < 0)
             return fail(QAA_ERR_INVALID_ARG, "qaa_evolve_batch: state %d has a bad T or step count", i);
@@ -1578,8 +1645,16 @@ extern "C" qaa_status qaa_observables(const qaa_state *st, qaa_obs *out, void *s
     QAA_HIP(hipMallocAsync(&scr.p, sizeof(double) * (3 * (size_t)nb + 4), s));
     double *partials = reinterpret_cast<double *>(scr.p);
     double *res = partials + 3 * (size_t)nb;
-    QAA_HIP(launch_observables(st->amp, (int)st->dtype, st->table, (int)st->etype, st->inst->n, st->inst->e_min,
-                               partials, nb, res, s));
+    ClauseRec *recs = nullptr;       // recompute mode: energies scored from the clause records
+    if (!st->table) {
+        r = device_clauses(const_cast<qaa_instance *>(st->inst), &recs, "qaa_observables");
+        if (r != QAA_OK) return r;
+    }
+    // (recompute mode: the etype argument picks the counter width, 8 planes
+    // when every count is at most 255)
+    const int et = st->table ? (int)st->etype : (st->inst->e_max <= 255 ? 0 : 1);
+    QAA_HIP(launch_observables(st->amp, (int)st->dtype, st->table, et, recs, st->inst->m, st->inst->n,
+                               st->inst->e_min, partials, nb, res, s));
     double h[3] = {0.0, 0.0, 0.0};
     QAA_HIP(hipMemcpyAsync(h, res, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
     QAA_HIP(hipStreamSynchronize(s));
@@ -1646,7 +1721,7 @@ extern "C" qaa_status qaa_plan_load(const char *path, int32_t *count)
 extern "C" qaa_status qaa_autotune(const qaa_state *scratch, int64_t steps, qaa_plan_choice *best,
                                    double *ms_per_step, void *stream)
 {
-    qaa_status r = check_state_table(scratch, "qaa_autotune");
+    qaa_status r = check_state_table(scratch, "qaa_autotune", false);
     if (r != QAA_OK) return r;
     if (steps < 1) return fail(QAA_ERR_INVALID_ARG, "qaa_autotune: steps < 1");
     const int n = scratch->inst->n, dt = (int)scratch->dtype, et = (int)scratch->etype;

@@ -82,6 +82,10 @@ struct ClauseRec {
 // For complex64, register bit 0 is always tile bit 0 (= physical bit 0), so
 // register pairs (j, j+1) are adjacent in memory and move as 16 bytes.
 //
+// Energies: a pass with a phase reads its tile's E(z) from the table, or,
+// when there is no table (recompute mode), scores the tile's basis states
+// against the clause records (32 consecutive z per thread, bit-sliced).
+//
 // Norm control: rounding in FP32 does not keep |psi|^2 = 1, and on the
 // nearly uniform states of the early sweep all amplitudes round alike, so
 // the error would add up coherently.  Every pass adds its output's
@@ -106,6 +110,9 @@ struct PassDesc {
     unsigned long long *acc_in;
     unsigned long long *acc_out;
     unsigned long long *acc_zero;
+    const ClauseRec *clauses;          // recompute mode (no energy table): the clause records
+    int32_t m;                         //   and their number
+    int32_t pad_;
     uint64_t goff_first[kMaxRegs];     // residency 0: global offset of register j
     uint64_t goff_last[kMaxRegs];      // last residency: global offset of register j
     uint16_t ljp[kMaxRes][kMaxRegs];   // residency r: padded LDS offset of register j
@@ -143,6 +150,9 @@ struct ResidentDesc {
     uint8_t gbits[8][8];       // group g: state bit of register bit i
     uint8_t tpos[8][16];       // group g: state bit of thread-index bit k
     uint8_t gmask[8];          // register bits of group g that rotate
+    const ClauseRec *clauses;  // table == nullptr: energies recomputed from these clause records
+    int32_t m;
+    int32_t pad2_;
     SchedKnots sched;
 };
 
@@ -222,8 +232,9 @@ constexpr int kPassRegBits[2] = {5, 4};
 // Low physical bits every high-qubit tile carries so that each global access
 // is a contiguous 256-byte run (32 complex64 / 16 complex128).
 constexpr int kPassengerBits[2] = {5, 4};
-hipError_t launch_observables(const void *amp, int dtype, const void *table, int etype, int n,
-                              int emin, double *partials, int nblocks, double *out,
+// table == nullptr: energies scored from clauses[0..m) instead.
+hipError_t launch_observables(const void *amp, int dtype, const void *table, int etype, const ClauseRec *clauses,
+                              int m, int n, int emin, double *partials, int nblocks, double *out,
                               hipStream_t s);
 int observables_blocks(int n);
 
