@@ -256,32 +256,16 @@ def run_spectrum(qaa, torch, n, points, iters, seed):
 def run_serving(qaa, count, rates, n_lo, n_hi, t_lo, t_hi, slots, budget):
     """Open-loop serving: Poisson arrivals at each rate (requests/s), each a
     planted 3-SAT solve; reports latency percentiles and completed solves/s."""
-    from qaa_inputs import planted_unique_3sat, serving_workload
+    from qaa_inputs import serving_workload
     out = []
     for rate in rates:
         wl = serving_workload(count, rate, n_lo=n_lo, n_hi=n_hi, t_lo=t_lo, t_hi=t_hi)
-        lits = [planted_unique_3sat(w["n"], w["seed"]).literals() for w in wl]
-        sv = qaa.qaa_server_create(budget, slots)
-        try:
-            t0 = time.perf_counter()
-            tickets = []
-            for w, li in zip(wl, lits):
-                delay = t0 + w["arrival"] - time.perf_counter()
-                if delay > 0:
-                    time.sleep(delay)
-                tickets.append(qaa.qaa_server_submit(sv, w["n"], li, w["T"], w["steps"]))
-            res = [qaa.qaa_server_wait(sv, t) for t in tickets]
-            t_end = time.perf_counter()
-        finally:
-            qaa.qaa_server_destroy(sv)
-        bad = [r for r in res if r["status"] != qaa.QAA_OK]
-        if bad:
-            raise RuntimeError("serving: %d requests failed (status %d)" % (len(bad), bad[0]["status"]))
+        res, secs = _serve_stream(qaa, wl, slots, budget, verbose=False)
         lat = [r["latency_s"] for r in res]
         out.append({"rate_per_s": rate, "requests": count, "p50_s": _percentile(lat, 50),
                     "p99_s": _percentile(lat, 99), "mean_queued_s": sum(r["queued_s"] for r in res) / count,
-                    "solves_per_s": count / (t_end - t0),
-                    "amp_steps_per_s": sum((1 << w["n"]) * w["steps"] for w in wl) / (t_end - t0)})
+                    "solves_per_s": count / secs,
+                    "amp_steps_per_s": sum((1 << w["n"]) * w["steps"] for w in wl) / secs})
         log("serving rate %.2f/s: p50 %.3f s p99 %.3f s, %.2f solves/s"
             % (rate, out[-1]["p50_s"], out[-1]["p99_s"], out[-1]["solves_per_s"]))
     return {"workload": "Poisson arrivals, n ~ U{%d..%d}, T ~ U[%g,%g), dt ~ 0.01, %d slots, %.1f GiB budget"
@@ -296,25 +280,42 @@ def _bootstrap_ci(xs, q, reps=2000, seed=1):
     return [est[int(0.025 * reps)], est[int(0.975 * reps) - 1]]
 
 
-def _serve_stream(qaa, wl, slots, budget):
-    """Submit the requests of wl at their arrival times; returns results and
-    the wall time from the first arrival to the last completion."""
+def _serve_stream(qaa, wl, slots, budget, verbose=True):
+    """Submit the requests of wl at their arrival times (open loop) and poll
+    them; returns the results in request order and the wall time from the
+    first arrival to the last completion.  verbose: log each completion, and
+    each quarter of a running request's steps as the server reports them."""
     from qaa_inputs import planted_unique_3sat
     lits = [planted_unique_3sat(w["n"], w["seed"]).literals() for w in wl]
+    count = len(wl)
+    res = [None] * count
+    tickets = []
+    quarter = [0] * count
+    done = 0
     sv = qaa.qaa_server_create(budget, slots)
     try:
         t0 = time.perf_counter()
-        tickets = []
-        for w, li in zip(wl, lits):
-            delay = t0 + w["arrival"] - time.perf_counter()
-            if delay > 0:
-                time.sleep(delay)
-            tickets.append(qaa.qaa_server_submit(sv, w["n"], li, w["T"], w["steps"]))
-        res = []
-        for i, t in enumerate(tickets):
-            res.append(qaa.qaa_server_wait(sv, t))
-            log("  request %d/%d n=%d T=%.1f done: latency %.2f s" % (i + 1, len(tickets), wl[i]["n"], wl[i]["T"],
-                                                                      res[-1]["latency_s"]))
+        while done < count:
+            now = time.perf_counter() - t0
+            while len(tickets) < count and wl[len(tickets)]["arrival"] <= now:
+                w = wl[len(tickets)]
+                tickets.append(qaa.qaa_server_submit(sv, w["n"], lits[len(tickets)], w["T"], w["steps"]))
+            for j, t in enumerate(tickets):
+                if res[j] is not None:
+                    continue
+                r = qaa.qaa_server_poll(sv, t)
+                if r["done"]:
+                    res[j] = r
+                    done += 1
+                    if verbose:
+                        log("  request %d/%d n=%d T=%.1f done (%d finished): latency %.2f s, queued %.2f s"
+                            % (j + 1, count, wl[j]["n"], wl[j]["T"], done, r["latency_s"], r["queued_s"]))
+                elif verbose and r["steps"] and 4 * r["steps_done"] // r["steps"] > quarter[j]:
+                    quarter[j] = 4 * r["steps_done"] // r["steps"]
+                    log("  request %d/%d n=%d: %d of %d steps" % (j + 1, count, wl[j]["n"], r["steps_done"],
+                                                                r["steps"]))
+            nxt = wl[len(tickets)]["arrival"] - (time.perf_counter() - t0) if len(tickets) < count else 0.002
+            time.sleep(min(0.002, max(0.0, nxt)))
         t_end = time.perf_counter()
     finally:
         qaa.qaa_server_destroy(sv)
@@ -322,6 +323,97 @@ def _serve_stream(qaa, wl, slots, budget):
     if bad:
         raise RuntimeError("serving: %d requests failed (status %d)" % (len(bad), bad[0]["status"]))
     return res, t_end - t0
+
+
+def _exclusive_step_ms(qaa, torch, n_lo, n_hi, seed=77, steps=10, warm=2):
+    """Step time of one request running alone, per n (complex64, uint8
+    table), and its one-off set-up (table, initial state, observables)."""
+    from qaa_inputs import planted_unique_3sat
+    out = {}
+    for n in range(n_lo, n_hi + 1):
+        li = planted_unique_3sat(n, seed + n).literals()
+        amp = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
+        table = torch.empty(1 << n, dtype=torch.uint8, device="cuda")
+        h = qaa.Instance(n, li)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        qaa.qaa_energy_table(h.handle, table, qaa.QAA_E_U8)
+        st = qaa.make_state(h.handle, amp, table, qaa.QAA_E_U8)
+        qaa.qaa_state_init_uniform(st)
+        qaa.qaa_observables(st)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        qaa.qaa_evolve_range(st, 100.0, 10000, 0, warm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        qaa.qaa_evolve_range(st, 100.0, 10000, warm, warm + steps)
+        torch.cuda.synchronize()
+        out[n] = {"step_ms": (time.perf_counter() - t0) / steps * 1e3, "setup_s": setup}
+        h.close()
+        del amp, table
+        log("  alone: n=%d %.4f ms/step, set-up %.3f s" % (n, out[n]["step_ms"], setup))
+    torch.cuda.empty_cache()          # the server allocates on its own
+    return out
+
+
+def run_serving_c5(qaa, torch, fractions, count, n_lo, n_hi, capacity_sample, one_slot, slots, budget):
+    """The serving workload: n ~ U{n_lo..n_hi}, T ~ U[10, 200), dt = 0.01,
+    Poisson arrivals at fractions of capacity; latency p50/p99 with 95 %
+    bootstrap intervals and completed solves/s per arrival rate.
+
+    Capacity (solves/s): the exclusive-service model 1 / E[service] from
+    each n's measured step time alone (E over the n and T distributions),
+    and, when capacity_sample > 0, a closed-loop measurement (that many
+    requests submitted at once, completed requests over the makespan) which
+    also counts the overlap of small solves; the arrival rates use the
+    closed-loop figure when there is one.  one_slot > 0: the same arrival
+    stream at that fraction once more through a one-slot server (one solve
+    at a time), the plain path the slots are compared with."""
+    from qaa_inputs import serving_workload
+    t_lo, t_hi, dt = 10.0, 200.0, 0.01
+    out = {"workload": "Poisson arrivals, n ~ U{%d..%d}, T ~ U[%g,%g), dt = %g, %d slots, %.0f GiB budget"
+                       % (n_lo, n_hi, t_lo, t_hi, dt, slots, budget / 2.0 ** 30)}
+    log("serving: exclusive step times for n = %d..%d" % (n_lo, n_hi))
+    alone = _exclusive_step_ms(qaa, torch, n_lo, n_hi)
+    mean_steps = (t_lo + t_hi) / 2.0 / dt
+    service = sum(a["setup_s"] + mean_steps * a["step_ms"] * 1e-3 for a in alone.values()) / len(alone)
+    out["alone"] = {str(k): v for k, v in alone.items()}
+    out["capacity_model"] = {"mean_service_s": service, "solves_per_s": 1.0 / service,
+                             "basis": "1 / E[set-up + steps x step time alone], n and T uniform"}
+    capacity = 1.0 / service
+    log("serving: exclusive-service capacity %.4f solves/s (mean service %.2f s)" % (capacity, service))
+    if capacity_sample > 0:
+        wl = serving_workload(capacity_sample, 1e9, seed=55, n_lo=n_lo, n_hi=n_hi, t_lo=t_lo, t_hi=t_hi, dt=dt)
+        log("serving capacity: %d requests at once" % capacity_sample)
+        res, secs = _serve_stream(qaa, wl, slots, budget, verbose=False)
+        capacity = capacity_sample / secs
+        out["capacity"] = {"requests": capacity_sample, "seconds": secs, "solves_per_s": capacity,
+                           "amp_steps": sum((1 << w["n"]) * w["steps"] for w in wl)}
+        log("serving capacity (closed loop): %.4f solves/s" % capacity)
+    points = []
+
+    def point(f, nslots):
+        rate = f * capacity
+        wl = serving_workload(count, rate, seed=int(1000 * f) + 7, n_lo=n_lo, n_hi=n_hi, t_lo=t_lo, t_hi=t_hi,
+                              dt=dt)
+        log("serving at %.2f of capacity: %.4f requests/s, %d requests, %d slots" % (f, rate, count, nslots))
+        res, secs = _serve_stream(qaa, wl, nslots, budget)
+        lat = [r["latency_s"] for r in res]
+        p = {"fraction": f, "slots": nslots, "rate_per_s": rate, "requests": count, "seconds": secs,
+             "p50_s": _percentile(lat, 50), "p50_ci95": _bootstrap_ci(lat, 50),
+             "p99_s": _percentile(lat, 99), "p99_ci95": _bootstrap_ci(lat, 99),
+             "mean_queued_s": sum(r["queued_s"] for r in res) / count, "solves_per_s": count / secs,
+             "n": [w["n"] for w in wl], "latency_s": [round(x, 4) for x in lat]}
+        log("serving %.2f (%d slots): p50 %.3f s p99 %.3f s, %.3f solves/s"
+            % (f, nslots, p["p50_s"], p["p99_s"], p["solves_per_s"]))
+        return p
+
+    for f in fractions:
+        points.append(point(f, slots))
+    if one_slot > 0:
+        points.append(point(one_slot, 1))
+    out["points"] = points
+    return out
 
 
 def run_recompute(qaa, torch, n, lits, T, N, K, knots, table_amp):
@@ -359,44 +451,6 @@ def run_recompute(qaa, torch, n, lits, T, N, K, knots, table_amp):
             "identical_state": same, "p_success": obs["p_success"], "norm": obs["norm"]}
 
 
-def run_serving_c5(qaa, fractions, count, capacity, capacity_sample, slots, budget):
-    """The serving workload at its configured scale: n ~ U{16..31}, T ~
-    U[10, 200), dt = 0.01, Poisson arrivals at fractions of the measured
-    capacity.  Capacity (solves/s) comes from a closed-loop run: a sample of
-    requests from the same distribution submitted at once, completed
-    requests over the makespan.  Latency p50/p99 with 95 % bootstrap
-    intervals per arrival rate."""
-    from qaa_inputs import serving_workload
-    out = {"workload": "Poisson arrivals, n ~ U{16..31}, T ~ U[10,200), dt ~ 0.01, %d slots, %.0f GiB budget"
-                       % (slots, budget / 2.0 ** 30)}
-    if capacity is None:
-        wl = serving_workload(capacity_sample, 1e9, seed=55)      # all arrive at once
-        log("serving capacity: %d requests at once (n = %s)" % (capacity_sample, [w["n"] for w in wl]))
-        res, secs = _serve_stream(qaa, wl, slots, budget)
-        capacity = capacity_sample / secs
-        out["capacity"] = {"requests": capacity_sample, "seconds": secs, "solves_per_s": capacity,
-                           "amp_steps": sum((1 << w["n"]) * w["steps"] for w in wl)}
-        log("serving capacity: %.4f solves/s" % capacity)
-    else:
-        out["capacity"] = {"solves_per_s": capacity, "given": True}
-    points = []
-    for f in fractions:
-        rate = f * capacity
-        wl = serving_workload(count, rate, seed=int(1000 * f) + 7)
-        log("serving at %.2f of capacity: %.4f requests/s, %d requests" % (f, rate, count))
-        res, secs = _serve_stream(qaa, wl, slots, budget)
-        lat = [r["latency_s"] for r in res]
-        points.append({"fraction": f, "rate_per_s": rate, "requests": count, "seconds": secs,
-                       "p50_s": _percentile(lat, 50), "p50_ci95": _bootstrap_ci(lat, 50),
-                       "p99_s": _percentile(lat, 99), "p99_ci95": _bootstrap_ci(lat, 99),
-                       "mean_queued_s": sum(r["queued_s"] for r in res) / count,
-                       "solves_per_s": count / secs,
-                       "n": [w["n"] for w in wl], "latency_s": lat})
-        log("serving %.2f: p50 %.2f s p99 %.2f s" % (f, points[-1]["p50_s"], points[-1]["p99_s"]))
-    out["points"] = points
-    return out
-
-
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -429,12 +483,15 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-c5", type=str, default="", metavar="FRACTIONS",
-                    help="the serving workload at its configured scale (n ~ U{16..31}, T ~ U[10,200)) at these "
-                         "comma-separated fractions of measured capacity; tens of minutes, off by default")
-    ap.add_argument("--serve-c5-requests", type=int, default=20)
-    ap.add_argument("--serve-c5-capacity", type=float, default=None,
-                    help="capacity in solves/s from an earlier run (skips the closed-loop measurement)")
-    ap.add_argument("--serve-c5-capacity-sample", type=int, default=8)
+                    help="the serving workload (n ~ U{16..31} by default, T ~ U[10,200)) at these "
+                         "comma-separated fractions of capacity; minutes to hours, off by default")
+    ap.add_argument("--serve-c5-requests", type=int, default=200, help="requests per arrival rate")
+    ap.add_argument("--serve-c5-n", type=str, default="16,31", help="n range lo,hi of the served requests")
+    ap.add_argument("--serve-c5-capacity-sample", type=int, default=0, metavar="COUNT",
+                    help="closed-loop capacity from COUNT requests submitted at once (0: the exclusive-service "
+                         "model alone)")
+    ap.add_argument("--serve-c5-one-slot", type=float, default=0.0, metavar="FRACTION",
+                    help="also run that fraction's arrival stream through a one-slot server")
     ap.add_argument("--spectrum", type=str, default="20,21,150", metavar="N,POINTS,ITERS",
                     help="lowest two levels of H(s) for an n-qubit instance on POINTS values of s with ITERS "
                          "Lanczos steps each (qaa_spectrum); empty: skip")
@@ -621,8 +678,10 @@ def main():
 
     if args.serve_c5:
         fr = [float(x) for x in args.serve_c5.split(",") if x]
-        extras["serving_c5"] = run_serving_c5(qaa, fr, args.serve_c5_requests, args.serve_c5_capacity,
-                                              args.serve_c5_capacity_sample, args.serve_slots, 256 << 30)
+        lo, hi = (int(x) for x in args.serve_c5_n.split(","))
+        extras["serving_c5"] = run_serving_c5(qaa, torch, fr, args.serve_c5_requests, lo, hi,
+                                              args.serve_c5_capacity_sample, args.serve_c5_one_slot,
+                                              args.serve_slots, 256 << 30)
 
     value = (2.0 ** n) / s_per_step
     out = {

@@ -333,7 +333,7 @@ qaa_status qaa_observables(const qaa_state *st, qaa_obs *out, void *stream);
  * Serving: a solve-request server.  Requests are admitted in arrival order
  * when one of `slots` workers is free and their HBM footprint
  * (qaa_server_footprint) fits the budget beside the admitted ones; each worker runs its solve (energy table, uniform
- * start, qaa_evolve, qaa_observables) on its own HIP stream, so solves
+ * start, qaa_evolve_range over chunks of steps, qaa_observables) on its own HIP stream, so solves
  * admitted while others run overlap on the device.  The server allocates
  * and frees each request's device buffers on the current device of the
  * thread that created it.
@@ -353,6 +353,9 @@ typedef struct qaa_server_result {
     qaa_obs obs;                /* observables of the final state (done == 1) */
     double queued_s;            /* time from submit to admission (so far, if not admitted) */
     double latency_s;           /* time from submit to completion (so far, if not done) */
+    int64_t steps;              /* the request's step count */
+    int64_t steps_done;         /* steps finished on the device so far (the solve evolves in
+                                   chunks and records each; == steps once done without error) */
 } qaa_server_result;
 
 /* Device bytes a request of n qubits and m clauses is charged at

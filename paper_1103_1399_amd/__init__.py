@@ -99,7 +99,8 @@ class qaa_server_config(ctypes.Structure):
 
 class qaa_server_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("done", ctypes.c_int32), ("obs", qaa_obs),
-                ("queued_s", ctypes.c_double), ("latency_s", ctypes.c_double)]
+                ("queued_s", ctypes.c_double), ("latency_s", ctypes.c_double),
+                ("steps", ctypes.c_int64), ("steps_done", ctypes.c_int64)]
 
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
@@ -441,6 +442,7 @@ def qaa_autotune(state: qaa_state, steps: int = 20, stream=None) -> dict:
 def _result_dict(r: qaa_server_result) -> dict:
     o = r.obs
     return {"status": r.status, "done": bool(r.done), "queued_s": r.queued_s, "latency_s": r.latency_s,
+            "steps": r.steps, "steps_done": r.steps_done,
             "norm": o.norm, "energy": o.energy, "p_success": o.p_success, "e_min": o.e_min,
             "degeneracy": o.degeneracy}
 

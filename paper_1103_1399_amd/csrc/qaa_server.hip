@@ -5,13 +5,14 @@
 // (qaa_server_footprint: complex64 state, energy table, clause records and
 // the library's per-call scratch).  Each slot owns
 // a HIP stream and runs the whole solve on it (energy table, uniform start,
-// all steps, observables), so solves admitted while others are running
+// the steps in chunks, observables), so solves admitted while others are running
 // overlap on the device and share it kernel by kernel.  Results do not
 // depend on what else runs: every kernel is deterministic and works only on
 // its request's buffers.
 #include "qaa.h"
 #include "qaa_internal.h"
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -38,6 +39,7 @@ struct Request {
     std::vector<double> knots;   // schedule table (empty: linear)
     double T = 0.0;
     int64_t steps = 0;
+    int64_t steps_done = 0;      // steps the device has finished (updated per chunk)
     size_t footprint = 0;
     int state = 0;               // 0 queued, 1 running, 2 done, 3 failed
     qaa_status status = QAA_OK;
@@ -75,8 +77,20 @@ size_t footprint_of(int32_t n, int32_t m)
     return dim * 8 + dim * (m > 255 ? 2 : 1) + sizeof(qaa::ClauseRec) * (size_t)m + (size_t(64) << 10);
 }
 
+// Steps evolved per qaa_evolve_range call of a solve: about a tenth to a
+// quarter of a second of device time at large n, the whole solve at small
+// n.  The worker waits for each chunk and records the steps done, which
+// qaa_server_poll reports; a chunk boundary costs one extra half-phase
+// pass, under 1 % at these sizes.
+int64_t chunk_steps(int32_t n)
+{
+    return n >= 29 ? 64 : (int64_t(1) << (35 - n));
+}
+
 // Run one solve on the worker's stream; returns a status and message.
-qaa_status solve(Request &rq, hipStream_t s, std::string &err)
+// progress(k) is called with the steps finished after each chunk.
+template <typename Progress>
+qaa_status solve(Request &rq, hipStream_t s, std::string &err, Progress &&progress)
 {
     qaa_instance *inst = nullptr;
     qaa_status st = qaa_instance_create(rq.n, (int32_t)(rq.lits.size() / 3), rq.lits.data(), &inst);
@@ -108,10 +122,22 @@ qaa_status solve(Request &rq, hipStream_t s, std::string &err)
         st = qaa_state_init_uniform(&state, s);
         const qaa_schedule sched{rq.knots.empty() ? QAA_SCHED_LINEAR : QAA_SCHED_TABLE, (int32_t)rq.knots.size(),
                                  rq.knots.empty() ? nullptr : rq.knots.data()};
-        if (st == QAA_OK) st = qaa_evolve(&state, &sched, rq.T, rq.steps, s);
+        const int64_t chunk = chunk_steps(rq.n);
+        for (int64_t k0 = 0; st == QAA_OK && k0 < rq.steps; k0 += chunk) {
+            const int64_t k1 = std::min(rq.steps, k0 + chunk);
+            st = qaa_evolve_range(&state, &sched, rq.T, rq.steps, k0, k1, s);
+            if (st == QAA_OK && k1 < rq.steps) {
+                if (hipStreamSynchronize(s) != hipSuccess) {
+                    st = QAA_ERR_DEVICE;
+                    err = "stream synchronisation failed";
+                    break;
+                }
+                progress(k1);
+            }
+        }
         if (st == QAA_OK) st = qaa_observables(&state, &rq.obs, s);
     }
-    if (st != QAA_OK) err = qaa_last_error();
+    if (st != QAA_OK && err.empty()) err = qaa_last_error();
     if (amp) (void)hipFreeAsync(amp, s);
     if (table) (void)hipFreeAsync(table, s);
     (void)hipStreamSynchronize(s);
@@ -143,7 +169,11 @@ void worker_main(qaa_server *sv)
         Request work = rq;                 // solve on a copy, outside the lock
         lk.unlock();
         std::string err;
-        const qaa_status st = s ? solve(work, s, err) : QAA_ERR_DEVICE;
+        auto progress = [&](int64_t k) {
+            std::lock_guard<std::mutex> g(sv->mu);
+            sv->reqs[id].steps_done = k;
+        };
+        const qaa_status st = s ? solve(work, s, err, progress) : QAA_ERR_DEVICE;
         if (!s) err = "worker stream could not be created";
         lk.lock();
         Request &done = sv->reqs[id];
@@ -152,6 +182,7 @@ void worker_main(qaa_server *sv)
         done.obs = work.obs;
         done.t_done = now_s();
         done.state = st == QAA_OK ? 2 : 3;
+        if (st == QAA_OK) done.steps_done = done.steps;
         std::vector<int32_t>().swap(done.lits);    // finished records keep only their results
         std::vector<double>().swap(done.knots);
         sv->in_use -= done.footprint;
@@ -230,6 +261,8 @@ void fill_result(const Request &rq, qaa_server_result *out)
     out->obs = rq.obs;
     out->queued_s = (rq.state >= 1 ? rq.t_start : now_s()) - rq.t_submit;
     out->latency_s = (rq.state >= 2 ? rq.t_done : now_s()) - rq.t_submit;
+    out->steps = rq.steps;
+    out->steps_done = rq.steps_done;
 }
 
 }  // namespace

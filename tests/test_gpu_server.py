@@ -161,3 +161,31 @@ def test_server_overlaps_solves(qaa):
         assert r_long["latency_s"] > r_short["latency_s"]
     finally:
         qaa.qaa_server_destroy(sv)
+
+
+def test_server_reports_progress_of_chunked_solves(qaa):
+    """A solve longer than one chunk of steps (2^13 steps at n = 22) runs as
+    several qaa_evolve_range calls: poll reports the steps finished, and the
+    result matches the same solve in one qaa_evolve call (a chunk boundary
+    applies two half-phases where one call merges them)."""
+    n, T, steps = 22, 90.0, 9000
+    lits = planted_unique_3sat(n, 140).literals()
+    sv = qaa.qaa_server_create(hbm_budget_bytes=1 << 30, slots=1)
+    seen = set()
+    try:
+        t = qaa.qaa_server_submit(sv, n, lits, T, steps)
+        while True:
+            r = qaa.qaa_server_poll(sv, t)
+            assert r["steps"] == steps and 0 <= r["steps_done"] <= steps
+            seen.add(r["steps_done"])
+            if r["done"]:
+                break
+            time.sleep(0.001)
+    finally:
+        qaa.qaa_server_destroy(sv)
+    assert r["status"] == qaa.QAA_OK and r["steps_done"] == steps
+    assert seen <= {0, 8192, steps}
+    solo = _solo(qaa, n, lits, T, steps)
+    for key in ("norm", "energy", "p_success"):
+        assert abs(r[key] - solo[key]) <= 1e-6 * max(1.0, abs(solo[key])), key
+    assert r["e_min"] == solo["e_min"] and r["degeneracy"] == solo["degeneracy"]
