@@ -295,8 +295,11 @@ __device__ __forceinline__ void pass_compute(TileRegs<F, ET, TB, RB> &tr, typena
         ssq += (unsigned long long)((double)st * kNormFixedScale + 0.5);
     }
     // Passes without a phase store with non-temporal (streaming) hints:
-    // measured 5 % faster.  With a phase the hint's register constraints
-    // push the kernel past 256 VGPRs, so those keep plain stores.
+    // measured 5 % faster.  Passes with a phase keep plain stores: in the
+    // persistent kernel the hint's register constraints push it past 256
+    // VGPRs, and in the other the streaming stores made the n = 28 set-0
+    // passes 7 % slower (what they write is what the next pass, running in
+    // the opposite direction, reads first from the last-level cache).
 #pragma unroll
     for (int j = 0; j < R; j += VW) {
         if constexpr (VW == 2) {
@@ -411,12 +414,19 @@ __device__ __forceinline__ unsigned long long tile_loop(typename V2<F>::T *__res
 // register budget is held to that occupancy.
 // PIPE: persistent grid (workgroup b takes tiles b, b + grid, ...) with the
 // next tile's loads in flight; otherwise one workgroup per tile.
+// xcds > 1: the grid is a multiple of xcds and the hardware deals
+// workgroups to the XCDs round-robin (workgroup b runs on XCD b % xcds);
+// workgroup b then takes the slot (b % xcds) * (grid / xcds) + b / xcds, so
+// that each XCD works through one contiguous range of tiles and tiles that
+// share cache lines (a top-set pass's table runs are shorter than a line)
+// meet in the same L2.
 template <typename F, typename ET, int TB, int RB, bool PHASE, bool PIPE, bool RECOMP>
 __global__ void __launch_bounds__(1 << (TB - RB), (TB - RB) >= 9 ? 1 : 2)
-pass_kernel(typename V2<F>::T *__restrict__ amp, const ET *__restrict__ table, const PassDesc d)
+pass_kernel(typename V2<F>::T *__restrict__ amp, const ET *__restrict__ table, const PassDesc d, uint32_t xcds)
 {
     if (d.acc_zero && blockIdx.x == 0 && threadIdx.x == 0) *d.acc_zero = 0ull;
-    const uint64_t first = d.tile_begin + blockIdx.x;     // grid size <= tile_count
+    const uint32_t slot = xcds > 1 ? (blockIdx.x % xcds) * (gridDim.x / xcds) + blockIdx.x / xcds : blockIdx.x;
+    const uint64_t first = d.tile_begin + slot;           // grid size <= tile_count
     const unsigned long long ss = tile_loop<F, ET, TB, RB, PHASE, PIPE, RECOMP>(
         amp, table, d, first, gridDim.x, d.tile_begin + d.tile_count, d.phi, d.gphase, d.emax, d.acc_in,
         make_rot<F>(d.tA, d.sA), make_rot<F>(d.tB, d.sB), d.acc_out != nullptr);
@@ -495,6 +505,19 @@ batch_pass_kernel(const BatchInst *__restrict__ insts, const uint32_t *__restric
     if (acc_out) norm_accumulate(acc_out, ss);
 }
 
+// XCDs the pass grid is arranged for (passes whose PassDesc::xcd_map is
+// set): 8 on MI355X (gfx950), the chiplets that each own an L2.
+// QAA_XCD_MAP=0 turns the arrangement off (a tuning switch; results do not
+// depend on it).
+inline unsigned xcd_count()
+{
+    static const unsigned x = [] {
+        const char *e = std::getenv("QAA_XCD_MAP");
+        return (e && std::atoi(e) == 0) ? 1u : 8u;
+    }();
+    return x;
+}
+
 template <typename F, typename ET, int TB, int RB, bool PHASE, bool PIPE, bool RECOMP>
 hipError_t launch_pass_p(void *amp, const void *table, const PassDesc &d, hipStream_t s)
 {
@@ -519,9 +542,14 @@ hipError_t launch_pass_p(void *amp, const void *table, const PassDesc &d, hipStr
         return Setup{e, (unsigned)std::max(1, cus * std::max(1, per_cu))};
     }();
     if (setup.err != hipSuccess) return setup.err;
-    const unsigned grid = PIPE ? (unsigned)std::min<uint64_t>(d.tile_count, setup.resident) : (unsigned)d.tile_count;
+    unsigned grid = PIPE ? (unsigned)std::min<uint64_t>(d.tile_count, setup.resident) : (unsigned)d.tile_count;
+    const unsigned xcds = xcd_count();
+    // the persistent grid rounds down to whole XCD groups (every slot still
+    // covers its tiles: the stride is the grid)
+    if (PIPE && d.xcd_map && xcds > 1 && grid > xcds) grid -= grid % xcds;
+    const unsigned xmap = d.xcd_map && xcds > 1 && grid % xcds == 0 ? xcds : 1u;
     hipLaunchKernelGGL((pass_kernel<F, ET, TB, RB, PHASE, PIPE, RECOMP>), dim3(grid), dim3(1u << (TB - RB)), lds, s,
-                       reinterpret_cast<F2 *>(amp), reinterpret_cast<const ET *>(table), d);
+                       reinterpret_cast<F2 *>(amp), reinterpret_cast<const ET *>(table), d, xmap);
     return hipGetLastError();
 }
 

@@ -1161,6 +1161,13 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, 
         // 0.89 -> 0.82 ms, set-0 turns 0.84 -> 0.81 ms; n = 16..21: 6-8 %
         // per step).
         d.persist = (top >= 2 && d.set_id == top) ? 1 : 0;
+        // Tiles grouped by XCD (pass_kernel): one workgroup per tile over a
+        // state larger than the last-level cache (n = 28: middle passes
+        // 0.82 -> 0.79 ms).  Smaller states, whose passes reuse what the
+        // previous pass left in the L2s, and the top set's persistent
+        // passes run better without (n = 22: +4 % per step; n = 28 top
+        // turns +5 %).
+        d.xcd_map = (!d.persist && st->inst->n >= 26 && st->dtype == QAA_C64) ? 1 : 0;
         prev_low = low;
         prev_rev = d.reverse != 0;
         // Norm control rides on the passes over the top qubit set: each one
