@@ -397,6 +397,27 @@ extern "C" qaa_status qaa_state_init_basis(const qaa_state *st, uint64_t z0, voi
 // ---------------------------------------------------------------------------
 namespace {
 
+// Which XCD takes which tiles of a pass (PassDesc::xcd_map, pass_kernel).
+// Over a state larger than the last-level cache: when the amplitude-index
+// bits of byte-address bits 10..12 are tile-number bits, those name the
+// XCD (each XCD streams its own 1 KiB-interleaved eighth of memory; n = 28
+// copy probe, 256-, 512- and 1024-byte runs: 5.8-6.0 TB/s, against
+// 5.0-5.3 with those bits at address bits 11..13 and 5.3-6.0 in the plain
+// order); when they lie inside the tile (set 0), the grid's top bits do
+// (64 KiB tiles: 5.0 -> 5.6 TB/s).  n = 28 passes: middle 0.82 -> 0.77 ms,
+// set-0 turns 0.81 -> 0.80 ms.  The persistent passes (top set) and
+// smaller states run better in the plain order (n = 28 top turns: 0.96 ms
+// plain, 0.98-1.00 ms with the XCD on tile bits 1..6; n = 22: 4 % per
+// step, its passes reusing what the previous pass left in the L2s).
+int xcd_arrangement(const PassDesc &d, int n, int dtype)
+{
+    if (n < 26 || d.persist) return 0;
+    const int xb = dtype == QAA_C64 ? 7 : 6;          // amplitude bit of byte-address bit 10
+    const uint64_t three = 7ull << xb;
+    if ((d.rest_mask & three) != three) return 1;
+    return 2 + __builtin_popcountll(d.rest_mask & ((1ull << xb) - 1));
+}
+
 struct SetPlan {
     int tb = 0;                  // tile bits of this set's passes
     std::vector<int> tile;       // physical bits of the tile, ascending (size tb)
@@ -1161,13 +1182,7 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, 
         // 0.89 -> 0.82 ms, set-0 turns 0.84 -> 0.81 ms; n = 16..21: 6-8 %
         // per step).
         d.persist = (top >= 2 && d.set_id == top) ? 1 : 0;
-        // Tiles grouped by XCD (pass_kernel): one workgroup per tile over a
-        // state larger than the last-level cache (n = 28: middle passes
-        // 0.82 -> 0.79 ms).  Smaller states, whose passes reuse what the
-        // previous pass left in the L2s, and the top set's persistent
-        // passes run better without (n = 22: +4 % per step; n = 28 top
-        // turns +5 %).
-        d.xcd_map = (!d.persist && st->inst->n >= 26 && st->dtype == QAA_C64) ? 1 : 0;
+        d.xcd_map = xcd_arrangement(d, st->inst->n, (int)st->dtype);
         prev_low = low;
         prev_rev = d.reverse != 0;
         // Norm control rides on the passes over the top qubit set: each one

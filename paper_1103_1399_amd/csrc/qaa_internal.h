@@ -112,7 +112,7 @@ struct PassDesc {
     unsigned long long *acc_zero;
     const ClauseRec *clauses;          // recompute mode (no energy table): the clause records
     int32_t m;                         //   and their number
-    int32_t xcd_map;                   // 1: arrange the grid by XCD (see pass_kernel)
+    int32_t xcd_map;                   // grid slots by XCD: 0 plain, 1 top bits, 2 + k tile bit k
     uint64_t goff_first[kMaxRegs];     // residency 0: global offset of register j
     uint64_t goff_last[kMaxRegs];      // last residency: global offset of register j
     uint16_t ljp[kMaxRes][kMaxRegs];   // residency r: padded LDS offset of register j
