@@ -29,6 +29,33 @@ __device__ __forceinline__ void norm_accumulate(unsigned long long *acc, unsigne
     if ((threadIdx.x & 63) == 0) atomicAdd(acc, v);
 }
 
+// Add the workgroup's fixed-point norm share into slot blockIdx %
+// kNormSlots of the accumulator acc (one atomic per workgroup).  Every
+// thread of the workgroup calls it.
+__device__ __forceinline__ void norm_accumulate_slots(unsigned long long *acc, unsigned long long v)
+{
+    __shared__ unsigned long long wave_sum[16];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const uint32_t wave = threadIdx.x >> 6, waves = (blockDim.x + 63) >> 6;
+    if ((threadIdx.x & 63) == 0) wave_sum[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (uint32_t w = 0; w < waves; ++w) t += wave_sum[w];
+        atomicAdd(acc + (size_t)(blockIdx.x % kNormSlots) * kNormStride, t);
+    }
+}
+
+// Sum of the first `slots` slots of a norm accumulator (slots <= 64), in
+// every lane of the calling wave.
+__device__ __forceinline__ unsigned long long norm_total(const unsigned long long *acc, int slots)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    unsigned long long v = lane < slots ? acc[(size_t)lane * kNormStride] : 0ull;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 // Workgroup barrier that orders LDS traffic only: HBM loads issued before it
 // stay in flight.
 __device__ __forceinline__ void lds_barrier()
@@ -337,7 +364,8 @@ __device__ __forceinline__ unsigned long long tile_loop(typename V2<F>::T *__res
                                                         const ET *__restrict__ table, const PassDesc &d,
                                                         uint64_t first, uint64_t stride, uint64_t end, double phi,
                                                         double gphase, int emax,
-                                                        const unsigned long long *acc_in, const Rot<F> &kA,
+                                                        const unsigned long long *acc_in, int acc_slots,
+                                                        const Rot<F> &kA,
                                                         const Rot<F> &kB, bool meas)
 {
     using P = PassTraits<F, ET, TB, RB>;
@@ -375,7 +403,7 @@ __device__ __forceinline__ unsigned long long tile_loop(typename V2<F>::T *__res
     pass_load<F, ET, TB, RB, PHASE, RECOMP>(ta, amp, table, d, tile_at(w), tg_first, tid);
 
     if constexpr (PHASE) {
-        const double scale = acc_in ? rsqrt((double)(*acc_in) * (1.0 / kNormFixedScale)) : 1.0;
+        const double scale = acc_in ? rsqrt((double)norm_total(acc_in, acc_slots) * (1.0 / kNormFixedScale)) : 1.0;
         for (int e = (int)tid; e <= emax; e += (int)P::WG) {
             double sn, cs;
             sincos(fma(phi, (double)e, gphase), &sn, &cs);
@@ -427,7 +455,7 @@ template <typename F, typename ET, int TB, int RB, bool PHASE, bool PIPE, bool R
 __global__ void __launch_bounds__(1 << (TB - RB), (TB - RB) >= 9 ? 1 : 2)
 pass_kernel(typename V2<F>::T *__restrict__ amp, const ET *__restrict__ table, const PassDesc d, int32_t xk)
 {
-    if (d.acc_zero && blockIdx.x == 0 && threadIdx.x == 0) *d.acc_zero = 0ull;
+    if (d.acc_zero && blockIdx.x == 0 && threadIdx.x < kNormSlots) d.acc_zero[threadIdx.x * kNormStride] = 0ull;
     uint32_t slot = blockIdx.x;
     if (xk >= 0) {
         const uint32_t r = slot >> 3;
@@ -435,9 +463,9 @@ pass_kernel(typename V2<F>::T *__restrict__ amp, const ET *__restrict__ table, c
     }
     const uint64_t first = d.tile_begin + slot;           // grid size <= tile_count
     const unsigned long long ss = tile_loop<F, ET, TB, RB, PHASE, PIPE, RECOMP>(
-        amp, table, d, first, gridDim.x, d.tile_begin + d.tile_count, d.phi, d.gphase, d.emax, d.acc_in,
+        amp, table, d, first, gridDim.x, d.tile_begin + d.tile_count, d.phi, d.gphase, d.emax, d.acc_in, kNormSlots,
         make_rot<F>(d.tA, d.sA), make_rot<F>(d.tB, d.sB), d.acc_out != nullptr);
-    if (d.acc_out) norm_accumulate(d.acc_out, ss);
+    if (d.acc_out) norm_accumulate_slots(d.acc_out, ss);
 }
 
 // ---------------------------------------------------------------------------
@@ -504,10 +532,10 @@ batch_pass_kernel(const BatchInst *__restrict__ insts, const uint32_t *__restric
     const ET *table = reinterpret_cast<const ET *>(I.table);
     unsigned long long ss;
     if (d.phase_at >= 0)
-        ss = tile_loop<F, ET, TB, RB, true, true>(amp, table, d, w0, 1, w1, phi, gph, I.emax, acc_in, kA, kB,
+        ss = tile_loop<F, ET, TB, RB, true, true>(amp, table, d, w0, 1, w1, phi, gph, I.emax, acc_in, 1, kA, kB,
                                                   acc_out != nullptr);
     else
-        ss = tile_loop<F, ET, TB, RB, false, true>(amp, table, d, w0, 1, w1, phi, gph, I.emax, acc_in, kA, kB,
+        ss = tile_loop<F, ET, TB, RB, false, true>(amp, table, d, w0, 1, w1, phi, gph, I.emax, acc_in, 1, kA, kB,
                                                    acc_out != nullptr);
     if (acc_out) norm_accumulate(acc_out, ss);
 }

@@ -1145,11 +1145,12 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, 
     const bool own_acc = fixed_acc == nullptr;
     if (norm_control_enabled()) {
         if (own_acc)
-            QAA_HIP(hipMallocAsync(reinterpret_cast<void **>(&acc), 3 * sizeof(unsigned long long), s));
+            QAA_HIP(hipMallocAsync(reinterpret_cast<void **>(&acc), 3 * kNormAccWords * sizeof(unsigned long long),
+                                   s));
         else
             acc = fixed_acc;
         // a fill kernel, not a memset node: callers may capture this call
-        QAA_HIP(launch_zero_u64(acc, 3, s));
+        QAA_HIP(launch_zero_u64(acc, 3 * kNormAccWords, s));
     }
     bool prof;
     {
@@ -1173,15 +1174,15 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, 
         const bool full = d.tile_begin == 0 && d.tile_count == (1ull << d.n_rest);
         const bool low = d.set_id != top && full;
         d.reverse = (low && prev_low && !prev_rev) ? 1 : 0;
-        // With three or more sets, the top set's tiles are gathered from
-        // 256-byte runs spread over the whole state and its table reads come
-        // in 64-byte runs: only the persistent grid, with the next tile's
-        // loads in flight, streams them well (one workgroup per tile: 5.6x
-        // slower).  Every other pass, and every pass of a two-set plan,
-        // streams faster with one workgroup per tile (n = 28: middle passes
-        // 0.89 -> 0.82 ms, set-0 turns 0.84 -> 0.81 ms; n = 16..21: 6-8 %
-        // per step).
-        d.persist = (top >= 2 && d.set_id == top) ? 1 : 0;
+        // One workgroup per tile streams fastest (n = 28: middle passes
+        // 0.89 -> 0.82 ms, set-0 turns 0.84 -> 0.81 ms, top turns 0.96 ->
+        // 0.94 ms; n = 16..21: 6-8 % per step), except over the top set of a
+        // plan with three or more sets from n = 29 on (complex64; its tiles
+        // are gathered from runs spread over the whole state, n = 29..31:
+        // 1-5 % per step faster on the persistent grid, with the next
+        // tile's loads in flight) and for complex128, measured on the
+        // persistent grid only.
+        d.persist = (top >= 2 && d.set_id == top && (st->dtype != QAA_C64 || st->inst->n >= 29)) ? 1 : 0;
         d.xcd_map = xcd_arrangement(d, st->inst->n, (int)st->dtype);
         prev_low = low;
         prev_rev = d.reverse != 0;
@@ -1189,9 +1190,9 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, 
         // measures the norm of its output, and rescales by the norm the
         // previous one measured (passes over other sets carry no norm work).
         if (acc && d.set_id == top) {
-            d.acc_out = acc + gj % 3;
-            d.acc_zero = acc + (gj + 1) % 3;
-            d.acc_in = gj > 0 ? acc + (gj + 2) % 3 : nullptr;
+            d.acc_out = acc + kNormAccWords * (gj % 3);
+            d.acc_zero = acc + kNormAccWords * ((gj + 1) % 3);
+            d.acc_in = gj > 0 ? acc + kNormAccWords * ((gj + 2) % 3) : nullptr;
             ++gj;
         }
         ProfRec rec{};
@@ -1259,7 +1260,7 @@ qaa_status qaa::to_knots(const qaa_schedule *sched, SchedKnots *out, const char 
 // ---------------------------------------------------------------------------
 namespace {
 
-constexpr int kScratchWords = 32;     // 256 bytes; a call uses 3 words
+constexpr int kScratchWords = 3 * kNormAccWords;     // 12 KiB: three norm accumulators
 static __device__ __align__(256) unsigned long long scratch[kScratchWords];
 
 std::mutex g_scratch_mu;
@@ -1308,7 +1309,7 @@ qaa_status evolve_common(const qaa_state *st, const qaa_schedule *sched, double 
     } else {
         // the accumulators do not grow with n: every state the library
         // accepts (n <= QAA_MAX_QUBITS) fits the scratch array
-        static_assert(3 <= kScratchWords, "norm-control accumulators exceed the scratch array");
+        static_assert(3 * kNormAccWords <= kScratchWords, "norm-control accumulators exceed the scratch array");
         unsigned long long *fixed_acc = nullptr;
         if (noalloc) {
             r = scratch_address(&fixed_acc, who);

@@ -93,6 +93,14 @@ struct ClauseRec {
 // order-independent, hence deterministic), clears acc_zero for the pass
 // after it, and a pass with a phase divides its LUT by sqrt(*acc_in), the
 // norm measured by the pass before it (acc_in == nullptr: no rescale).
+// Each accumulator is kNormSlots 64-bit slots kNormStride words apart (one
+// per 128-byte line): a pass grid of tens of thousands of workgroups adds
+// one share per workgroup into slot blockIdx % kNormSlots, and the reader
+// sums the slots.  (One address taking every share serialises them: about
+// 3 ms per n = 28 pass with one atomic per wave.)
+constexpr int kNormSlots = 32;
+constexpr int kNormStride = 16;
+constexpr int kNormAccWords = kNormSlots * kNormStride;    // one accumulator
 constexpr int kMaxRegs = 32;
 struct PassDesc {
     int32_t n;
