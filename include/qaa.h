@@ -31,7 +31,7 @@
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Calls are asynchronous on it unless stated otherwise.
  *  - Library-owned device memory: a device copy of each instance's clause
- *    list, the 12 KiB scratch array of qaa_evolve_range_noalloc (one per
+ *    list, the 64 KiB scratch array of qaa_evolve_range_noalloc (one per
  *    device, held until the process ends), and per-call buffers (norm
  *    accumulators, reduction partials, batch descriptors, qaa_spectrum's
  *    Lanczos vectors) taken from the stream-ordered allocator and released
@@ -233,9 +233,9 @@ qaa_status qaa_evolve_range(const qaa_state *st, const qaa_schedule *sched, doub
  * capture, tight serving loops, harnesses that forbid hipMalloc: the same
  * evolution as qaa_evolve_range (same arguments, same kernels, bit-identical
  * results), but it allocates nothing.  The only device scratch an evolution
- * needs, three norm-control accumulators (32 64-bit slots each, one per
- * 128-byte line), lives in a library-owned static device array of 12 KiB
- * per device (held until the process
+ * needs, the norm-control totals and partial sums (8192 + 16 64-bit words),
+ * lives in a library-owned static device array of 64 KiB + 128 bytes per
+ * device (held until the process
  * ends; its address is looked up once per device on the first call there).
  * Every state the library accepts fits it, so no size is refused beyond
  * what qaa_evolve_range refuses.  All calls on one device share that array

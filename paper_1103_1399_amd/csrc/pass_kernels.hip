@@ -29,32 +29,43 @@ __device__ __forceinline__ void norm_accumulate(unsigned long long *acc, unsigne
     if ((threadIdx.x & 63) == 0) atomicAdd(acc, v);
 }
 
-// Add the workgroup's fixed-point norm share into slot blockIdx %
-// kNormSlots of the accumulator acc (one atomic per workgroup).  Every
-// thread of the workgroup calls it.
-__device__ __forceinline__ void norm_accumulate_slots(unsigned long long *acc, unsigned long long v)
+// Add each wave's fixed-point norm share into its partial slot (wave g of
+// the grid into slot g mod kNormPartials): no barrier, and a slot takes
+// only the few shares of waves kNormPartials apart in the grid.
+__device__ __forceinline__ void norm_accumulate_partials(unsigned long long *slots, unsigned long long v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const uint32_t waves = (blockDim.x + 63) >> 6;
+    const uint32_t g = blockIdx.x * waves + (threadIdx.x >> 6);
+    if ((threadIdx.x & 63) == 0) atomicAdd(slots + (g & (kNormPartials - 1)), v);
+}
+
+// Workgroup b < min(kNormReducers, grid) sums its share of the partial
+// slots of the previous measuring pass, clears them for the next one, and
+// adds the sum into *dst (the total the next phase pass reads).
+__device__ __noinline__ void norm_reduce_partials(unsigned long long *src, unsigned long long *dst)
 {
     __shared__ unsigned long long wave_sum[16];
+    const uint32_t nred = gridDim.x < (uint32_t)kNormReducers ? gridDim.x : (uint32_t)kNormReducers;
+    const uint32_t chunk = ((uint32_t)kNormPartials + nred - 1) / nred;
+    const uint32_t lo = blockIdx.x * chunk;
+    const uint32_t hi = lo + chunk < (uint32_t)kNormPartials ? lo + chunk : (uint32_t)kNormPartials;
+    unsigned long long v = 0;
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        v += src[i];
+        src[i] = 0ull;
+    }
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    const uint32_t wave = threadIdx.x >> 6, waves = (blockDim.x + 63) >> 6;
-    if ((threadIdx.x & 63) == 0) wave_sum[wave] = v;
+    const uint32_t waves = (blockDim.x + 63) >> 6;
+    if ((threadIdx.x & 63) == 0) wave_sum[threadIdx.x >> 6] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long t = 0;
         for (uint32_t w = 0; w < waves; ++w) t += wave_sum[w];
-        atomicAdd(acc + (size_t)(blockIdx.x % kNormSlots) * kNormStride, t);
+        atomicAdd(dst, t);
     }
 }
 
-// Sum of the first `slots` slots of a norm accumulator (slots <= 64), in
-// every lane of the calling wave.
-__device__ __forceinline__ unsigned long long norm_total(const unsigned long long *acc, int slots)
-{
-    const int lane = (int)(threadIdx.x & 63);
-    unsigned long long v = lane < slots ? acc[(size_t)lane * kNormStride] : 0ull;
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
 
 // Workgroup barrier that orders LDS traffic only: HBM loads issued before it
 // stay in flight.
@@ -364,8 +375,7 @@ __device__ __forceinline__ unsigned long long tile_loop(typename V2<F>::T *__res
                                                         const ET *__restrict__ table, const PassDesc &d,
                                                         uint64_t first, uint64_t stride, uint64_t end, double phi,
                                                         double gphase, int emax,
-                                                        const unsigned long long *acc_in, int acc_slots,
-                                                        const Rot<F> &kA,
+                                                        const unsigned long long *acc_in, const Rot<F> &kA,
                                                         const Rot<F> &kB, bool meas)
 {
     using P = PassTraits<F, ET, TB, RB>;
@@ -403,7 +413,7 @@ __device__ __forceinline__ unsigned long long tile_loop(typename V2<F>::T *__res
     pass_load<F, ET, TB, RB, PHASE, RECOMP>(ta, amp, table, d, tile_at(w), tg_first, tid);
 
     if constexpr (PHASE) {
-        const double scale = acc_in ? rsqrt((double)norm_total(acc_in, acc_slots) * (1.0 / kNormFixedScale)) : 1.0;
+        const double scale = acc_in ? rsqrt((double)(*acc_in) * (1.0 / kNormFixedScale)) : 1.0;
         for (int e = (int)tid; e <= emax; e += (int)P::WG) {
             double sn, cs;
             sincos(fma(phi, (double)e, gphase), &sn, &cs);
@@ -455,7 +465,8 @@ template <typename F, typename ET, int TB, int RB, bool PHASE, bool PIPE, bool R
 __global__ void __launch_bounds__(1 << (TB - RB), (TB - RB) >= 9 ? 1 : 2)
 pass_kernel(typename V2<F>::T *__restrict__ amp, const ET *__restrict__ table, const PassDesc d, int32_t xk)
 {
-    if (d.acc_zero && blockIdx.x == 0 && threadIdx.x < kNormSlots) d.acc_zero[threadIdx.x * kNormStride] = 0ull;
+    if (d.acc_zero && blockIdx.x == 0 && threadIdx.x == 0) *d.acc_zero = 0ull;
+    if (d.red_dst && blockIdx.x < (uint32_t)kNormReducers) norm_reduce_partials(d.red_src, d.red_dst);
     uint32_t slot = blockIdx.x;
     if (xk >= 0) {
         const uint32_t r = slot >> 3;
@@ -463,9 +474,9 @@ pass_kernel(typename V2<F>::T *__restrict__ amp, const ET *__restrict__ table, c
     }
     const uint64_t first = d.tile_begin + slot;           // grid size <= tile_count
     const unsigned long long ss = tile_loop<F, ET, TB, RB, PHASE, PIPE, RECOMP>(
-        amp, table, d, first, gridDim.x, d.tile_begin + d.tile_count, d.phi, d.gphase, d.emax, d.acc_in, kNormSlots,
+        amp, table, d, first, gridDim.x, d.tile_begin + d.tile_count, d.phi, d.gphase, d.emax, d.acc_in,
         make_rot<F>(d.tA, d.sA), make_rot<F>(d.tB, d.sB), d.acc_out != nullptr);
-    if (d.acc_out) norm_accumulate_slots(d.acc_out, ss);
+    if (d.acc_out) norm_accumulate_partials(d.acc_out, ss);
 }
 
 // ---------------------------------------------------------------------------
@@ -532,10 +543,10 @@ batch_pass_kernel(const BatchInst *__restrict__ insts, const uint32_t *__restric
     const ET *table = reinterpret_cast<const ET *>(I.table);
     unsigned long long ss;
     if (d.phase_at >= 0)
-        ss = tile_loop<F, ET, TB, RB, true, true>(amp, table, d, w0, 1, w1, phi, gph, I.emax, acc_in, 1, kA, kB,
+        ss = tile_loop<F, ET, TB, RB, true, true>(amp, table, d, w0, 1, w1, phi, gph, I.emax, acc_in, kA, kB,
                                                   acc_out != nullptr);
     else
-        ss = tile_loop<F, ET, TB, RB, false, true>(amp, table, d, w0, 1, w1, phi, gph, I.emax, acc_in, 1, kA, kB,
+        ss = tile_loop<F, ET, TB, RB, false, true>(amp, table, d, w0, 1, w1, phi, gph, I.emax, acc_in, kA, kB,
                                                    acc_out != nullptr);
     if (acc_out) norm_accumulate(acc_out, ss);
 }

@@ -1145,12 +1145,11 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, 
     const bool own_acc = fixed_acc == nullptr;
     if (norm_control_enabled()) {
         if (own_acc)
-            QAA_HIP(hipMallocAsync(reinterpret_cast<void **>(&acc), 3 * kNormAccWords * sizeof(unsigned long long),
-                                   s));
+            QAA_HIP(hipMallocAsync(reinterpret_cast<void **>(&acc), kNormWords * sizeof(unsigned long long), s));
         else
             acc = fixed_acc;
         // a fill kernel, not a memset node: callers may capture this call
-        QAA_HIP(launch_zero_u64(acc, 3 * kNormAccWords, s));
+        QAA_HIP(launch_zero_u64(acc, kNormWords, s));
     }
     bool prof;
     {
@@ -1168,6 +1167,7 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, 
     // opposite direction: consecutive lower-set passes alternate direction
     // and start on data still in the last-level cache.
     bool prev_low = false, prev_rev = false;
+    bool reduce_next = false;   // the previous pass measured the norm
     for (PassDesc d : ps) {
         d.clauses = recs;
         d.m = st->inst->m;
@@ -1190,10 +1190,18 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, 
         // measures the norm of its output, and rescales by the norm the
         // previous one measured (passes over other sets carry no norm work).
         if (acc && d.set_id == top) {
-            d.acc_out = acc + kNormAccWords * (gj % 3);
-            d.acc_zero = acc + kNormAccWords * ((gj + 1) % 3);
-            d.acc_in = gj > 0 ? acc + kNormAccWords * ((gj + 2) % 3) : nullptr;
+            d.acc_out = acc + kNormTotalsWords;
+            d.acc_zero = acc + (gj + 1) % 3;
+            d.acc_in = gj > 0 ? acc + (gj + 2) % 3 : nullptr;
             ++gj;
+            reduce_next = true;
+        } else if (reduce_next) {
+            // the pass after a measuring pass reduces its partial slots into
+            // the total the next measuring pass scales by (top-set passes
+            // are never adjacent)
+            d.red_src = acc + kNormTotalsWords;
+            d.red_dst = acc + (gj - 1) % 3;
+            reduce_next = false;
         }
         ProfRec rec{};
         if (prof) {
@@ -1260,7 +1268,7 @@ qaa_status qaa::to_knots(const qaa_schedule *sched, SchedKnots *out, const char 
 // ---------------------------------------------------------------------------
 namespace {
 
-constexpr int kScratchWords = 3 * kNormAccWords;     // 12 KiB: three norm accumulators
+constexpr int kScratchWords = kNormWords;     // 64 KiB + 128 B: the norm totals and partial slots
 static __device__ __align__(256) unsigned long long scratch[kScratchWords];
 
 std::mutex g_scratch_mu;
@@ -1309,7 +1317,7 @@ qaa_status evolve_common(const qaa_state *st, const qaa_schedule *sched, double 
     } else {
         // the accumulators do not grow with n: every state the library
         // accepts (n <= QAA_MAX_QUBITS) fits the scratch array
-        static_assert(3 * kNormAccWords <= kScratchWords, "norm-control accumulators exceed the scratch array");
+        static_assert(kNormWords <= kScratchWords, "norm-control accumulators exceed the scratch array");
         unsigned long long *fixed_acc = nullptr;
         if (noalloc) {
             r = scratch_address(&fixed_acc, who);

@@ -93,14 +93,16 @@ struct ClauseRec {
 // order-independent, hence deterministic), clears acc_zero for the pass
 // after it, and a pass with a phase divides its LUT by sqrt(*acc_in), the
 // norm measured by the pass before it (acc_in == nullptr: no rescale).
-// Each accumulator is kNormSlots 64-bit slots kNormStride words apart (one
-// per 128-byte line): a pass grid of tens of thousands of workgroups adds
-// one share per workgroup into slot blockIdx % kNormSlots, and the reader
-// sums the slots.  (One address taking every share serialises them: about
-// 3 ms per n = 28 pass with one atomic per wave.)
-constexpr int kNormSlots = 32;
-constexpr int kNormStride = 16;
-constexpr int kNormAccWords = kNormSlots * kNormStride;    // one accumulator
+// A measuring pass adds each wave's share into one of kNormPartials slots
+// (acc_out, wave g of the grid into slot g mod kNormPartials), so that no
+// address takes more than a few of the tens of thousands of shares (one
+// address taking them all serialises them: about 3 ms per n = 28 pass).
+// The pass after it reduces the slots (red_src, clearing them) into the
+// single total red_dst with one atomic per reducing workgroup.
+constexpr int kNormPartials = 8192;
+constexpr int kNormReducers = 64;           // workgroups that reduce the slots
+constexpr int kNormTotalsWords = 16;        // the ring of three totals, padded to a line
+constexpr int kNormWords = kNormTotalsWords + kNormPartials;
 constexpr int kMaxRegs = 32;
 struct PassDesc {
     int32_t n;
@@ -115,9 +117,11 @@ struct PassDesc {
     double phi, gphase;
     uint64_t tile_begin;       // this launch handles tiles [tile_begin, tile_begin + tile_count)
     uint64_t tile_count;
-    unsigned long long *acc_in;
-    unsigned long long *acc_out;
-    unsigned long long *acc_zero;
+    unsigned long long *acc_in;        // norm total the phase is scaled by (nullptr: none)
+    unsigned long long *acc_out;       // norm partial slots this pass adds its shares into
+    unsigned long long *acc_zero;      // norm total to clear for a later pass
+    unsigned long long *red_src;       // norm partial slots to reduce (and clear) ...
+    unsigned long long *red_dst;       //   into this total (nullptr: no reduction)
     const ClauseRec *clauses;          // recompute mode (no energy table): the clause records
     int32_t m;                         //   and their number
     int32_t xcd_map;                   // grid slots by XCD: 0 plain, 1 top bits, 2 + k tile bit k
