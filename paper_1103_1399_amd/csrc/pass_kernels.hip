@@ -42,30 +42,24 @@ __device__ __forceinline__ void norm_accumulate_partials(unsigned long long *slo
 
 // Workgroup b < min(kNormReducers, grid) sums its share of the partial
 // slots of the previous measuring pass, clears them for the next one, and
-// adds the sum into *dst (the total the next phase pass reads).
+// adds the sum into *dst (the total the next phase pass reads).  Its first
+// wave does it alone: no LDS (the pass kernels' LDS budget is exact) and
+// no barrier.
 __device__ __noinline__ void norm_reduce_partials(unsigned long long *src, unsigned long long *dst)
 {
-    __shared__ unsigned long long wave_sum[16];
+    if (threadIdx.x >= 64) return;
     const uint32_t nred = gridDim.x < (uint32_t)kNormReducers ? gridDim.x : (uint32_t)kNormReducers;
     const uint32_t chunk = ((uint32_t)kNormPartials + nred - 1) / nred;
     const uint32_t lo = blockIdx.x * chunk;
     const uint32_t hi = lo + chunk < (uint32_t)kNormPartials ? lo + chunk : (uint32_t)kNormPartials;
     unsigned long long v = 0;
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += 64) {
         v += src[i];
         src[i] = 0ull;
     }
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    const uint32_t waves = (blockDim.x + 63) >> 6;
-    if ((threadIdx.x & 63) == 0) wave_sum[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (uint32_t w = 0; w < waves; ++w) t += wave_sum[w];
-        atomicAdd(dst, t);
-    }
+    if (threadIdx.x == 0) atomicAdd(dst, v);
 }
-
 
 // Workgroup barrier that orders LDS traffic only: HBM loads issued before it
 // stay in flight.
