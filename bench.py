@@ -53,13 +53,14 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
 # HBM traffic of the pass kernel measured with rocprofv3 --pmc (FETCH_SIZE and
 # WRITE_SIZE runs, scaled by the same counters' reading for a plain copy of
 # known size), per launch of the timed region's mix.  Valid only for the
-# kernel sources it was taken on (the pass kernels, their shared device
-# helpers and the descriptor layout).
+# sources it was taken on (the pass kernels, their shared device helpers,
+# the descriptor layout and the planner that decides the passes' tiles,
+# grids and order).
 PASS_KERNEL_SOURCES = ("paper_1103_1399_amd/csrc/pass_kernels.hip", "paper_1103_1399_amd/csrc/kernel_common.h",
-                       "paper_1103_1399_amd/csrc/qaa_internal.h")
+                       "paper_1103_1399_amd/csrc/qaa_internal.h", "paper_1103_1399_amd/csrc/qaa_api.hip")
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "",
-    "bytes_per_launch": 4.5085e+09,
+    "kernel_source_sha256": "99162d9c2870742276f49308d29207646ec1edbd2dc50b064467cabde36c0b55",
+    "bytes_per_launch": 4.4342e+09,
 }
 
 
