@@ -357,8 +357,9 @@ def _exclusive_step_ms(qaa, torch, n_lo, n_hi, seed=77, steps=10, warm=2):
     return out
 
 
-def run_serving_c5(qaa, torch, fractions, count, n_lo, n_hi, capacity_sample, one_slot, slots, budget):
-    """The serving workload: n ~ U{n_lo..n_hi}, T ~ U[10, 200), dt = 0.01,
+def run_serving_c5(qaa, torch, fractions, count, n_lo, n_hi, capacity_sample, one_slot, slots, budget,
+                   t_lo=10.0, t_hi=200.0):
+    """The serving workload: n ~ U{n_lo..n_hi}, T ~ U[t_lo, t_hi), dt = 0.01,
     Poisson arrivals at fractions of capacity; latency p50/p99 with 95 %
     bootstrap intervals and completed solves/s per arrival rate.
 
@@ -371,7 +372,7 @@ def run_serving_c5(qaa, torch, fractions, count, n_lo, n_hi, capacity_sample, on
     stream at that fraction once more through a one-slot server (one solve
     at a time), the plain path the slots are compared with."""
     from qaa_inputs import serving_workload
-    t_lo, t_hi, dt = 10.0, 200.0, 0.01
+    dt = 0.01
     out = {"workload": "Poisson arrivals, n ~ U{%d..%d}, T ~ U[%g,%g), dt = %g, %d slots, %.0f GiB budget"
                        % (n_lo, n_hi, t_lo, t_hi, dt, slots, budget / 2.0 ** 30)}
     log("serving: exclusive step times for n = %d..%d" % (n_lo, n_hi))
@@ -488,6 +489,7 @@ def main():
                          "comma-separated fractions of capacity; minutes to hours, off by default")
     ap.add_argument("--serve-c5-requests", type=int, default=200, help="requests per arrival rate")
     ap.add_argument("--serve-c5-n", type=str, default="16,31", help="n range lo,hi of the served requests")
+    ap.add_argument("--serve-c5-t", type=str, default="10,200", help="T range lo,hi of the served requests")
     ap.add_argument("--serve-c5-capacity-sample", type=int, default=0, metavar="COUNT",
                     help="closed-loop capacity from COUNT requests submitted at once (0: the exclusive-service "
                          "model alone)")
@@ -680,9 +682,10 @@ def main():
     if args.serve_c5:
         fr = [float(x) for x in args.serve_c5.split(",") if x]
         lo, hi = (int(x) for x in args.serve_c5_n.split(","))
+        tlo, thi = (float(x) for x in args.serve_c5_t.split(","))
         extras["serving_c5"] = run_serving_c5(qaa, torch, fr, args.serve_c5_requests, lo, hi,
                                               args.serve_c5_capacity_sample, args.serve_c5_one_slot,
-                                              args.serve_slots, 256 << 30)
+                                              args.serve_slots, 256 << 30, tlo, thi)
 
     value = (2.0 ** n) / s_per_step
     out = {
