@@ -456,6 +456,8 @@ def run_recompute(qaa, torch, n, lits, T, N, K, knots, table_amp):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--record", type=str, default="", metavar="PATH",
+                    help="also append the result line, with the host and library versions, to this JSONL file")
     ap.add_argument("--steps", type=int, default=5000, help="second-order steps timed (default: the full job)")
     ap.add_argument("--warmup", type=int, default=20, help="untimed warm-up steps")
     ap.add_argument("--n", type=int, default=28)
@@ -724,7 +726,16 @@ def main():
     out.update(extras)
     if cpu:
         out["gpu_over_cpu"] = value / cpu["value"]
-    print(json.dumps(out), flush=True)
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.record:
+        rec = dict(out)
+        rec["record"] = {"time_unix": time.time(), "host_cpus": os.cpu_count(), "torch": torch.__version__,
+                         "hip": torch.version.hip, "device": torch.cuda.get_device_name(dev),
+                         "libqaa_version": qaa.qaa_version(), "kernel_source_sha256": kernel_source_sha(),
+                         "argv": sys.argv[1:]}
+        with open(args.record, "a") as f:
+            f.write(json.dumps(rec) + "\n")
 
 
 if __name__ == "__main__":

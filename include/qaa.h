@@ -60,7 +60,8 @@ typedef enum qaa_status {
     QAA_ERR_OUT_OF_MEMORY = 3, /* a library-owned allocation failed / request can never fit */
     QAA_ERR_DEVICE = 4,        /* a HIP runtime call or kernel launch failed */
     QAA_ERR_NOT_READY = 5,     /* a prerequisite call has not run (e.g. no energy table yet) */
-    QAA_ERR_INTERNAL = 6
+    QAA_ERR_INTERNAL = 6,
+    QAA_ERR_CANCELLED = 7      /* a served request was cancelled (qaa_server_cancel) */
 } qaa_status;
 
 typedef enum qaa_dtype {
@@ -349,8 +350,8 @@ typedef struct qaa_server_config {
 } qaa_server_config;
 
 typedef struct qaa_server_result {
-    qaa_status status;          /* QAA_OK once done without error */
-    int32_t done;               /* 1 when the solve finished (or failed) */
+    qaa_status status;          /* QAA_OK once done without error (QAA_ERR_CANCELLED if cancelled) */
+    int32_t done;               /* 1 when the solve finished, failed or was cancelled */
     qaa_obs obs;                /* observables of the final state (done == 1) */
     double queued_s;            /* time from submit to admission (so far, if not admitted) */
     double latency_s;           /* time from submit to completion (so far, if not done) */
@@ -382,6 +383,15 @@ qaa_status qaa_server_submit(qaa_server *sv, int32_t n, int32_t m, const int32_t
 /* Non-blocking status of a ticket.  A finished request's record (its
  * status, observables and times, about 100 bytes) is kept until destroy. */
 qaa_status qaa_server_poll(qaa_server *sv, int64_t ticket, qaa_server_result *out);
+
+/* Cancel a request.  Still queued: it leaves the queue at once and
+ * finishes with status QAA_ERR_CANCELLED.  Running: the solve stops at its
+ * next chunk boundary (see above; the device finishes the chunk in flight),
+ * frees its buffers and finishes with QAA_ERR_CANCELLED, steps_done
+ * telling how far it got.  Already finished: nothing changes.  Either way
+ * the call returns QAA_OK without waiting; QAA_ERR_INVALID_ARG for a NULL
+ * server or an unknown ticket. */
+qaa_status qaa_server_cancel(qaa_server *sv, int64_t ticket);
 
 /* Block until the ticket's solve has finished, then fill *out. */
 qaa_status qaa_server_wait(qaa_server *sv, int64_t ticket, qaa_server_result *out);

@@ -42,6 +42,7 @@ QAA_ERR_OUT_OF_MEMORY = 3
 QAA_ERR_DEVICE = 4
 QAA_ERR_NOT_READY = 5
 QAA_ERR_INTERNAL = 6
+QAA_ERR_CANCELLED = 7
 # dtypes / table element types
 QAA_C64 = 0
 QAA_C128 = 1
@@ -142,6 +143,7 @@ _SIGS = {
                                 ctypes.c_double, ctypes.c_int64, _i64p]),
     "qaa_server_poll": (_st, [_vp, ctypes.c_int64, ctypes.POINTER(qaa_server_result)]),
     "qaa_server_wait": (_st, [_vp, ctypes.c_int64, ctypes.POINTER(qaa_server_result)]),
+    "qaa_server_cancel": (_st, [_vp, ctypes.c_int64]),
     "qaa_server_stats": (_st, [_vp, _i64p, _i64p, ctypes.POINTER(ctypes.c_uint64)]),
     "qaa_server_destroy": (None, [_vp]),
     "qaa_plan_get": (_st, [ctypes.c_int32, ctypes.c_int, ctypes.POINTER(qaa_plan_choice)]),
@@ -474,6 +476,11 @@ def qaa_server_poll(server: int, ticket: int) -> dict:
     r = qaa_server_result()
     _check(_lib.qaa_server_poll(server, int(ticket), ctypes.byref(r)), "qaa_server_poll")
     return _result_dict(r)
+
+
+def qaa_server_cancel(server: int, ticket: int) -> None:
+    """Cancel a queued or running request (see qaa.h)."""
+    _check(_lib.qaa_server_cancel(server, int(ticket)), "qaa_server_cancel")
 
 
 def qaa_server_wait(server: int, ticket: int) -> dict:

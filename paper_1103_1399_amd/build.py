@@ -15,6 +15,8 @@ SOURCES = ["kernels.hip", "pass_kernels.hip", "qaa_api.hip", "qaa_server.hip", "
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-result"]
+# roctx ranges (host-side names of API calls and pass launches in traces)
+LINK_FLAGS = ["-L" + os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib"), "-lrocprofiler-sdk-roctx"]
 
 
 def hipcc() -> str:
@@ -27,7 +29,7 @@ def build(verbose: bool = False, extra: list[str] | None = None) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc()] + HIP_FLAGS + (extra or []) + [
         "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-        *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+        *[os.path.join(CSRC, s) for s in SOURCES], *LINK_FLAGS, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -4,6 +4,8 @@
 #include "qaa.h"
 #include "qaa_internal.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
@@ -21,6 +23,27 @@ using namespace qaa;
 // ---------------------------------------------------------------------------
 // Errors
 // ---------------------------------------------------------------------------
+namespace {
+
+// A roctx range over the enclosing scope: host-side time of an API call or
+// of one pass's launch, named in rocprofv3 traces taken with
+// --marker-trace (the calls cost a few tens of nanoseconds when no tool
+// listens).
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    TraceRange(const char *fmt, int a, int b, long long c, long long d)
+    {
+        char buf[96];
+        std::snprintf(buf, sizeof buf, fmt, a, b, c, d);
+        roctxRangePushA(buf);
+    }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
+
+}  // namespace
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -257,6 +280,7 @@ qaa_status device_clauses(qaa_instance *inst, ClauseRec **out, const char *who)
 
 extern "C" qaa_status qaa_energy_stats(qaa_instance *inst, void *stream)
 {
+    TraceRange trace_range("qaa_energy_stats");
     const char *who = "qaa_energy_stats";
     if (!inst) return fail(QAA_ERR_INVALID_ARG, "%s: inst is NULL", who);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -294,6 +318,7 @@ extern "C" qaa_status qaa_energy_stats(qaa_instance *inst, void *stream)
 
 extern "C" qaa_status qaa_energy_table(qaa_instance *inst, void *d_table, qaa_etype etype, void *stream)
 {
+    TraceRange trace_range("qaa_energy_table");
     if (!inst) return fail(QAA_ERR_INVALID_ARG, "qaa_energy_table: inst is NULL");
     if (!d_table) return fail(QAA_ERR_INVALID_ARG, "qaa_energy_table: d_table is NULL");
     if (reinterpret_cast<uintptr_t>(d_table) % 16)
@@ -1213,8 +1238,12 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, 
                         (2.0 * amp_bytes + (d.phase_at >= 0 && st->table ? e_bytes : 0.0));
             QAA_HIP(hipEventRecord(rec.a, s));
         }
-        hipError_t e = launch_pass(st->amp, (int)st->dtype, st->table, (int)st->etype, d.n - d.n_rest, p.reg_bits,
-                                   d, s);
+        hipError_t e;
+        {
+            TraceRange tr("qaa pass: set %d, phase at residency %d, tiles %lld+%lld", d.set_id, d.phase_at,
+                          (long long)d.tile_begin, (long long)d.tile_count);
+            e = launch_pass(st->amp, (int)st->dtype, st->table, (int)st->etype, d.n - d.n_rest, p.reg_bits, d, s);
+        }
         if (e != hipSuccess) {
             if (acc && own_acc) (void)hipFreeAsync(acc, s);
             return fail(QAA_ERR_DEVICE, "pass launch failed: %s", hipGetErrorString(e));
@@ -1334,18 +1363,21 @@ qaa_status evolve_common(const qaa_state *st, const qaa_schedule *sched, double 
 extern "C" qaa_status qaa_evolve(const qaa_state *st, const qaa_schedule *sched, double T, int64_t steps,
                                  void *stream)
 {
+    TraceRange tr("qaa_evolve");
     return evolve_common(st, sched, T, steps, 0, steps, stream, "qaa_evolve");
 }
 
 extern "C" qaa_status qaa_evolve_range(const qaa_state *st, const qaa_schedule *sched, double T, int64_t steps,
                                        int64_t k0, int64_t k1, void *stream)
 {
+    TraceRange tr("qaa_evolve_range");
     return evolve_common(st, sched, T, steps, k0, k1, stream, "qaa_evolve_range");
 }
 
 extern "C" qaa_status qaa_evolve_range_noalloc(const qaa_state *st, const qaa_schedule *sched, double T,
                                                int64_t steps, int64_t k0, int64_t k1, void *stream)
 {
+    TraceRange tr("qaa_evolve_range_noalloc");
     return evolve_common(st, sched, T, steps, k0, k1, stream, "qaa_evolve_range_noalloc", true);
 }
 
@@ -1557,6 +1589,7 @@ qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states
 extern "C" qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, const qaa_schedule *scheds,
                                        const double *T, const int64_t *steps, void *stream)
 {
+    TraceRange trace_range("qaa_evolve_batch");
     if (count < 0) return fail(QAA_ERR_INVALID_ARG, "qaa_evolve_batch: count < 0");
     if (count == 0) return ok();
     if (!states || !T || !steps) return fail(QAA_ERR_INVALID_ARG, "qaa_evolve_batch: NULL array");
@@ -1640,6 +1673,7 @@ extern "C" qaa_status qaa_spectrum(const qaa_instance *inst, const void *table, 
                                    const double *s_values, const double *v0, int32_t iters, int32_t k,
                                    double *evals, double *bounds, void *stream)
 {
+    TraceRange trace_range("qaa_spectrum");
     const char *who = "qaa_spectrum";
     if (!inst) return fail(QAA_ERR_INVALID_ARG, "%s: instance is NULL", who);
     if (!table || !v0) return fail(QAA_ERR_INVALID_ARG, "%s: table or v0 is NULL", who);
@@ -1666,6 +1700,7 @@ extern "C" qaa_status qaa_spectrum(const qaa_instance *inst, const void *table, 
 // ---------------------------------------------------------------------------
 extern "C" qaa_status qaa_observables(const qaa_state *st, qaa_obs *out, void *stream)
 {
+    TraceRange trace_range("qaa_observables");
     if (!out) return fail(QAA_ERR_INVALID_ARG, "qaa_observables: out is NULL");
     qaa_status r = check_state_table(st, "qaa_observables");
     if (r != QAA_OK) return r;
@@ -1752,6 +1787,7 @@ extern "C" qaa_status qaa_plan_load(const char *path, int32_t *count)
 extern "C" qaa_status qaa_autotune(const qaa_state *scratch, int64_t steps, qaa_plan_choice *best,
                                    double *ms_per_step, void *stream)
 {
+    TraceRange trace_range("qaa_autotune");
     qaa_status r = check_state_table(scratch, "qaa_autotune", false);
     if (r != QAA_OK) return r;
     if (steps < 1) return fail(QAA_ERR_INVALID_ARG, "qaa_autotune: steps < 1");
@@ -1888,6 +1924,7 @@ extern "C" const char *qaa_status_str(qaa_status s)
     case QAA_ERR_DEVICE: return "device error";
     case QAA_ERR_NOT_READY: return "not ready";
     case QAA_ERR_INTERNAL: return "internal error";
+    case QAA_ERR_CANCELLED: return "cancelled";
     }
     return "unknown status";
 }

@@ -41,7 +41,8 @@ struct Request {
     int64_t steps = 0;
     int64_t steps_done = 0;      // steps the device has finished (updated per chunk)
     size_t footprint = 0;
-    int state = 0;               // 0 queued, 1 running, 2 done, 3 failed
+    int state = 0;               // 0 queued, 1 running, 2 done, 3 failed or cancelled
+    bool cancel = false;         // stop at the next chunk boundary
     qaa_status status = QAA_OK;
     std::string error;
     qaa_obs obs{};
@@ -88,7 +89,8 @@ int64_t chunk_steps(int32_t n)
 }
 
 // Run one solve on the worker's stream; returns a status and message.
-// progress(k) is called with the steps finished after each chunk.
+// progress(k) is called with the steps finished after each chunk and
+// returns false when the request has been cancelled.
 template <typename Progress>
 qaa_status solve(Request &rq, hipStream_t s, std::string &err, Progress &&progress)
 {
@@ -132,7 +134,10 @@ qaa_status solve(Request &rq, hipStream_t s, std::string &err, Progress &&progre
                     err = "stream synchronisation failed";
                     break;
                 }
-                progress(k1);
+                if (!progress(k1)) {
+                    st = QAA_ERR_CANCELLED;
+                    err = "cancelled";
+                }
             }
         }
         if (st == QAA_OK) st = qaa_observables(&state, &rq.obs, s);
@@ -171,7 +176,9 @@ void worker_main(qaa_server *sv)
         std::string err;
         auto progress = [&](int64_t k) {
             std::lock_guard<std::mutex> g(sv->mu);
-            sv->reqs[id].steps_done = k;
+            Request &r = sv->reqs[id];
+            r.steps_done = k;
+            return !r.cancel;
         };
         const qaa_status st = s ? solve(work, s, err, progress) : QAA_ERR_DEVICE;
         if (!s) err = "worker stream could not be created";
@@ -274,6 +281,33 @@ extern "C" qaa_status qaa_server_poll(qaa_server *sv, int64_t ticket, qaa_server
     auto it = sv->reqs.find(ticket);
     if (it == sv->reqs.end()) return qaa::set_error(QAA_ERR_INVALID_ARG, "qaa_server_poll: unknown ticket");
     fill_result(it->second, out);
+    return qaa::set_error(QAA_OK, nullptr);
+}
+
+extern "C" qaa_status qaa_server_cancel(qaa_server *sv, int64_t ticket)
+{
+    if (!sv) return qaa::set_error(QAA_ERR_INVALID_ARG, "qaa_server_cancel: NULL argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(ticket);
+    if (it == sv->reqs.end()) return qaa::set_error(QAA_ERR_INVALID_ARG, "qaa_server_cancel: unknown ticket");
+    Request &rq = it->second;
+    if (rq.state == 0) {
+        for (auto q = sv->queue.begin(); q != sv->queue.end(); ++q)
+            if (*q == ticket) {
+                sv->queue.erase(q);
+                break;
+            }
+        rq.state = 3;
+        rq.status = QAA_ERR_CANCELLED;
+        rq.error = "cancelled";
+        rq.t_start = rq.t_done = now_s();
+        std::vector<int32_t>().swap(rq.lits);
+        std::vector<double>().swap(rq.knots);
+        sv->cv_work.notify_all();     // the next request may be admissible now
+        sv->cv_done.notify_all();
+    } else if (rq.state == 1) {
+        rq.cancel = true;
+    }
     return qaa::set_error(QAA_OK, nullptr);
 }
 

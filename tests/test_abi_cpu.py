@@ -220,6 +220,12 @@ def test_one_hip_runtime_in_process():
     assert len(hip) == 1, hip
 
 
+def test_library_carries_roctx_ranges():
+    # API calls and pass launches are named for rocprofv3 --marker-trace
+    maps = open("/proc/self/maps").read()
+    assert "librocprofiler-sdk-roctx" in maps
+
+
 def _bp(choice):
     return {"balance": choice["balance"], "passengers": choice["passengers"]}
 

@@ -189,3 +189,38 @@ def test_server_reports_progress_of_chunked_solves(qaa):
     for key in ("norm", "energy", "p_success"):
         assert abs(r[key] - solo[key]) <= 1e-6 * max(1.0, abs(solo[key])), key
     assert r["e_min"] == solo["e_min"] and r["degeneracy"] == solo["degeneracy"]
+
+
+def test_server_cancels_queued_and_running_requests(qaa):
+    """One slot: a long solve runs, two more wait.  Cancelling a queued one
+    takes it out at once; cancelling the running one stops it at a chunk
+    boundary (2^11 steps at n = 24); the last one then runs to the end with
+    the same result as alone."""
+    long_lits = planted_unique_3sat(24, 150).literals()
+    small = planted_unique_3sat(14, 151)
+    sv = qaa.qaa_server_create(hbm_budget_bytes=1 << 30, slots=1)
+    try:
+        t_long = qaa.qaa_server_submit(sv, 24, long_lits, 3000.0, 300000)
+        t_q1 = qaa.qaa_server_submit(sv, 14, small.literals(), 4.0, 40)
+        t_q2 = qaa.qaa_server_submit(sv, 14, small.literals(), 4.0, 40)
+        while qaa.qaa_server_poll(sv, t_long)["steps_done"] == 0:
+            time.sleep(0.01)
+        qaa.qaa_server_cancel(sv, t_q1)
+        r1 = qaa.qaa_server_poll(sv, t_q1)
+        assert r1["done"] and r1["status"] == qaa.QAA_ERR_CANCELLED and r1["steps_done"] == 0
+        qaa.qaa_server_cancel(sv, t_long)
+        rl = qaa.qaa_server_wait(sv, t_long)
+        assert rl["status"] == qaa.QAA_ERR_CANCELLED
+        assert 0 < rl["steps_done"] < 300000 and rl["steps_done"] % 2048 == 0
+        r2 = qaa.qaa_server_wait(sv, t_q2)
+        assert r2["status"] == qaa.QAA_OK and r2["steps_done"] == 40
+        qaa.qaa_server_cancel(sv, t_q2)            # finished: unchanged
+        assert qaa.qaa_server_poll(sv, t_q2)["status"] == qaa.QAA_OK
+        with pytest.raises(qaa.QaaError) as ei:
+            qaa.qaa_server_cancel(sv, 10 ** 9)
+        assert ei.value.status == qaa.QAA_ERR_INVALID_ARG
+    finally:
+        qaa.qaa_server_destroy(sv)
+    solo = _solo(qaa, 14, small.literals(), 4.0, 40)
+    for key in ("norm", "energy", "p_success"):
+        assert r2[key] == solo[key], key
