@@ -40,7 +40,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "qaa_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# QAA_ORACLE_LIB: load another build of the C oracle (the sanitizer build of
+# tests/test_sanitizers.py) instead of oracle/liboracle.so.
+_LIB = os.environ.get("QAA_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
 

@@ -16,11 +16,13 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libqaa.so")
+# QAA_LIBRARY: load another build of the library (the sanitizer build of the
+# host code, paper_1103_1399_amd/sanitize_check.py) instead of the in-tree one.
+LIB_PATH = os.environ.get("QAA_LIBRARY") or os.path.join(_HERE, "libqaa.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        "libqaa.so is not built (expected at %s); run `python paper_1103_1399_amd/build.py`" % LIB_PATH)
+        "libqaa is not built (expected at %s); run `python paper_1103_1399_amd/build.py`" % LIB_PATH)
 
 # One HIP runtime per process.  PyTorch's ROCm wheels carry their own copies
 # of the HIP and HSA runtimes; when torch is loaded first, libqaa's runtime
