@@ -498,6 +498,22 @@ int default_tiles(int n, int dtype)
 }
 PlanChoice default_plan_choice(int sets) { return PlanChoice{sets == 2 ? 1 : 0, sets >= 3 ? 1 : 0, 0}; }
 
+// With three sets, how many of the highest qubits set 1 takes (0: none, the
+// top set takes them).  Set 1 then holds the lowest of the high qubits and
+// the `spread` highest ones, the top set the run between.  Measured on
+// complex64 (ms per step; set 1 takes 2..5 of the highest qubits): n = 30
+// 7.74 -> 7.52 / 7.62 / 7.33 / 7.54, n = 31 18.06 -> 21.97 / 17.57 / 16.88 /
+// 16.73 (the top set's tiles then gather runs from fewer, nearer rows, and
+// set 1's passes, which take the spread qubits, lose less than the top set's
+// gain); n = 28 and 29 within 1 % either way, so 4 from n = 30 on.
+// QAA_PLAN_SPREAD (a digit, read at every call) overrides it for every n.
+int plan_spread(int n, int dtype, int high_sets)
+{
+    if (const char *e = std::getenv("QAA_PLAN_SPREAD"))
+        return (e[0] >= '0' && e[0] <= '9') ? e[0] - '0' : 0;
+    return (dtype == 0 && n >= 30 && high_sets == 2) ? 4 : 0;
+}
+
 int env_knob(const char *name)
 {
     const char *e = std::getenv(name);
@@ -638,6 +654,17 @@ Plan make_plan(int n, int dtype, int etype, int tile_override = 0, PlanChoice *u
         std::vector<int> r;
         for (int q = b; q < b + sizes[j]; ++q) r.push_back(q);
         hi_sets.push_back(r);
+    }
+    const int spread = plan_spread(n, dtype, h);
+    if (h == 2 && spread > 0 && spread < sizes[0]) {
+        // set 1: the lowest sizes[0] - spread high qubits and the spread
+        // highest; the top set: the run of sizes[1] qubits between them
+        const int lo = tb0 + sizes[0] - spread;
+        hi_sets[0].clear();
+        hi_sets[1].clear();
+        for (int q = tb0; q < lo; ++q) hi_sets[0].push_back(q);
+        for (int q = lo; q < lo + sizes[1]; ++q) hi_sets[1].push_back(q);
+        for (int q = lo + sizes[1]; q < n; ++q) hi_sets[0].push_back(q);
     }
     const PlanChoice def = default_plan_choice(1 + h);
     const int balance = c.balance >= 0 ? c.balance : def.balance;

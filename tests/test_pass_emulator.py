@@ -165,6 +165,29 @@ def test_smaller_tile_plans_replay_the_oracle(n, dtype, tile_bits, sets, T, N):
     assert np.max(np.abs(got - ref)) < 1e-12
 
 
+@pytest.mark.parametrize("n,dtype,tile_bits,spread,T,N", [
+    (20, 0, 10, 2, 5.0, 2),     # 10 + (3 + 2) + 5: set 1 takes the 2 highest qubits
+    (20, 0, 10, 4, 4.0, 2),     # 10 + (1 + 4) + 5
+    (18, 0, 10, 1, 5.0, 3),     # 10 + (4 + 1) + 3 (ragged top set)
+    (17, 1, 9, 2, 5.0, 2),      # complex128: 9 + (3 + 2) + 3
+])
+def test_spread_plans_replay_the_oracle(n, dtype, tile_bits, spread, T, N, monkeypatch):
+    """Three-set plans whose set 1 takes the highest qubits and whose top set
+    takes the run between (the library's layout from n = 30 on), replayed
+    against the oracle."""
+    monkeypatch.setenv("QAA_PLAN_SPREAD", str(spread))
+    inst = planted_unique_3sat(n, 720 + n)
+    E = oracle.energy(n, inst.clauses).astype(np.int64)
+    psi = np.full(1 << n, 2.0 ** (-n / 2), np.complex128)
+    got, descs = _replay(n, dtype, E, psi, T, N, 0, N, tile_bits=tile_bits)
+    assert len({d.set_id for d in descs}) == 3
+    s1 = [d for d in descs if d.set_id == 1][0]
+    assert n - 1 in [s1.tile_pos[j] for j in range(s1.n - s1.n_rest)]     # set 1 holds the top qubit
+    ref = oracle.init_uniform(n)
+    oracle.evolve(n, inst.clauses, ref, T, N)
+    assert np.max(np.abs(got - ref)) < 1e-12
+
+
 @pytest.mark.parametrize("n,tile_bits,tiles,sets,T,N,passengers", [
     (22, 0, 1, 2, 5.0, 1, (0,)),        # the library's n = 22: 13 + 9, the top set in a 2^14 tile
     (18, 9, 1, 3, 5.0, 2, (0, 1)),      # 9 + 4 + 5: three sets, the top one wide (as n = 30)
