@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -1120,7 +1121,7 @@ struct ProfRec {
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
-std::vector<ProfRec> g_prof_live;     // recorded, not yet read
+std::deque<ProfRec> g_prof_live;      // recorded, not yet read (launch order)
 std::vector<hipEvent_t> g_prof_pool;  // free events
 int64_t g_prof_launches = 0;
 double g_prof_ms = 0.0, g_prof_min = 0.0, g_prof_max = 0.0, g_prof_bytes = 0.0;
@@ -1135,18 +1136,18 @@ hipError_t prof_event(hipEvent_t *e)
     return hipEventCreate(e);
 }
 
-// Collect finished records; with wait = false only those already complete.
+// Collect finished records, oldest first; with wait = false only up to the
+// first one still running (later launches on its stream cannot have
+// finished), so a drain costs one query per record collected plus one.
 hipError_t prof_drain(bool wait)
 {
-    size_t keep = 0;
-    for (size_t i = 0; i < g_prof_live.size(); ++i) {
-        ProfRec &r = g_prof_live[i];
+    while (!g_prof_live.empty()) {
+        ProfRec r = g_prof_live.front();
         if (wait) {
             hipError_t e = hipEventSynchronize(r.b);
             if (e != hipSuccess) return e;
         } else if (hipEventQuery(r.b) != hipSuccess) {
-            g_prof_live[keep++] = r;
-            continue;
+            break;
         }
         float ms = 0.f;
         hipError_t e = hipEventElapsedTime(&ms, r.a, r.b);
@@ -1158,8 +1159,8 @@ hipError_t prof_drain(bool wait)
         g_prof_bytes += r.bytes;
         g_prof_pool.push_back(r.a);
         g_prof_pool.push_back(r.b);
+        g_prof_live.pop_front();
     }
-    g_prof_live.resize(keep);
     return hipSuccess;
 }
 
