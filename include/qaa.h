@@ -516,9 +516,10 @@ qaa_status qaa_debug_pass_descs(int32_t n, qaa_dtype dtype, int32_t emax, const 
 
 /*
  * While enabled (on != 0), every pass-kernel launch made by the calling
- * process is bracketed by two HIP events recorded on the launch's own
- * stream.  Enabling adds one event pair per launch; it does not change
- * results.  Disabled by default.
+ * process carries a start and a stop HIP event on its own dispatch
+ * (hipExtLaunchKernel: the events time that kernel alone, with no event
+ * commands between launches).  Enabling adds one event pair per launch; it
+ * does not change results.  Disabled by default.
  */
 qaa_status qaa_profile_enable(int32_t on);
 

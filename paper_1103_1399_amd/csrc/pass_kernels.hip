@@ -4,6 +4,7 @@
 // launchers.  See PassDesc (qaa_internal.h) for the tile and residency
 // layout and kernel_common.h for the rotation arithmetic.
 #include "qaa_internal.h"
+#include <hip/hip_ext.h>
 #include "kernel_common.h"
 
 #include <algorithm>
@@ -564,7 +565,8 @@ inline int xcd_bit(const PassDesc &d, unsigned grid)
 }
 
 template <typename F, typename ET, int TB, int RB, bool PHASE, bool PIPE, bool RECOMP>
-hipError_t launch_pass_p(void *amp, const void *table, const PassDesc &d, hipStream_t s)
+hipError_t launch_pass_p(void *amp, const void *table, const PassDesc &d, hipStream_t s, hipEvent_t ev0,
+                         hipEvent_t ev1)
 {
     using F2 = typename V2<F>::T;
     constexpr int DT = sizeof(F) == 4 ? 0 : 1;
@@ -588,8 +590,15 @@ hipError_t launch_pass_p(void *amp, const void *table, const PassDesc &d, hipStr
     }();
     if (setup.err != hipSuccess) return setup.err;
     const unsigned grid = PIPE ? (unsigned)std::min<uint64_t>(d.tile_count, setup.resident) : (unsigned)d.tile_count;
-    hipLaunchKernelGGL((pass_kernel<F, ET, TB, RB, PHASE, PIPE, RECOMP>), dim3(grid), dim3(1u << (TB - RB)), lds, s,
-                       reinterpret_cast<F2 *>(amp), reinterpret_cast<const ET *>(table), d, xcd_bit(d, grid));
+    // profiling: the start and stop events ride on the dispatch itself
+    // (no separate event-record commands between the passes)
+    if (ev0)
+        hipExtLaunchKernelGGL((pass_kernel<F, ET, TB, RB, PHASE, PIPE, RECOMP>), dim3(grid), dim3(1u << (TB - RB)),
+                              (std::uint32_t)lds, s, ev0, ev1, 0u, reinterpret_cast<F2 *>(amp),
+                              reinterpret_cast<const ET *>(table), d, xcd_bit(d, grid));
+    else
+        hipLaunchKernelGGL((pass_kernel<F, ET, TB, RB, PHASE, PIPE, RECOMP>), dim3(grid), dim3(1u << (TB - RB)), lds,
+                           s, reinterpret_cast<F2 *>(amp), reinterpret_cast<const ET *>(table), d, xcd_bit(d, grid));
     return hipGetLastError();
 }
 
@@ -607,7 +616,8 @@ inline int pass_variant()
 }
 
 template <typename F, typename ET, int TB, int RB, bool PHASE>
-hipError_t launch_pass_v(void *amp, const void *table, const PassDesc &d, hipStream_t s)
+hipError_t launch_pass_v(void *amp, const void *table, const PassDesc &d, hipStream_t s, hipEvent_t ev0,
+                         hipEvent_t ev1)
 {
     // recompute mode (no table): passes with a phase score their tiles'
     // energies from the clause records
@@ -616,20 +626,21 @@ hipError_t launch_pass_v(void *amp, const void *table, const PassDesc &d, hipStr
             // (the persistent form would spill registers with 16-bit energies)
             const int v = pass_variant();
             if (sizeof(ET) == 2 || v == 0 || (v < 0 && !d.persist))
-                return launch_pass_p<F, ET, TB, RB, true, false, true>(amp, table, d, s);
-            if constexpr (sizeof(ET) == 1) return launch_pass_p<F, ET, TB, RB, true, true, true>(amp, table, d, s);
+                return launch_pass_p<F, ET, TB, RB, true, false, true>(amp, table, d, s, ev0, ev1);
+            if constexpr (sizeof(ET) == 1) return launch_pass_p<F, ET, TB, RB, true, true, true>(amp, table, d, s, ev0, ev1);
         }
     }
     const int v = pass_variant();
-    if (v == 0 || (v < 0 && !d.persist)) return launch_pass_p<F, ET, TB, RB, PHASE, false, false>(amp, table, d, s);
-    return launch_pass_p<F, ET, TB, RB, PHASE, true, false>(amp, table, d, s);
+    if (v == 0 || (v < 0 && !d.persist)) return launch_pass_p<F, ET, TB, RB, PHASE, false, false>(amp, table, d, s, ev0, ev1);
+    return launch_pass_p<F, ET, TB, RB, PHASE, true, false>(amp, table, d, s, ev0, ev1);
 }
 
 template <typename F, typename ET, int TB, int RB>
-hipError_t launch_pass_t(void *amp, const void *table, const PassDesc &d, hipStream_t s)
+hipError_t launch_pass_t(void *amp, const void *table, const PassDesc &d, hipStream_t s, hipEvent_t ev0,
+                         hipEvent_t ev1)
 {
-    if (d.phase_at >= 0) return launch_pass_v<F, ET, TB, RB, true>(amp, table, d, s);
-    return launch_pass_v<F, ET, TB, RB, false>(amp, table, d, s);
+    if (d.phase_at >= 0) return launch_pass_v<F, ET, TB, RB, true>(amp, table, d, s, ev0, ev1);
+    return launch_pass_v<F, ET, TB, RB, false>(amp, table, d, s, ev0, ev1);
 }
 
 }  // namespace
@@ -639,18 +650,18 @@ hipError_t launch_pass_t(void *amp, const void *table, const PassDesc &d, hipStr
 //               tile 2^14 = 16384 amps, 32 per thread, 512 threads (uint8 table)
 //   complex128: tile 2^12 = 4096 amps, 16 per thread, 256 threads
 hipError_t launch_pass(void *amp, int dtype, const void *table, int etype, int tile_bits, int reg_bits,
-                       const PassDesc &d, hipStream_t s)
+                       const PassDesc &d, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     // 2^14-amplitude tiles: complex64 with a uint8 table only (LDS)
     if (dtype == 0 && tile_bits == kWideTileBits && reg_bits == 5 && etype == 0)
-        return launch_pass_t<float, uint8_t, kWideTileBits, 5>(amp, table, d, s);
+        return launch_pass_t<float, uint8_t, kWideTileBits, 5>(amp, table, d, s, ev0, ev1);
     if (dtype == 0 && tile_bits == 13 && reg_bits == 5) {
-        if (etype == 0) return launch_pass_t<float, uint8_t, 13, 5>(amp, table, d, s);
-        return launch_pass_t<float, uint16_t, 13, 5>(amp, table, d, s);
+        if (etype == 0) return launch_pass_t<float, uint8_t, 13, 5>(amp, table, d, s, ev0, ev1);
+        return launch_pass_t<float, uint16_t, 13, 5>(amp, table, d, s, ev0, ev1);
     }
     if (dtype == 1 && tile_bits == 12 && reg_bits == 4) {
-        if (etype == 0) return launch_pass_t<double, uint8_t, 12, 4>(amp, table, d, s);
-        return launch_pass_t<double, uint16_t, 12, 4>(amp, table, d, s);
+        if (etype == 0) return launch_pass_t<double, uint8_t, 12, 4>(amp, table, d, s, ev0, ev1);
+        return launch_pass_t<double, uint16_t, 12, 4>(amp, table, d, s, ev0, ev1);
     }
     return hipErrorInvalidValue;
 }

@@ -1264,13 +1264,14 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, 
             QAA_HIP(prof_event(&rec.b));
             rec.bytes = dim * (double)d.tile_count / std::ldexp(1.0, d.n_rest) *
                         (2.0 * amp_bytes + (d.phase_at >= 0 && st->table ? e_bytes : 0.0));
-            QAA_HIP(hipEventRecord(rec.a, s));
         }
         hipError_t e;
         {
             TraceRange tr("qaa pass: set %d, phase at residency %d, tiles %lld+%lld", d.set_id, d.phase_at,
                           (long long)d.tile_begin, (long long)d.tile_count);
-            e = launch_pass(st->amp, (int)st->dtype, st->table, (int)st->etype, d.n - d.n_rest, p.reg_bits, d, s);
+            // profiling: the events are the dispatch's own start and stop
+            e = launch_pass(st->amp, (int)st->dtype, st->table, (int)st->etype, d.n - d.n_rest, p.reg_bits, d, s,
+                            prof ? rec.a : nullptr, prof ? rec.b : nullptr);
         }
         if (e != hipSuccess) {
             if (acc && own_acc) (void)hipFreeAsync(acc, s);
@@ -1278,7 +1279,6 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, 
         }
         if (prof) {
             std::lock_guard<std::mutex> lk(g_prof_mu);
-            QAA_HIP(hipEventRecord(rec.b, s));
             g_prof_live.push_back(rec);
         }
     }

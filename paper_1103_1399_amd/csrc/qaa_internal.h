@@ -204,8 +204,10 @@ hipError_t launch_count_equal(const void *table, int etype, int n, int value,
                               unsigned long long *count, hipStream_t s);
 hipError_t launch_init_uniform(void *amp, int dtype, int n, hipStream_t s);
 hipError_t launch_init_basis(void *amp, int dtype, int n, uint64_t z0, hipStream_t s);
+// ev0, ev1: when set, start and stop events of the pass's dispatch (profiling)
 hipError_t launch_pass(void *amp, int dtype, const void *table, int etype, int tile_bits,
-                       int reg_bits, const PassDesc &d, hipStream_t s);
+                       int reg_bits, const PassDesc &d, hipStream_t s, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr);
 hipError_t launch_zero_u64(unsigned long long *p, int count, hipStream_t s);
 // One lock-step pass (step s, sub-pass j) over a group of states with the
 // same number of qubit sets: workgroup b takes up to chunk_tiles tiles of
