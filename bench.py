@@ -59,7 +59,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
 PASS_KERNEL_SOURCES = ("paper_1103_1399_amd/csrc/pass_kernels.hip", "paper_1103_1399_amd/csrc/kernel_common.h",
                        "paper_1103_1399_amd/csrc/qaa_internal.h", "paper_1103_1399_amd/csrc/qaa_api.hip")
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "735ff6cdc780adff6dba3c3f23c294c1b37c14867f0e0fcffed9e2fc6170cef3",
+    "kernel_source_sha256": "bcaa858484f2a9e2e770fdd1df4e055ee041a04407d6b5e70040826589d97e39",
     "bytes_per_launch": 4.4342e+09,
 }
 

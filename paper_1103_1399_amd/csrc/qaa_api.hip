@@ -995,13 +995,14 @@ std::vector<PassDesc> build_passes(const Plan &p, int n, int dty, int emax, cons
     std::memset(&base, 0, sizeof base);
     base.n = n;
     base.emax = emax;
-    for (int64_t k = k0; k < k1; ++k) {
-        const bool fwd = ((k - k0) & 1) == 0;
-        const StepCoef ck = step_coef(T, N, k, sc);
-        for (int idx = 0; idx < r; ++idx) {
-            const int set = fwd ? idx : r - 1 - idx;
-            const bool first = idx == 0, last = idx == r - 1;
-            if (first && k > k0) continue;    // merged into the previous turn pass
+    // The index maps depend only on the set and the pass kind (first pass,
+    // turn, closing pass, rotations only): built once per (set, kind) and
+    // copied, with each pass's coefficients written into the copy.
+    std::vector<PassDesc> tmpl(4 * (size_t)r);
+    std::vector<char> have(4 * (size_t)r, 0);
+    auto templ = [&](int set, int kind) -> const PassDesc & {
+        const size_t key = 4 * (size_t)set + (size_t)kind;
+        if (!have[key]) {
             PassDesc d = base;
             const SetPlan &sp = p.sets[set];
             const int TB = sp.tb;
@@ -1017,14 +1018,33 @@ std::vector<PassDesc> build_passes(const Plan &p, int n, int dty, int emax, cons
             d.set_id = set;
             d.tile_begin = 0;
             d.tile_count = 1ull << nr;
+            static const bool rot_a[4] = {false, true, true, true}, phase[4] = {true, true, true, false},
+                              rot_b[4] = {true, true, false, false};
+            fill_residencies(d, sp, TB, RB, dty, rot_a[kind], phase[kind], rot_b[kind]);
+            tmpl[key] = d;
+            have[key] = 1;
+        }
+        return tmpl[key];
+    };
+    out.reserve((size_t)(k1 - k0) * (size_t)std::max(1, r - 1) + 1);
+    for (int64_t k = k0; k < k1; ++k) {
+        const bool fwd = ((k - k0) & 1) == 0;
+        const StepCoef ck = step_coef(T, N, k, sc);
+        for (int idx = 0; idx < r; ++idx) {
+            const int set = fwd ? idx : r - 1 - idx;
+            const bool first = idx == 0, last = idx == r - 1;
+            if (first && k > k0) continue;    // merged into the previous turn pass
             if (first) {
                 // k == k0: half phase of step k0, then this set's rotations
+                out.push_back(templ(set, 0));
+                PassDesc &d = out.back();
                 d.phi = 0.5 * dt * ck.s;
                 d.gphase = 0.0;
                 d.tB = ck.t;
                 d.sB = ck.sn;
-                fill_residencies(d, sp, TB, RB, dty, false, true, true);
             } else if (last && k + 1 < k1) {
+                out.push_back(templ(set, 1));
+                PassDesc &d = out.back();
                 const StepCoef cn = step_coef(T, N, k + 1, sc);
                 d.tA = ck.t;
                 d.sA = ck.sn;
@@ -1032,19 +1052,19 @@ std::vector<PassDesc> build_passes(const Plan &p, int n, int dty, int emax, cons
                 d.gphase = step_gphase(n, ck);
                 d.tB = cn.t;
                 d.sB = cn.sn;
-                fill_residencies(d, sp, TB, RB, dty, true, true, true);
             } else if (last) {
+                out.push_back(templ(set, 2));
+                PassDesc &d = out.back();
                 d.tA = ck.t;
                 d.sA = ck.sn;
                 d.phi = 0.5 * dt * ck.s;
                 d.gphase = step_gphase(n, ck);
-                fill_residencies(d, sp, TB, RB, dty, true, true, false);
             } else {
+                out.push_back(templ(set, 3));
+                PassDesc &d = out.back();
                 d.tA = ck.t;
                 d.sA = ck.sn;
-                fill_residencies(d, sp, TB, RB, dty, true, false, false);
             }
-            out.push_back(d);
         }
     }
     return out;
@@ -1167,7 +1187,9 @@ hipError_t prof_drain(bool wait)
 std::vector<PassDesc> plan_passes(const Plan &p, int n, int dty, int emax, const SchedKnots &sc, double T,
                                   int64_t N, int64_t k0, int64_t k1)
 {
-    return schedule_passes(build_passes(p, n, dty, emax, sc, T, N, k0, k1), p, n, dty == 0 ? 3 : 4);
+    std::vector<PassDesc> v = build_passes(p, n, dty, emax, sc, T, N, k0, k1);
+    if (chunk_log2_bytes() <= 0) return v;
+    return schedule_passes(v, p, n, dty == 0 ? 3 : 4);
 }
 
 // Norm control (see PassDesc) is on unless QAA_NORM_CONTROL=0 is set in
@@ -1187,8 +1209,7 @@ bool norm_control_enabled()
 qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, double T, int64_t N, int64_t k0,
                       int64_t k1, hipStream_t s, unsigned long long *fixed_acc)
 {
-    const std::vector<PassDesc> ps =
-        plan_passes(p, st->inst->n, (int)st->dtype, st->inst->e_max, sc, T, N, k0, k1);
+    std::vector<PassDesc> ps = plan_passes(p, st->inst->n, (int)st->dtype, st->inst->e_max, sc, T, N, k0, k1);
     ClauseRec *recs = nullptr;       // recompute mode: passes with a phase score their tiles
     if (!st->table) {
         qaa_status rc = device_clauses(const_cast<qaa_instance *>(st->inst), &recs, "evolve");
@@ -1221,7 +1242,7 @@ qaa_status run_passes(const qaa_state *st, const Plan &p, const SchedKnots &sc, 
     // and start on data still in the last-level cache.
     bool prev_low = false, prev_rev = false;
     bool reduce_next = false;   // the previous pass measured the norm
-    for (PassDesc d : ps) {
+    for (PassDesc &d : ps) {
         d.clauses = recs;
         d.m = st->inst->m;
         const bool full = d.tile_begin == 0 && d.tile_count == (1ull << d.n_rest);
