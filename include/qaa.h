@@ -215,6 +215,16 @@ typedef struct qaa_schedule {
  * T, a bad schedule, or a state without amp/table/inst.
  * QAA_ERR_UNSUPPORTED if the instance's E_max exceeds what the table type
  * allows.  Asynchronous.
+ *
+ * The state must have unit norm (as qaa_state_init_uniform / _basis leave
+ * it; the evolution is unitary).  Norm control keeps it there against FP32
+ * rounding: every measuring pass sums |psi|^2 as a 2^-60 fixed-point
+ * integer, and the next one divides by the square root of what the
+ * previous one measured -- so a state of another norm is rescaled to 1 as
+ * it evolves (a multi-pass state of norm^2 >= 16 would overflow the
+ * accumulator), and the norm that qaa_observables reports stays within
+ * rounding of 1 rather than measuring the integration error.  States held
+ * in one workgroup (n <= 13) are renormalised exactly once per 32 steps.
  */
 qaa_status qaa_evolve(const qaa_state *st, const qaa_schedule *sched, double T,
                       int64_t steps, void *stream);
