@@ -166,16 +166,24 @@ __device__ __forceinline__ void pass_load(TileRegs<F, ET, TB, RB> &tr, const typ
     }
 }
 
-// Clause records a recompute-mode workgroup keeps in LDS at a time.
+// LDS a recompute-mode workgroup gives its clause records: kPassClauses
+// 16-byte slots, the last one holding the survivor counter.
 constexpr int kPassClauses = 128;
 
 // The energies of the tile at `base` into etile, recomputed from the clause
 // records: thread tid scores the RUN consecutive tile-local indices
 // tid*RUN .. tid*RUN + RUN - 1 (RUN = 32 for complex64, 16 for complex128:
 // the tile's passenger bits), which are consecutive basis states z because
-// the low tile bits are the low physical bits in every plan.  Clause
-// records come from cls in LDS (staged once per launch when m fits, else
-// in chunks here).
+// the low tile bits are the low physical bits in every plan.
+//
+// Only clauses that some z of the tile violates are scored: the qubits
+// outside the tile are fixed for the whole tile (its base), so a clause
+// whose literal on such a qubit is satisfied there adds nothing to any
+// count of the tile.  The records are read from the instance's list,
+// kPassClauses - 1 at a time; the survivors of each batch go to cls (in
+// whatever order the LDS atomic gives them: the counts do not depend on
+// it) and are scored.  With 13 of 28 qubits in a tile, a random clause
+// survives with probability (1 - 15/56)^3 = 0.39.
 template <typename F, typename ET, int TB, int RB>
 __device__ __forceinline__ void tile_energies(const PassDesc &d, uint64_t base, uint32_t tid, ET *etile,
                                               ClauseRec *cls)
@@ -184,26 +192,32 @@ __device__ __forceinline__ void tile_energies(const PassDesc &d, uint64_t base, 
     constexpr int RUN = (int)(P::TS / P::WG);
     constexpr int LRUN = RUN == 32 ? 5 : 4;
     static_assert(RUN == (1 << LRUN), "one run of consecutive z per thread");
+    static_assert((int)P::WG >= kPassClauses - 1, "one clause record per thread and batch");
     constexpr int K = sizeof(ET) == 1 ? 8 : 16;      // E <= 255 with a uint8 width, else <= 1023
+    constexpr int kBatch = kPassClauses - 1;
     const uint32_t l0 = tid * (uint32_t)RUN;
     uint64_t off = 0;
 #pragma unroll
     for (int j = LRUN; j < TB; ++j) off |= (uint64_t)((l0 >> j) & 1u) << d.tile_pos[j];
     const uint64_t z0 = base | off;
     const uint32_t t = (uint32_t)(z0 >> 5), lane0 = (uint32_t)(z0 & 31u);
+    // index bits 5.. of z that stay fixed over the tile, and their values
+    const uint32_t out_t = (uint32_t)(d.rest_mask >> 5), base_t = (uint32_t)(base >> 5);
+    unsigned int *count = reinterpret_cast<unsigned int *>(cls + kBatch);
     BitCounter<K> bc;
     bc.clear();
     const int m = d.m;
-    if (m <= kPassClauses) {
-        score_clauses<K>(bc, cls, m, t);
-    } else {
-        for (int c0 = 0; c0 < m; c0 += kPassClauses) {
-            const int cm = min(kPassClauses, m - c0);
-            lds_barrier();
-            for (int i = (int)tid; i < cm; i += (int)P::WG) cls[i] = d.clauses[c0 + i];
-            lds_barrier();
-            score_clauses<K>(bc, cls, cm, t);
+    for (int c0 = 0; c0 < m; c0 += kBatch) {
+        lds_barrier();                       // the previous batch is scored
+        if (tid == 0) *count = 0u;
+        lds_barrier();
+        const int c = c0 + (int)tid;
+        if ((int)tid < kBatch && c < m) {
+            const ClauseRec r = d.clauses[c];
+            if (((base_t ^ r.phi) & r.mhi & out_t) == 0u) cls[atomicAdd(count, 1u)] = r;
         }
+        lds_barrier();
+        score_clauses<K>(bc, cls, (int)*count, t);
     }
 #pragma unroll
     for (int i = 0; i < RUN; ++i) etile[l0 + i] = (ET)count_of<K>(bc, lane0 + (uint32_t)i);
@@ -383,12 +397,6 @@ __device__ __forceinline__ unsigned long long tile_loop(typename V2<F>::T *__res
     ClauseRec *cls = reinterpret_cast<ClauseRec *>(etile + P::TS);     // recompute mode only
 
     const uint32_t tid = threadIdx.x;
-    if constexpr (PHASE && RECOMP) {
-        // clause records staged once for every tile of this launch (the
-        // first residency's barrier orders them before their first use)
-        if (d.m <= kPassClauses)
-            for (int i = (int)tid; i < d.m; i += (int)P::WG) cls[i] = d.clauses[i];
-    }
     uint64_t tg_first = 0, tg_last = 0;
 #pragma unroll
     for (int k = 0; k < P::WB; ++k) {
