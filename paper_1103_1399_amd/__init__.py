@@ -371,6 +371,7 @@ class PassDesc(ctypes.Structure):
                 ("acc_in", ctypes.c_void_p), ("acc_out", ctypes.c_void_p), ("acc_zero", ctypes.c_void_p),
                 ("red_src", ctypes.c_void_p), ("red_dst", ctypes.c_void_p),
                 ("clauses", ctypes.c_void_p), ("m", ctypes.c_int32), ("xcd_map", ctypes.c_int32),
+                ("reg_bits", ctypes.c_int32), ("pad_", ctypes.c_int32),
                 ("goff_first", ctypes.c_uint64 * 32), ("goff_last", ctypes.c_uint64 * 32),
                 ("ljp", (ctypes.c_uint16 * 32) * 12), ("lj", (ctypes.c_uint16 * 32) * 12),
                 ("rest_mask", ctypes.c_uint64),

@@ -667,6 +667,10 @@ hipError_t launch_pass(void *amp, int dtype, const void *table, int etype, int t
         if (etype == 0) return launch_pass_t<float, uint8_t, 13, 5>(amp, table, d, s, ev0, ev1);
         return launch_pass_t<float, uint16_t, 13, 5>(amp, table, d, s, ev0, ev1);
     }
+    if (dtype == 0 && tile_bits == 13 && reg_bits == kSmallPlanRegBits) {
+        if (etype == 0) return launch_pass_t<float, uint8_t, 13, kSmallPlanRegBits>(amp, table, d, s, ev0, ev1);
+        return launch_pass_t<float, uint16_t, 13, kSmallPlanRegBits>(amp, table, d, s, ev0, ev1);
+    }
     if (dtype == 1 && tile_bits == 12 && reg_bits == 4) {
         if (etype == 0) return launch_pass_t<double, uint8_t, 12, 4>(amp, table, d, s, ev0, ev1);
         return launch_pass_t<double, uint16_t, 12, 4>(amp, table, d, s, ev0, ev1);
@@ -702,6 +706,13 @@ hipError_t launch_batch_pass(const BatchInst *insts, const uint32_t *chunk_inst,
         if (etype == 0)
             return launch_batch_t<float, uint8_t, 13, 5>(insts, chunk_inst, chunks, structs, s, j, chunk_tiles, st);
         return launch_batch_t<float, uint16_t, 13, 5>(insts, chunk_inst, chunks, structs, s, j, chunk_tiles, st);
+    }
+    if (dtype == 0 && tile_bits == 13 && reg_bits == kSmallPlanRegBits) {
+        if (etype == 0)
+            return launch_batch_t<float, uint8_t, 13, kSmallPlanRegBits>(insts, chunk_inst, chunks, structs, s, j,
+                                                                          chunk_tiles, st);
+        return launch_batch_t<float, uint16_t, 13, kSmallPlanRegBits>(insts, chunk_inst, chunks, structs, s, j,
+                                                                       chunk_tiles, st);
     }
     if (dtype == 1 && tile_bits == 12 && reg_bits == 4) {
         if (etype == 0)

@@ -672,7 +672,11 @@ Plan make_plan(int n, int dtype, int etype, int tile_override = 0, PlanChoice *u
     const int passengers = c.passengers >= 0 ? c.passengers : def.passengers;
     if (used) *used = PlanChoice{balance, passengers, tiles};
     p.tile_bits = tb0;
-    p.reg_bits = kPassRegBits[dtype];
+    // two sets of 2^13-amplitude tiles (complex64, n = 14..21): 4 register
+    // bits, 512 threads per tile (n = 18: 14.9 -> 12.9 us per pass, n = 20:
+    // 17.1 -> 15.9 us); replays with smaller tiles keep 5
+    p.reg_bits = (dtype == 0 && h == 1 && tb0 == kPassTileBits[0] && tb_top == tb0) ? kSmallPlanRegBits
+                                                                                     : kPassRegBits[dtype];
     // The top set takes set 0's highest qubits until it rotates q_top of
     // them (set 0 keeps at least the passenger bits, which only it
     // rotates): the turn passes over set 0 and over the top set then rotate
@@ -1016,6 +1020,7 @@ std::vector<PassDesc> build_passes(const Plan &p, int n, int dty, int emax, cons
                 }
             d.n_rest = nr;
             d.set_id = set;
+            d.reg_bits = RB;
             d.tile_begin = 0;
             d.tile_count = 1ull << nr;
             static const bool rot_a[4] = {false, true, true, true}, phase[4] = {true, true, true, false},
@@ -1515,23 +1520,22 @@ qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states
     // kernel variant for all of them.  Each state has a chunk table entry
     // per tile variant its sets use (base [0], wide [1]).
     struct GroupPlan {
-        int r = 0;
+        int r = 0, rb = 0;                        // qubit sets, register bits
         std::vector<int> tbs;                     // tile bits per set
         std::vector<int> order;                   // state indices, longest first
         size_t inst_base = 0, chunk_base[2] = {0, 0};
         std::vector<uint64_t> chunk_prefix[2];    // chunks of the first q states, per variant
     };
     std::map<std::vector<int>, GroupPlan> groups;
-    int RB = 0;
     for (int i : idx) {
         const Plan p = make_plan(states[i].inst->n, dty, ety);
-        std::vector<int> key{(int)p.sets.size()};
+        std::vector<int> key{p.reg_bits, (int)p.sets.size()};
         for (const SetPlan &sp : p.sets) key.push_back(sp.tb);
         GroupPlan &g = groups[key];
+        g.rb = p.reg_bits;
         g.r = (int)p.sets.size();
-        g.tbs.assign(key.begin() + 1, key.end());
+        g.tbs.assign(key.begin() + 2, key.end());
         g.order.push_back(i);
-        RB = p.reg_bits;
     }
     std::vector<PassDesc> structs;
     std::map<int, int> base_of_n;
@@ -1620,7 +1624,7 @@ qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states
                 const int tb = g.tbs[set];
                 const int v = tb == kWideTileBits ? 1 : 0;
                 hipError_t e = launch_batch_pass(d_insts + g.inst_base, d_chunks[v] + g.chunk_base[v],
-                                                 g.chunk_prefix[v][a], d_structs, k, j, chunk_tiles, dty, ety, tb, RB,
+                                                 g.chunk_prefix[v][a], d_structs, k, j, chunk_tiles, dty, ety, tb, g.rb,
                                                  s);
                 if (e != hipSuccess) {
                     release();

@@ -125,6 +125,8 @@ struct PassDesc {
     const ClauseRec *clauses;          // recompute mode (no energy table): the clause records
     int32_t m;                         //   and their number
     int32_t xcd_map;                   // grid slots by XCD: 0 plain, 1 top bits, 2 + k tile bit k
+    int32_t reg_bits;                  // register bits per thread the pass was planned for
+    int32_t pad_;
     uint64_t goff_first[kMaxRegs];     // residency 0: global offset of register j
     uint64_t goff_last[kMaxRegs];      // last residency: global offset of register j
     uint16_t ljp[kMaxRes][kMaxRegs];   // residency r: padded LDS offset of register j
@@ -243,6 +245,10 @@ constexpr int kPassTileBits[2] = {13, 12};
 // threads x 32 registers, one workgroup per CU (154 KiB of LDS).
 constexpr int kWideTileBits = 14;
 constexpr int kPassRegBits[2] = {5, 4};
+// Complex64 plans of two sets in 2^13-amplitude tiles (n = 14..21) use 4
+// register bits: 512 threads per tile of 16 amplitudes each, so that the
+// few workgroups of a small state (8..256) finish their tiles sooner.
+constexpr int kSmallPlanRegBits = 4;
 // Low physical bits every high-qubit tile carries so that each global access
 // is a contiguous 256-byte run (32 complex64 / 16 complex128).
 constexpr int kPassengerBits[2] = {5, 4};

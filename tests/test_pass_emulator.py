@@ -35,9 +35,12 @@ def _replay(n, dtype, E, psi, T, N, k0, k1, knots=None, tile_bits=0, any_tile=Fa
     descs = qaa.qaa_debug_pass_descs(n, dtype, int(E.max()), T, N, k0, k1, knots, tile_bits=tile_bits)
     if not descs:
         return psi, descs
-    RB = 5 if dtype == qaa.QAA_C64 else 4
-    R = 1 << RB
     for d in descs:
+        # register bits per thread the pass was planned for (complex64
+        # two-set plans in 2^13 tiles use 4, other complex64 plans 5)
+        RB = d.reg_bits
+        assert RB == (5 if dtype == qaa.QAA_C64 else 4) or (dtype == qaa.QAA_C64 and RB == 4)
+        R = 1 << RB
         # each pass's tile size (sets may differ: 2^14-amplitude top sets)
         TB = n - d.n_rest
         if tile_bits and not any_tile:
