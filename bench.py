@@ -59,8 +59,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
 PASS_KERNEL_SOURCES = ("paper_1103_1399_amd/csrc/pass_kernels.hip", "paper_1103_1399_amd/csrc/kernel_common.h",
                        "paper_1103_1399_amd/csrc/qaa_internal.h", "paper_1103_1399_amd/csrc/qaa_api.hip")
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "af33f2dfcf45b79918114af566a99e11ecaf548c5ca9e22b8d6ec275be82504d",
-    "bytes_per_launch": 4.4342e+09,
+    "kernel_source_sha256": "f671949bfb353a4becf8ec2d7ce5fdb34e86511c1cdbc37b25074f37a0dc9bd9",
+    "bytes_per_launch": 4.4343e+09,
 }
 
 
