@@ -444,6 +444,12 @@ qaa_status qaa_plan_info(int32_t n, qaa_dtype dtype, int32_t *tile_bits, int32_t
  *                Tiles 1 and 2 apply to complex64 states with a uint8 table
  *                and n >= 22 only (elsewhere the base tile is used whatever
  *                is recorded).
+ * Beyond the choice, two things follow from the plan's shape: complex64
+ * plans of two sets in 2^13-amplitude tiles (n = 14..21) run 512 threads
+ * of 16 amplitudes per tile instead of 256 of 32, and three-set complex64
+ * plans from n = 30 on give set 1 the four highest qubits as well as the
+ * lowest high ones, the top set taking the run between them
+ * (QAA_PLAN_SPREAD = a digit sets that count for every n; 0 turns it off).
  * Results do not depend on the choice beyond FP32 rounding order.  The
  * choice is process-wide per (n, dtype); the environment variables
  * QAA_PLAN_BALANCE / QAA_PLAN_PASSENGERS (0 or 1) and QAA_PLAN_TILES
