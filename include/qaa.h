@@ -398,7 +398,8 @@ qaa_status qaa_server_poll(qaa_server *sv, int64_t ticket, qaa_server_result *ou
  * finishes with status QAA_ERR_CANCELLED.  Running: the solve stops at its
  * next chunk boundary (see above; the device finishes the chunk in flight),
  * frees its buffers and finishes with QAA_ERR_CANCELLED, steps_done
- * telling how far it got.  Already finished: nothing changes.  Either way
+ * telling how far it got; a solve already in its last chunk (at small n,
+ * the whole solve is one chunk) runs to its end and finishes normally.  Already finished: nothing changes.  Either way
  * the call returns QAA_OK without waiting; QAA_ERR_INVALID_ARG for a NULL
  * server or an unknown ticket. */
 qaa_status qaa_server_cancel(qaa_server *sv, int64_t ticket);
