@@ -272,7 +272,13 @@ qaa_status qaa_evolve_range_noalloc(const qaa_state *st, const qaa_schedule *sch
  * equals what qaa_evolve gives for that state alone up to FP32 rounding
  * (same pass plan per n).  The call waits for the descriptor uploads (and
  * so for work already queued on the stream); the evolution itself is
- * asynchronous on the stream.
+ * asynchronous on the stream.  Internally the small states, and the launch
+ * groups after the first (states sharing a number of qubit sets and tile
+ * sizes), run on library-owned streams of the device, forked from `stream`
+ * and joined back into it: work queued on `stream` after the call waits
+ * for all of them.  QAA_BATCH_STREAMS (0..2, default 1) sets how many
+ * streams the launch groups after the first spread over; 0 keeps every
+ * group on `stream` (results are the same either way).
  */
 qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, const qaa_schedule *scheds,
                             const double *T, const int64_t *steps, void *stream);

@@ -97,6 +97,10 @@ struct DeviceCtx {
     std::mutex mu;                          // enqueueing on `side`
     bool ready = false;
     hipStream_t side = nullptr;             // second stream for batched small states
+    // streams for the second and later launch groups of a batch (see
+    // run_batch_passes); created on first use, default priority
+    std::mutex group_mu;
+    std::vector<hipStream_t> group;
 };
 
 std::mutex g_dev_mu;
@@ -1509,8 +1513,33 @@ int batch_chunk_tiles()
     return v;
 }
 
+// Extra streams for a batch's launch groups: QAA_BATCH_STREAMS (0..2, read
+// once), else 1.  0 runs every group on the caller's stream.
+int batch_group_streams()
+{
+    static const int v = [] {
+        const char *e = std::getenv("QAA_BATCH_STREAMS");
+        const int x = e ? std::atoi(e) : 1;
+        return x >= 0 && x <= 2 ? x : 1;
+    }();
+    return v;
+}
+
+// The first `want` group streams of the device (created on first use).
+qaa_status group_streams(DeviceCtx *ctx, int want, std::vector<hipStream_t> *out)
+{
+    std::lock_guard<std::mutex> lk(ctx->group_mu);
+    while ((int)ctx->group.size() < want) {
+        hipStream_t st = nullptr;
+        QAA_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        ctx->group.push_back(st);
+    }
+    out->assign(ctx->group.begin(), ctx->group.begin() + want);
+    return QAA_OK;
+}
+
 qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states, const SchedKnots *scs,
-                            const double *T, const int64_t *steps, hipStream_t s)
+                            const double *T, const int64_t *steps, hipStream_t s, DeviceCtx *ctx)
 {
     if (idx.empty()) return QAA_OK;
     const int dty = (int)states[idx[0]].dtype, ety = (int)states[idx[0]].etype;
@@ -1608,11 +1637,65 @@ qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states
         release();
         return r;
     }
+    // Launch groups share no state, so each may run on a stream of its own:
+    // the first on the caller's stream, the others on the device's group
+    // streams, forked after the uploads and joined back before the buffers
+    // are released.  A group's launches each drain before the next of that
+    // group starts; on separate streams the device fills one group's
+    // ragged last round of workgroups with another group's work.  (Calls
+    // from several threads may share the group streams: their launches then
+    // also wait for each other, in enqueue order, which only serialises.)
+    std::vector<hipStream_t> gs;
+    const int extra = std::min<int>(batch_group_streams(), (int)groups.size() - 1);
+    if (extra > 0) {
+        r = group_streams(ctx, extra, &gs);
+        if (r != QAA_OK) {
+            release();
+            return r;
+        }
+    }
+    std::vector<hipEvent_t> evs(gs.size(), nullptr);
+    auto free_events = [&]() {
+        for (hipEvent_t &e : evs)
+            if (e) (void)hipEventDestroy(e);
+    };
+    for (size_t i = 0; i < gs.size(); ++i) {
+        hipError_t e = hipEventCreateWithFlags(&evs[i], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(evs[i], s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(gs[i], evs[i], 0);
+        if (e != hipSuccess) {
+            // the group streams forked so far hold no work of this call yet
+            free_events();
+            release();
+            return fail(QAA_ERR_DEVICE, "batched passes: fork failed: %s", hipGetErrorString(e));
+        }
+    }
+    // every group stream's work of this call is ordered before the caller's
+    // stream continues (and before the buffers go back), on every path
+    auto join = [&]() {
+        hipError_t first = hipSuccess;
+        for (size_t i = 0; i < gs.size(); ++i) {
+            hipError_t e = hipEventRecord(evs[i], gs[i]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, evs[i], 0);
+            if (e != hipSuccess && first == hipSuccess) first = e;
+        }
+        free_events();
+        return first;
+    };
     std::map<std::vector<int>, int> active;
-    for (auto &kv : groups) active[kv.first] = (int)kv.second.order.size();
+    std::map<std::vector<int>, hipStream_t> stream_of;
+    {
+        int gi = 0;
+        for (auto &kv : groups) {
+            active[kv.first] = (int)kv.second.order.size();
+            stream_of[kv.first] = gi == 0 || gs.empty() ? s : gs[(gi - 1) % gs.size()];
+            ++gi;
+        }
+    }
     for (int64_t k = 0; k < maxN; ++k) {
         for (auto &kv : groups) {
             const GroupPlan &g = kv.second;
+            const hipStream_t gst = stream_of[kv.first];
             int &a = active[kv.first];
             while (a > 0 && insts[g.inst_base + a - 1].N <= k) --a;
             if (a == 0) continue;
@@ -1625,15 +1708,18 @@ qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states
                 const int v = tb == kWideTileBits ? 1 : 0;
                 hipError_t e = launch_batch_pass(d_insts + g.inst_base, d_chunks[v] + g.chunk_base[v],
                                                  g.chunk_prefix[v][a], d_structs, k, j, chunk_tiles, dty, ety, tb, g.rb,
-                                                 s);
+                                                 gst);
                 if (e != hipSuccess) {
+                    (void)join();
                     release();
                     return fail(QAA_ERR_DEVICE, "batched pass launch failed: %s", hipGetErrorString(e));
                 }
             }
         }
     }
+    const hipError_t je = join();
     release();
+    if (je != hipSuccess) return fail(QAA_ERR_DEVICE, "batched passes: join failed: %s", hipGetErrorString(je));
     return QAA_OK;
 }
 
@@ -1710,7 +1796,7 @@ extern "C" qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, c
     if (r == QAA_OK && he != hipSuccess)
         r = fail(QAA_ERR_DEVICE, "qaa_evolve_batch: resident launch failed: %s", hipGetErrorString(he));
     for (int dt = 0; dt < 2 && r == QAA_OK; ++dt)
-        for (int et = 0; et < 2 && r == QAA_OK; ++et) r = run_batch_passes(large[dt][et], states, scs.data(), T, steps, s);
+        for (int et = 0; et < 2 && r == QAA_OK; ++et) r = run_batch_passes(large[dt][et], states, scs.data(), T, steps, s, ctx);
     // the caller's stream waits for the side stream's work of this call on
     // every path, so none of it outlives the caller's stream unordered
     he = joined ? hipStreamWaitEvent(s, join, 0) : hipErrorUnknown;

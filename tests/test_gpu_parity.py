@@ -397,6 +397,32 @@ def test_batch_equals_individual(qaa):
             _compare(b, b.observables(), psi, ref, L2_TOL_C64, P_TOL_C64)
 
 
+def test_batch_groups_join_the_callers_stream(qaa):
+    """Launch groups after the first run on library streams that are joined
+    back into the caller's stream: work queued on that stream right after
+    the call (no device synchronisation) sees every state finished."""
+    ns, Ts, Ns = [20, 22], [1.0, 4.0], [4, 300]      # the n = 22 group runs long
+    insts, batch, tables = [], [], []
+    for i, n in enumerate(ns):
+        inst = qaa.Instance(n, planted_unique_3sat(n, 500 + i).literals())
+        table = inst.energy_table()
+        insts.append(inst)
+        tables.append(table)
+        batch.append(qaa.State(inst, table).init_uniform())
+    solo = qaa.State(insts[1], tables[1]).init_uniform().evolve(Ts[1], Ns[1])
+    torch.cuda.synchronize()
+    caller = torch.cuda.Stream()
+    caller.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(caller):
+        qaa.qaa_evolve_batch([b.c for b in batch], Ts, Ns, stream=caller)
+        snaps = [b.amp.clone() for b in batch]
+    torch.cuda.synchronize()
+    for snap, b in zip(snaps, batch):
+        assert torch.equal(snap, b.amp)
+    diff = float(torch.linalg.vector_norm((solo.amp - batch[1].amp).to(torch.complex128)).item())
+    assert diff < 2e-6, diff
+
+
 def test_batch_many_uneven_states_vs_oracle(qaa):
     """A batch drawn like the batched workload (n uniform, T uniform,
     steps = round(T/dt)), shortened: 40 states, n in 12..17, T in [1, 3)."""
