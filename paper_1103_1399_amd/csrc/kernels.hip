@@ -194,6 +194,49 @@ __global__ void __launch_bounds__(256) init_basis_kernel(typename V2<F>::T *__re
 // ---------------------------------------------------------------------------
 constexpr int kResChunk = 32;
 
+// Phase angle phi_k, global phase and rotation coefficients (rt, rs) of
+// step k of a range that opens at k0: the half phase that opens the range
+// (k == k0), else the merged halves of k-1 and k with step k-1's driver
+// global phase.
+__device__ __forceinline__ void res_step_terms(const double *knots, int kcount, int64_t k, int64_t k0, int64_t N,
+                                               double dt, int n, double &phi, double &gph, double &rt, double &rs)
+{
+    const double sk = sched_mid(knots, kcount, k, N);
+    bool flip;
+    rot_params(dt * (1.0 - sk), rt, rs, flip);
+    if (k == k0) {
+        phi = 0.5 * dt * sk;
+        gph = 0.0;
+    } else {
+        const double sp = sched_mid(knots, kcount, k - 1, N);
+        const double thp = dt * (1.0 - sp);
+        double tp, sq;
+        bool fp;
+        rot_params(thp, tp, sq, fp);
+        phi = 0.5 * dt * (sp + sk);
+        gph = step_gphase(n, thp, fp);
+    }
+}
+
+// Rows [0, rows) of a chunk's phase table, row j entry e =
+// exp(-i (phi_j e + gph_j)) in FP64 rounded once; row 0 carries the norm
+// correction scale0.  Threads tid = 0..nthr-1 share the entries.
+template <typename F2, typename F>
+__device__ __forceinline__ void res_build_rows(F2 *ring, const double *phi_s, const double *gph_s, int rows,
+                                               int width, double scale0, int tid, int nthr)
+{
+    for (int x = tid; x < rows * width; x += nthr) {
+        const int j = x / width, e = x - j * width;
+        double sn, cs;
+        sincos(fma(phi_s[j], (double)e, gph_s[j]), &sn, &cs);
+        const double sc = j == 0 ? scale0 : 1.0;
+        F2 L;
+        L.x = (F)(sc * cs);
+        L.y = (F)(-sc * sn);
+        ring[x] = L;
+    }
+}
+
 template <typename F, typename ET, int RB, int WB, int RING>
 __device__ __forceinline__ void resident_body(const ResidentDesc &d)
 {
@@ -277,39 +320,11 @@ __device__ __forceinline__ void resident_body(const ResidentDesc &d)
         __syncthreads();      // red is rewritten by the next measure
         return total;
     };
-    // phase angle phi_k, global phase and rotation of step k: the half phase
-    // that opens the range (k == k0), else the merged halves of k-1 and k
-    // with step k-1's driver global phase
     auto step_terms = [&](int64_t k, double &phi, double &gph, double &rt, double &rs) {
-        const double sk = sched_mid(knots_s, kcount, k, d.N);
-        bool flip;
-        rot_params(dt * (1.0 - sk), rt, rs, flip);
-        if (k == d.k0) {
-            phi = 0.5 * dt * sk;
-            gph = 0.0;
-        } else {
-            const double sp = sched_mid(knots_s, kcount, k - 1, d.N);
-            const double thp = dt * (1.0 - sp);
-            double tp, sq;
-            bool fp;
-            rot_params(thp, tp, sq, fp);
-            phi = 0.5 * dt * (sp + sk);
-            gph = step_gphase(n, thp, fp);
-        }
+        res_step_terms(knots_s, kcount, k, d.k0, d.N, dt, n, phi, gph, rt, rs);
     };
-    // rows [0, rows) of the chunk's phase table from phi_s / gph_s; row 0
-    // carries the norm correction
     auto build_rows = [&](int rows, double scale0) {
-        for (int x = (int)tid; x < rows * width; x += (int)blockDim.x) {
-            const int j = x / width, e = x - j * width;
-            double sn, cs;
-            sincos(fma(phi_s[j], (double)e, gph_s[j]), &sn, &cs);
-            const double sc = j == 0 ? scale0 : 1.0;
-            F2 L;
-            L.x = (F)(sc * cs);
-            L.y = (F)(-sc * sn);
-            ring[x] = L;
-        }
+        res_build_rows<F2, F>(ring, phi_s, gph_s, rows, width, scale0, (int)tid, (int)blockDim.x);
     };
     // Few registers per thread (a single state of up to 2^11 amplitudes: 4
     // per thread, at most 512 threads): every group's LDS offsets and the
@@ -447,6 +462,218 @@ template <typename F, typename ET, int RB, int WB>
 __global__ void __launch_bounds__(1 << WB) resident_batch_kernel(const ResidentDesc *__restrict__ descs)
 {
     resident_body<F, ET, RB, WB, kResRingBatch>(descs[blockIdx.x]);
+}
+
+// ---------------------------------------------------------------------------
+// One complex64 state of n = RB + 6 + WV qubits (n = 8..11) held in
+// registers: 2^RB amplitudes per thread, 64 << WV threads.  Layout A puts
+// qubits 0..RB-1 in the register index, qubits RB..RB+5 in the lane index
+// and the top WV qubits in the wave index; layout B swaps the lowest WV
+// register bits with the wave bits.  A step applies its phase row and then
+// rotates every qubit: those in register bits inside the thread, those in
+// lane bits with the partner lane's value (cross-lane shuffles; each lane
+// keeps its own half of the pair, with the same three-shear arithmetic as
+// rotate_bit), and the wave qubits after one exchange through LDS into the
+// other layout.  Steps alternate the layout they start in, so a step costs
+// one exchange (none at n = 8) and one barrier, instead of an LDS
+// residency with a barrier per pair of qubits.  Coefficients, phase rows
+// and the once-per-chunk renormalisation are as in resident_body.
+// ---------------------------------------------------------------------------
+// The value of lane l ^ (1 << B) of the wave.  Within a row of 16 lanes the
+// exchange is a DPP move (no trip through the LDS crossbar): quad_perm
+// [1,0,3,2] and [2,3,0,1] swap lanes 1 and 2 apart; a half-row mirror
+// (l ^ 7 within 8) after a quad reversal (l ^ 3) is l ^ 4; a row mirror
+// (l ^ 15 within 16) after a half-row mirror is l ^ 8.  Lanes 16 and 32
+// apart go through ds_bpermute.
+template <int B>
+__device__ __forceinline__ float lane_xor(float x)
+{
+    const int v = __float_as_int(x);
+    if constexpr (B == 0) {
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true));
+    } else if constexpr (B == 1) {
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true));
+    } else if constexpr (B == 2) {
+        const int t = __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true);
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, t, 0x1B, 0xF, 0xF, true));
+    } else if constexpr (B == 3) {
+        const int t = __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, true);
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, t, 0x141, 0xF, 0xF, true));
+    } else {
+        return __shfl_xor(x, 1 << B, 64);
+    }
+}
+
+template <int B, int RB, typename F>
+__device__ __forceinline__ void rotate_lane_bit(float2 (&v)[1 << RB], const Rot<F> &k)
+{
+#pragma unroll
+    for (int j = 0; j < (1 << RB); ++j) {
+        const float px = lane_xor<B>(v[j].x);
+        const float py = lane_xor<B>(v[j].y);
+        // (Re mine, Im partner) and (Re partner, Im mine) are the two
+        // sheared planes; this lane keeps Re mine and Im mine
+        const float a = fma(-k.t, py, v[j].x);
+        const float w = fma(k.s, a, py);
+        const float c = fma(-k.t, v[j].y, px);
+        v[j].x = fma(-k.t, w, a);
+        v[j].y = fma(k.s, c, v[j].y);
+    }
+}
+
+template <int RB, typename F>
+__device__ __forceinline__ void rotate_lanes(float2 (&v)[1 << RB], const Rot<F> &k)
+{
+    rotate_lane_bit<0, RB>(v, k);
+    rotate_lane_bit<1, RB>(v, k);
+    rotate_lane_bit<2, RB>(v, k);
+    rotate_lane_bit<3, RB>(v, k);
+    rotate_lane_bit<4, RB>(v, k);
+    rotate_lane_bit<5, RB>(v, k);
+}
+
+template <typename ET, int RB, int WV>
+__global__ void __launch_bounds__(64 << WV) resident_lane_kernel(const ResidentDesc d)
+{
+    using F = float;
+    using F2 = float2;
+    constexpr int R = 1 << RB;
+    constexpr uint32_t NT = 64u << WV;
+    constexpr uint32_t DIM = (uint32_t)R * NT;
+    constexpr uint32_t LO = (1u << WV) - 1u;
+    static_assert(WV <= RB, "the wave bits swap with register bits");
+    extern __shared__ __align__(16) unsigned char smem[];
+    F2 *xbuf = reinterpret_cast<F2 *>(smem);             // two exchange buffers of DIM entries
+    F2 *ring = xbuf + 2 * DIM;                           // phase rows
+    ET *etile = reinterpret_cast<ET *>(ring + kResRingOne);   // recompute mode: energies
+
+    F2 *__restrict__ amp = reinterpret_cast<F2 *>(d.amp);
+    const ET *__restrict__ table = reinterpret_cast<const ET *>(d.table);
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    auto zA = [&](uint32_t j) { return j | (lane << RB) | (wave << (RB + 6)); };
+    auto zB = [&](uint32_t j) { return wave | (j & ~LO) | (lane << RB) | ((j & LO) << (RB + 6)); };
+
+    __shared__ double knots_s[kMaxKnots];
+    const int kcount = d.sched.count;
+    for (int x = (int)tid; x < kcount; x += (int)NT) knots_s[x] = d.sched.v[x];
+    if (!table) {
+        // recompute mode: score the state's energies once, 32 z per thread
+        constexpr int K = sizeof(ET) == 1 ? 8 : 16;
+        for (uint32_t b = tid; b < DIM / 32u; b += NT) {
+            BitCounter<K> bc;
+            bc.clear();
+            score_clauses<K>(bc, d.clauses, d.m, b);
+            for (uint32_t i = 0; i < 32u; ++i) etile[32u * b + i] = (ET)count_of<K>(bc, i);
+        }
+        __syncthreads();
+    }
+    F2 v[R];
+    uint32_t eA[R], eB[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        v[j] = amp[zA(j)];
+        eA[j] = table ? (uint32_t)table[zA(j)] : (uint32_t)etile[zA(j)];
+        eB[j] = table ? (uint32_t)table[zB(j)] : (uint32_t)etile[zB(j)];
+    }
+
+    const double dt = d.T / (double)d.N;
+    const int width = d.emax + 1;
+    const int chunk = min(kResChunk, kResRingOne / width);
+    __shared__ double red[NT / 64];
+    __shared__ double phi_s[kResChunk], gph_s[kResChunk];
+    __shared__ Rot<F> rot_s[kResChunk];
+    bool inA = true;          // layout the state is in
+    int buf = 0;              // exchange buffer written next
+    auto phase = [&](const F2 *lut) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) v[j] = cmul<F2, F>(v[j], lut[inA ? eA[j] : eB[j]]);
+    };
+    auto rotA = [&](const Rot<F> &k) {
+        rotate_mask<RB>(v, (1u << RB) - 1u, k);
+        rotate_lanes<RB>(v, k);
+    };
+    auto rotB = [&](const Rot<F> &k) {
+#pragma unroll
+        for (int b = 0; b < WV; ++b) rotate_bit<RB>(v, b, k);
+    };
+    // to the other layout through LDS; two buffers in turn, so one barrier
+    // per exchange (a buffer is rewritten only after every thread has
+    // passed the next exchange's barrier, i.e. finished reading it)
+    auto exchange = [&]() {
+        F2 *x = xbuf + buf * DIM;
+#pragma unroll
+        for (int j = 0; j < R; ++j) x[swz<F>(inA ? zA(j) : zB(j))] = v[j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < R; ++j) v[j] = x[swz<F>(inA ? zB(j) : zA(j))];
+        inA = !inA;
+        buf ^= 1;
+    };
+    auto step = [&](const F2 *lut, const Rot<F> &k) {
+        phase(lut);
+        if constexpr (WV == 0) {
+            rotA(k);
+        } else if (inA) {
+            rotA(k);
+            exchange();
+            rotB(k);
+        } else {
+            rotB(k);
+            exchange();
+            rotA(k);
+        }
+    };
+    auto measure = [&]() {
+        F ss = F(0);
+#pragma unroll
+        for (int j = 0; j < R; ++j) ss = fma(v[j].x, v[j].x, fma(v[j].y, v[j].y, ss));
+        double t = (double)ss;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+        if (lane == 0) red[wave] = t;
+        __syncthreads();
+        double total = 0.0;
+#pragma unroll
+        for (int w = 0; w < (int)(NT / 64); ++w) total += red[w];
+        return total;
+    };
+
+    double scale = 1.0;
+    for (int64_t kc = d.k0; kc < d.k1; kc += chunk) {
+        const int cs = (int)min<int64_t>((int64_t)chunk, d.k1 - kc);
+        __syncthreads();         // knots loaded / the previous chunk's rows and norm read
+        if ((int)tid < cs) {
+            double phi, gph, rt, rs;
+            res_step_terms(knots_s, kcount, kc + (int)tid, d.k0, d.N, dt, d.n, phi, gph, rt, rs);
+            phi_s[tid] = phi;
+            gph_s[tid] = gph;
+            rot_s[tid] = make_rot<F>(rt, rs);
+        }
+        __syncthreads();
+        res_build_rows<F2, F>(ring, phi_s, gph_s, cs, width, scale, (int)tid, (int)NT);
+        __syncthreads();
+        for (int j = 0; j < cs; ++j) step(ring + j * width, rot_s[j]);
+        scale = rsqrt(measure());
+    }
+    if (d.k1 > d.k0) {
+        // closing half phase of the last step, with its driver global phase
+        __syncthreads();
+        if (tid == 0) {
+            const double sl = sched_mid(knots_s, kcount, d.k1 - 1, d.N);
+            const double thl = dt * (1.0 - sl);
+            double tl, sl2;
+            bool fl;
+            rot_params(thl, tl, sl2, fl);
+            phi_s[0] = 0.5 * dt * sl;
+            gph_s[0] = step_gphase(d.n, thl, fl);
+        }
+        __syncthreads();
+        res_build_rows<F2, F>(ring, phi_s, gph_s, 1, width, scale, (int)tid, (int)NT);
+        __syncthreads();
+        phase(ring);
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) amp[inA ? zA(j) : zB(j)] = v[j];
 }
 
 // ---------------------------------------------------------------------------
@@ -593,10 +820,46 @@ hipError_t launch_resident_t(const ResidentDesc *descs_dev, const ResidentDesc *
 
 }  // namespace
 
+bool resident_lanes_enabled()
+{
+    static const bool on = [] {
+        const char *e = std::getenv("QAA_RESIDENT_LANES");
+        return !(e && std::atoi(e) == 0);
+    }();
+    return on;
+}
+
+template <typename ET, int RB, int WV>
+hipError_t launch_resident_lane_t(const ResidentDesc &one, hipStream_t s)
+{
+    constexpr size_t DIM = size_t(1) << (RB + 6 + WV);
+    const size_t lds = sizeof(float2) * (2 * DIM + kResRingOne) + sizeof(ET) * DIM;
+    const void *fn = reinterpret_cast<const void *>(&resident_lane_kernel<ET, RB, WV>);
+    static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL((resident_lane_kernel<ET, RB, WV>), dim3(1), dim3(64u << WV), lds, s, one);
+    return hipGetLastError();
+}
+
+template <typename ET>
+hipError_t launch_resident_lane(const ResidentDesc &one, hipStream_t s)
+{
+    switch (one.n) {
+    case 8: return launch_resident_lane_t<ET, 2, 0>(one, s);
+    case 9: return launch_resident_lane_t<ET, 2, 1>(one, s);
+    case 10: return launch_resident_lane_t<ET, 2, 2>(one, s);
+    case 11: return launch_resident_lane_t<ET, 3, 2>(one, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 // Single-state shapes (see resident_shape): 2^(rb + wb) amplitudes.
 template <typename F, typename ET>
 hipError_t launch_resident_one(const ResidentDesc *one, int rb, int wb, hipStream_t s)
 {
+    if constexpr (sizeof(F) == 4)
+        if (resident_lanes_enabled() && one->n >= kResLaneMinN && one->n <= kResLaneMaxN)
+            return launch_resident_lane<ET>(*one, s);
     if (rb == 2 && wb == 8) return launch_resident_t<F, ET, 2, 8, true>(nullptr, one, 1, s);
     if (rb == 2 && wb == 9) return launch_resident_t<F, ET, 2, 9, true>(nullptr, one, 1, s);
     if (rb == 2 && wb == 10) return launch_resident_t<F, ET, 2, 10, true>(nullptr, one, 1, s);

@@ -151,6 +151,38 @@ def test_evolve_n10_T10_1000_steps(qaa, seed):
     _compare(st, obs, psi, ref, L2_TOL_C64, P_TOL_C64)
 
 
+@pytest.mark.parametrize("n,T,N,etype", [(8, 5.0, 77, 0), (9, 6.0, 65, 0), (9, 6.0, 65, 1), (10, 4.0, 33, 0),
+                                         (11, 7.0, 101, 0), (11, 7.0, 101, 1)])
+def test_register_resident_sizes_vs_oracle(qaa, n, T, N, etype):
+    """n = 8..11 (one state in registers, lane qubits rotated across lanes,
+    the wave qubits after an exchange that alternates the layout): odd step
+    counts past one 32-step chunk, so runs end in either layout."""
+    inst_in = planted_unique_3sat(n, 120 + n)
+    _, _, st, obs = _run_gpu(qaa, n, inst_in.clauses, T, N, etype=etype)
+    psi, ref = _oracle_run(n, inst_in.clauses, T, N)
+    _compare(st, obs, psi, ref, L2_TOL_C64, P_TOL_C64)
+
+
+@pytest.mark.parametrize("n", [9, 10, 11])
+def test_register_resident_ranges_compose(qaa, n):
+    """Ranges that stop after an odd number of steps (the state is stored
+    from the other layout) and resume: equal to the uninterrupted run to
+    rounding, and to the oracle."""
+    T, N, K = 6.0, 90, 37
+    inst_in = planted_unique_3sat(n, 130 + n)
+    inst = qaa.Instance(n, inst_in.literals())
+    table = inst.energy_table()
+    a = qaa.State(inst, table).init_uniform().evolve(T, N)
+    b = qaa.State(inst, table).init_uniform()
+    b.evolve_range(T, N, 0, K)
+    b.evolve_range(T, N, K, N)
+    torch.cuda.synchronize()
+    diff = float(torch.linalg.vector_norm((a.amp - b.amp).to(torch.complex128)).item())
+    assert diff < 1e-5
+    psi, ref = _oracle_run(n, inst_in.clauses, T, N)
+    _compare(b, b.observables(), psi, ref, L2_TOL_C64, P_TOL_C64)
+
+
 @pytest.mark.parametrize("n,T,N", [(5, 3.0, 40), (13, 5.0, 60), (14, 5.0, 60), (15, 8.0, 80), (17, 5.0, 50),
                                    (21, 5.0, 30), (22, 5.0, 12), (23, 4.0, 8)])
 def test_evolve_multipass_parity(qaa, n, T, N):
