@@ -482,9 +482,9 @@ __global__ void __launch_bounds__(1 << WB) resident_batch_kernel(const ResidentD
 // The value of lane l ^ (1 << B) of the wave.  Within a row of 16 lanes the
 // exchange is a DPP move (no trip through the LDS crossbar): quad_perm
 // [1,0,3,2] and [2,3,0,1] swap lanes 1 and 2 apart; a half-row mirror
-// (l ^ 7 within 8) after a quad reversal (l ^ 3) is l ^ 4; a row mirror
-// (l ^ 15 within 16) after a half-row mirror is l ^ 8.  Lanes 16 and 32
-// apart go through ds_bpermute.
+// (l ^ 7 within 8) followed by a quad reversal (l ^ 3) gives l ^ 4; a row
+// mirror (l ^ 15 within 16) followed by a half-row mirror gives l ^ 8.
+// Lanes 16 and 32 apart go through ds_bpermute.
 template <int B>
 __device__ __forceinline__ float lane_xor(float x)
 {
