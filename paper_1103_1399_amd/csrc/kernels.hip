@@ -465,7 +465,7 @@ __global__ void __launch_bounds__(1 << WB) resident_batch_kernel(const ResidentD
 }
 
 // ---------------------------------------------------------------------------
-// One complex64 state of n = RB + 6 + WV qubits (n = 8..11) held in
+// One complex64 state of n = RB + 6 + WV qubits (n = 8..12) held in
 // registers: 2^RB amplitudes per thread, 64 << WV threads.  Layout A puts
 // qubits 0..RB-1 in the register index, qubits RB..RB+5 in the lane index
 // and the top WV qubits in the wave index; layout B swaps the lowest WV
@@ -820,7 +820,13 @@ hipError_t launch_resident_t(const ResidentDesc *descs_dev, const ResidentDesc *
 
 }  // namespace
 
-bool resident_lanes_enabled()
+// A single complex64 state of n = 8..12 runs resident_lane_kernel instead
+// of the LDS-resident kernel (QAA_RESIDENT_LANES=0 turns it off; results
+// differ by rounding only).
+constexpr int kResLaneMinN = 8;
+constexpr int kResLaneMaxN = 12;
+
+static bool resident_lanes_enabled()
 {
     static const bool on = [] {
         const char *e = std::getenv("QAA_RESIDENT_LANES");
@@ -849,6 +855,7 @@ hipError_t launch_resident_lane(const ResidentDesc &one, hipStream_t s)
     case 9: return launch_resident_lane_t<ET, 2, 1>(one, s);
     case 10: return launch_resident_lane_t<ET, 2, 2>(one, s);
     case 11: return launch_resident_lane_t<ET, 3, 2>(one, s);
+    case 12: return launch_resident_lane_t<ET, 3, 3>(one, s);
     default: return hipErrorInvalidValue;
     }
 }

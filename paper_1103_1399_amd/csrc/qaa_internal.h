@@ -239,12 +239,6 @@ inline void resident_shape(int n, int *rb, int *wb)
     *wb = n <= 10 ? 8 : (n == 11 ? 9 : 10);
     *rb = n <= 12 ? 2 : 3;
 }
-// A single complex64 state of n = 8..11 runs the register-resident kernel
-// with cross-lane rotations instead (QAA_RESIDENT_LANES=0 turns it off;
-// results differ from the LDS-resident kernel's by rounding only).
-constexpr int kResLaneMinN = 8;
-constexpr int kResLaneMaxN = 11;
-bool resident_lanes_enabled();
 // Pass tile shapes: complex64 2^13 (5 register bits), complex128 2^12 (4).
 constexpr int kPassTileBits[2] = {13, 12};
 // Wide tile (complex64 with a uint8 table only): 2^14 amplitudes, 512

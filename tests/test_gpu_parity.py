@@ -152,9 +152,9 @@ def test_evolve_n10_T10_1000_steps(qaa, seed):
 
 
 @pytest.mark.parametrize("n,T,N,etype", [(8, 5.0, 77, 0), (9, 6.0, 65, 0), (9, 6.0, 65, 1), (10, 4.0, 33, 0),
-                                         (11, 7.0, 101, 0), (11, 7.0, 101, 1)])
+                                         (11, 7.0, 101, 0), (11, 7.0, 101, 1), (12, 5.0, 45, 0), (12, 5.0, 45, 1)])
 def test_register_resident_sizes_vs_oracle(qaa, n, T, N, etype):
-    """n = 8..11 (one state in registers, lane qubits rotated across lanes,
+    """n = 8..12 (one state in registers, lane qubits rotated across lanes,
     the wave qubits after an exchange that alternates the layout): odd step
     counts past one 32-step chunk, so runs end in either layout."""
     inst_in = planted_unique_3sat(n, 120 + n)
@@ -163,7 +163,7 @@ def test_register_resident_sizes_vs_oracle(qaa, n, T, N, etype):
     _compare(st, obs, psi, ref, L2_TOL_C64, P_TOL_C64)
 
 
-@pytest.mark.parametrize("n", [9, 10, 11])
+@pytest.mark.parametrize("n", [9, 10, 11, 12])
 def test_register_resident_ranges_compose(qaa, n):
     """Ranges that stop after an odd number of steps (the state is stored
     from the other layout) and resume: equal to the uninterrupted run to
