@@ -59,7 +59,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
 PASS_KERNEL_SOURCES = ("paper_1103_1399_amd/csrc/pass_kernels.hip", "paper_1103_1399_amd/csrc/kernel_common.h",
                        "paper_1103_1399_amd/csrc/qaa_internal.h", "paper_1103_1399_amd/csrc/qaa_api.hip")
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "7c4b2ce69a219e4ad652f46fd08f37fcb8f3b52b72ee0e74b678271e19ea39ba",
+    "kernel_source_sha256": "696be0a06968bab0d67316cc81b1c1b8550d8df7bc5b9bc9e3e29e929229e9a2",
     "bytes_per_launch": 4.4343e+09,
 }
 
