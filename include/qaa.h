@@ -274,11 +274,13 @@ qaa_status qaa_evolve_range_noalloc(const qaa_state *st, const qaa_schedule *sch
  * so for work already queued on the stream); the evolution itself is
  * asynchronous on the stream.  Internally the small states, and the launch
  * groups after the first (states sharing a number of qubit sets and tile
- * sizes), run on library-owned streams of the device, forked from `stream`
- * and joined back into it: work queued on `stream` after the call waits
- * for all of them.  QAA_BATCH_STREAMS (0..2, default 1) sets how many
- * streams the launch groups after the first spread over; 0 keeps every
- * group on `stream` (results are the same either way).
+ * sizes, the heaviest split in two until each stream has a group), run on
+ * library-owned streams of the device, forked from `stream` and joined
+ * back into it: work queued on `stream` after the call waits for all of
+ * them.  QAA_BATCH_STREAMS (0..3, default 2) sets how many streams the
+ * launch groups after the first spread over; 0 keeps every group on
+ * `stream`; QAA_BATCH_SPLIT=0 keeps one group per plan shape (results are
+ * the same either way).
  */
 qaa_status qaa_evolve_batch(int32_t count, const qaa_state *states, const qaa_schedule *scheds,
                             const double *T, const int64_t *steps, void *stream);

@@ -1513,14 +1513,27 @@ int batch_chunk_tiles()
     return v;
 }
 
-// Extra streams for a batch's launch groups: QAA_BATCH_STREAMS (0..2, read
-// once), else 1.  0 runs every group on the caller's stream.
+// Extra streams for a batch's launch groups: QAA_BATCH_STREAMS (0..3, read
+// once), else 2.  0 runs every group on the caller's stream.  (With the
+// caller's stream and the side stream, 2 extra streams fill the four
+// hardware queues a process gets by default.)
 int batch_group_streams()
 {
     static const int v = [] {
         const char *e = std::getenv("QAA_BATCH_STREAMS");
-        const int x = e ? std::atoi(e) : 1;
-        return x >= 0 && x <= 2 ? x : 1;
+        const int x = e ? std::atoi(e) : 2;
+        return x >= 0 && x <= 3 ? x : 2;
+    }();
+    return v;
+}
+
+// Split the heaviest launch groups in two until every stream has one
+// (QAA_BATCH_SPLIT=0, read once: one launch group per plan shape).
+bool batch_split()
+{
+    static const bool v = [] {
+        const char *e = std::getenv("QAA_BATCH_SPLIT");
+        return !(e && std::atoi(e) == 0);
     }();
     return v;
 }
@@ -1565,6 +1578,46 @@ qaa_status run_batch_passes(const std::vector<int> &idx, const qaa_state *states
         g.r = (int)p.sets.size();
         g.tbs.assign(key.begin() + 2, key.end());
         g.order.push_back(i);
+    }
+    // Splitting: while there are fewer launch groups than streams, the
+    // group with the most amplitude-steps is split in two, its states
+    // (longest first) dealt alternately, so each part runs on its own stream.
+    if (batch_split()) {
+        const size_t want = 1 + (size_t)batch_group_streams();
+        auto work = [&](const GroupPlan &g) {
+            double w = 0.0;
+            for (int i : g.order) w += std::ldexp((double)steps[i], states[i].inst->n);
+            return w;
+        };
+        std::map<std::vector<int>, GroupPlan> parts;
+        for (auto &kv : groups) {
+            std::vector<int> key = kv.first;
+            key.push_back(0);
+            parts[key] = kv.second;
+        }
+        int next_id = 1;
+        while (parts.size() < want) {
+            auto best = parts.end();
+            for (auto it = parts.begin(); it != parts.end(); ++it)
+                if (it->second.order.size() >= 2 && (best == parts.end() || work(it->second) > work(best->second)))
+                    best = it;
+            if (best == parts.end()) break;
+            GroupPlan g = best->second;
+            std::vector<int> key = best->first;
+            parts.erase(best);
+            std::stable_sort(g.order.begin(), g.order.end(), [&](int a, int b) { return steps[a] > steps[b]; });
+            GroupPlan h[2];
+            for (int q = 0; q < 2; ++q) {
+                h[q].rb = g.rb;
+                h[q].r = g.r;
+                h[q].tbs = g.tbs;
+            }
+            for (size_t q = 0; q < g.order.size(); ++q) h[q & 1].order.push_back(g.order[q]);
+            parts[key] = h[0];
+            key.back() = next_id++;
+            parts[key] = h[1];
+        }
+        groups.swap(parts);
     }
     std::vector<PassDesc> structs;
     std::map<int, int> base_of_n;
