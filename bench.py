@@ -59,7 +59,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
 PASS_KERNEL_SOURCES = ("paper_1103_1399_amd/csrc/pass_kernels.hip", "paper_1103_1399_amd/csrc/kernel_common.h",
                        "paper_1103_1399_amd/csrc/qaa_internal.h", "paper_1103_1399_amd/csrc/qaa_api.hip")
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "696be0a06968bab0d67316cc81b1c1b8550d8df7bc5b9bc9e3e29e929229e9a2",
+    "kernel_source_sha256": "81d5340307927aa18a92062671b2ba3a10ff7c97386d95326dfdce0d42849321",
     "bytes_per_launch": 4.4343e+09,
 }
 
